@@ -1,0 +1,70 @@
+"""Tier B: the cross-covariance (HiKF) filter in FP64 -- test infrastructure.
+
+Follows Algorithm ``Algorithm_HiKF`` and Sec. 3.1 with an exact or given
+C_Q = Q H^T:
+
+  predict   s_{t+1|t} = s_{t|t};  C_{t+1|t} = C_{t|t} + C_Q  (eq. eqn_KF_forecast_new)
+            var_{t+1|t} = var_{t|t} + diag Q                   (reading: the
+            algorithm prints no variance prediction; diag Q = K(0))
+  gain      K = C_{t+1|t} (H C_{t+1|t} + R)^{-1}               (eq. eqn_kalmangin_new)
+  state     s_{t+1|t+1} = s_{t+1|t} + K (y_{t+1} - H s_{t+1|t})
+  cross-cov C_{t+1|t+1} = C_{t+1|t} - K (H C_{t+1|t})          (eq. eqn_KF_pred_new)
+  variance  var_i -= sum_j K_ij (C_{t+1|t})_ij                  (Sec. 3.1)
+
+Readings: H C is symmetric only in exact arithmetic, so the innovation
+covariance is taken as S = (G + G^T)/2 + R with G = H C_{t+1|t}; S^{-1} is
+applied by Cholesky solves.  Rows are independent given G, so the filter may
+be run on any row subset that contains every cell a ray crosses (the
+columns where H is nonzero); the other rows are then exact samples.
+"""
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+
+def _as_operator(H):
+    return H.tocsr() if sp.issparse(H) else np.asarray(H, np.float64)
+
+
+def crosscov_kf(CQ, H, R, x0, C0, var0, qdiag, ys, return_C=False):
+    """Run tier B over the rows of ``ys``.
+
+    CQ (m,p) = Q H^T; H (p,m) dense or scipy-sparse; R (p,p); x0 (m,);
+    C0 (m,p) = P0 H^T; var0 (m,) = diag P0; qdiag = K(0) (scalar or (m,)).
+    Returns (xs, variances) of shape (steps, m) [and the final C].
+    """
+    H = _as_operator(H)
+    R = np.asarray(R, np.float64)
+    C = np.array(C0, np.float64, copy=True)
+    x = np.array(x0, np.float64, copy=True)
+    var = np.array(var0, np.float64, copy=True)
+    xs, vs = [], []
+    for y in np.atleast_2d(ys):
+        C = C + CQ                                   # predict
+        var = var + qdiag
+        G = H @ C                                    # H C_{t+1|t}, (p,p)
+        S = 0.5 * (G + G.T) + R
+        cf = sla.cho_factor(S, lower=True)
+        K = sla.cho_solve(cf, C.T).T                 # C S^{-1}
+        x = x + K @ (y - H @ x)
+        var = var - np.einsum("ij,ij->i", K, C)
+        C = C - K @ G
+        xs.append(x.copy())
+        vs.append(var.copy())
+    if return_C:
+        return np.array(xs), np.array(vs), C
+    return np.array(xs), np.array(vs)
+
+
+def crosscov_gain_identity(C_prior, G, R):
+    """Both forms of the posterior cross-covariance for one step.
+
+    Returns (C - K G, K R) with K = C S^{-1}, S = (G+G^T)/2 + R.  They agree
+    because S - R = G (for symmetric G), so C - C S^{-1} G = C S^{-1} R; the
+    second form (P_post H^T = K R) is the one that avoids cancellation.
+    """
+    S = 0.5 * (G + G.T) + R
+    cf = sla.cho_factor(S, lower=True)
+    K = sla.cho_solve(cf, C_prior.T).T
+    return C_prior - K @ G, K @ R

@@ -1,0 +1,93 @@
+"""Pins for the FP64 black-box FMM oracle (Sec. 3.2).
+
+* Chebyshev interpolation with n_c >= 3 nodes per axis reproduces a kernel
+  of degree 2 in every coordinate exactly, so every pass and list must give
+  the dense product to rounding (catches a wrong operator, sign, index or
+  list).
+* The approximate Q is symmetric (M2L for offset -o is the transpose of
+  offset o, L2L the transpose of M2M), so u^T (Q v) = v^T (Q u).
+* The error against the exact product falls geometrically with n_c (the
+  trend of Table ``table_bbfmm``; its values are parity unpinned).
+* The near and interaction-list pair totals equal closed-form counts.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import bbfmm, cq_exact
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("dim,n,leaf,nc", [(2, 32, 8, 3), (2, 64, 8, 4),
+                                           (2, 64, 8, 5), (3, 16, 4, 3),
+                                           (3, 16, 4, 4)])
+def test_polynomial_kernel_is_exact(dim, n, leaf, nc):
+    rng = np.random.default_rng(7)
+    W = rng.standard_normal((n ** dim, 3))
+    pts = synth.cell_centres(dim, n)
+    exact = cq_exact.cq_dense(pts, W, "r2", 1.0)
+    approx = bbfmm.bbfmm_apply(dim, n, W, nc, leaf, "r2", 1.0)
+    assert _rel(approx, exact) < 1e-13
+
+
+def test_symmetry():
+    rng = np.random.default_rng(2)
+    n = 64
+    u = rng.standard_normal((n * n, 1))
+    v = rng.standard_normal((n * n, 1))
+    Qu = bbfmm.bbfmm_apply(2, n, u, 4, 8, "powexp", 1.0, 0.1, 1.0)
+    Qv = bbfmm.bbfmm_apply(2, n, v, 4, 8, "powexp", 1.0, 0.1, 1.0)
+    a, b = float((u.T @ Qv)[0, 0]), float((v.T @ Qu)[0, 0])
+    assert abs(a - b) < 1e-13 * (abs(a) + abs(b) + np.abs(u).sum() * np.abs(Qv).max())
+
+
+def test_linearity():
+    rng = np.random.default_rng(4)
+    n = 32
+    W = rng.standard_normal((n * n, 2))
+    F = bbfmm.bbfmm_apply(2, n, W, 4, 8, "powexp", 1.0, 0.2, 1.0)
+    G = bbfmm.bbfmm_apply(2, n, W @ np.array([[2.0], [-3.0]]), 4, 8, "powexp", 1.0, 0.2, 1.0)
+    assert _rel(G, F @ np.array([[2.0], [-3.0]])) < 1e-13
+
+
+@pytest.mark.parametrize("n,ell,gamma", [(256, 0.05, 2.0), (64, 0.3, 1.0)])
+def test_geometric_convergence(n, ell, gamma):
+    rng = np.random.default_rng(5)
+    W = rng.standard_normal((n * n, 2))
+    exact = cq_exact.cq_fft(2, n, W, "powexp", 1.0, ell, gamma)
+    errs = [_rel(bbfmm.bbfmm_apply(2, n, W, nc, 8, "powexp", 1.0, ell, gamma), exact)
+            for nc in (3, 4, 5, 6, 7)]
+    for a, b in zip(errs, errs[1:]):
+        assert b < a * 0.6
+    # Table "table_bbfmm" reports ~1e-9 at 5 nodes and ~3e-11 at 7 nodes for
+    # a Gaussian kernel on an unstated workload; here only the geometric
+    # decay is checked.
+    assert errs[-1] < 1e-5
+
+
+@pytest.mark.parametrize("dim,n,leaf", [(2, 256, 8), (2, 1024, 8), (3, 128, 4), (2, 32, 8)])
+def test_pair_counts_closed_form(dim, n, leaf):
+    near, far = bbfmm.interaction_counts(dim, n, leaf)
+    nl = n // leaf
+    assert near == (nl + 2 * (nl - 1)) ** dim
+    D = int(np.log2(nl))
+    # per axis and level: pairs whose parents are within one box, minus
+    # pairs that are themselves within one box
+    closed = sum((6 * 2 ** l - 8) ** dim - (3 * 2 ** l - 2) ** dim
+                 for l in range(2, D + 1))
+    assert far == closed
+
+
+def test_interior_list_sizes():
+    # an interior box has 27 (2-D) / 189 (3-D) interaction-list entries
+    for dim in (2, 3):
+        counts = 0
+        for o in bbfmm.il_offsets(dim):
+            if all(len(bbfmm._il_axis_targets(16, v)) and
+                   (5 in bbfmm._il_axis_targets(16, v)) for v in o):
+                counts += 1
+        assert counts == (27 if dim == 2 else 189)
