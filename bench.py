@@ -1,0 +1,255 @@
+#!/usr/bin/env python3
+"""HiKF hot-path benchmark on one MI355X.
+
+One benchmark step is one whole assimilation job of the chosen workload:
+hikf_init (W = H^T, the H^2 / FMM product C_Q = Q H^T, the initial state)
+followed by the workload's assimilation steps (gather, p-space Cholesky and
+inverse, fused row pass), all through the C ABI on one HIP stream.  Inputs
+(H, R, the y stream) are resident in HBM before the timed region starts.
+
+Prints one JSON line: whole-job assimilation steps/s, per-step latency
+percentiles, the row-pass kernel against the FP64 MFMA roofline (kernel time
+from HIP events the library records on the launch stream), the FMM passes
+against their roofs, and the FP64 CPU oracle timed on a bounded sample of the
+same workload.
+"""
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed jobs")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed jobs")
+    ap.add_argument("--workload", default="crosswell-1024x1024-p256")
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--n-c", type=int, default=None)
+    ap.add_argument("--assim-steps", type=int, default=None,
+                    help="assimilation steps per job (default: the workload's)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0,
+                    help="approximate seconds of CPU work for the oracle sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, assim_steps, budget):
+    """The FP64 oracle on a bounded sample of the workload, scaled to the
+    whole job: exact C_Q by FFT (oracle tier C) on a few right-hand sides and
+    cross-covariance steps (tier B) on a subset of rows."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import cq_exact, kf_crosscov
+    import synth
+
+    dim, n, p, m = w["dim"], w["n"], w["p"], w["m"]
+    rowptr, col, val = synth.crosswell_h(dim, n, p, planes=8)
+    # exact C_Q = Q H^T by FFT on the first `cols` rays
+    cols = 2
+    t_fft = 0.0
+    while True:
+        Ht = np.zeros((m, cols))
+        for a in range(cols):
+            Ht[col[rowptr[a]:rowptr[a + 1]], a] = val[rowptr[a]:rowptr[a + 1]]
+        t0 = time.perf_counter()
+        cq_exact.cq_fft(dim, n, Ht, "powexp", w["theta"], w["ell"], w["gamma"])
+        t_fft = time.perf_counter() - t0
+        if t_fft > budget / 3 or cols >= p:
+            break
+        cols = min(p, cols * 4)
+    t_cq_full = t_fft * p / cols
+    # tier-B steps on a row subset (cost is linear in the number of rows)
+    rows = min(m, 16384)
+    rng = np.random.default_rng(0)
+    steps = 1
+    while True:
+        CQ = rng.standard_normal((rows, p)) * 1e-2
+        Hs = np.zeros((p, rows))
+        for a in range(p):
+            Hs[a, rng.choice(rows, 8, replace=False)] = 1.0 / n
+        ys = rng.standard_normal((steps, p)) * 1e-2
+        t0 = time.perf_counter()
+        kf_crosscov.crosscov_kf(CQ, Hs, w["r_var"] * np.eye(p), np.zeros(rows), CQ,
+                                np.ones(rows), 1.0, ys)
+        t_b = time.perf_counter() - t0
+        if t_b > budget / 3 or rows >= m:
+            break
+        grow = min(4, max(2, int(budget / 3 / max(t_b, 1e-3))))
+        if rows * grow <= m and rows * grow <= 262144:
+            rows *= grow
+        else:
+            steps *= 2
+    t_step_full = t_b / steps * m / rows
+    job = t_cq_full + assim_steps * t_step_full
+    threads = max((d.get("num_threads", 1) for d in threadpool_info()), default=1)
+    return {
+        "value": assim_steps / job, "unit": "assim steps/s", "cores": int(threads),
+        "kind": "oracle",
+        "sample": (f"exact C_Q by FFT on {cols} of {p} rays ({t_fft:.1f} s, scaled x{p / cols:g}); "
+                   f"{steps} cross-covariance step(s) on {rows} of {m} rows ({t_b:.1f} s, scaled "
+                   f"x{m / rows:g}); job = C_Q + {assim_steps} steps = {job:.0f} s"),
+    }
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: the hot path here is built and timed on a "
+              "single MI355X; the multi-GPU sharding is a design note, not code.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import synth
+    from paper_1404_3816_amd import filter as F
+    from paper_1404_3816_amd import hikf as H
+
+    w = synth.workload(a.workload)
+    dim, n, p, m = w["dim"], w["n"], w["p"], w["m"]
+    n_c = a.n_c or w["n_c"]
+    K = a.assim_steps or w["steps"]
+    log(f"[bench] workload {a.workload}: m={m} p={p} n_c={n_c} precision={a.precision} "
+        f"assim steps/job={K}")
+    rowptr, col, val = synth.crosswell_h(dim, n, p, planes=8)
+    ys = synth.plume_observations(dim, n, rowptr, col, val, K, w["r_var"], w["seed"] + 1)
+    torch.cuda.set_device(0)
+    pr, keep = F.problem_from_csr(dim, n, rowptr, col, val, np.full(p, w["r_var"]),
+                                  theta=w["theta"], ell=w["ell"], gamma=w["gamma"],
+                                  prior=w["prior"])
+    op = F.make_options(n_c, a.precision, False, timing=True)
+    info = F.plan(pr, op)
+    resident = torch.empty(int(info.resident_bytes), dtype=torch.uint8, device="cuda")
+    scratch = torch.empty(int(info.scratch_bytes), dtype=torch.uint8, device="cuda")
+    ydev = torch.as_tensor(ys, dtype=torch.float64, device="cuda").contiguous()
+    stream = torch.cuda.current_stream()
+    sh = ctypes.c_void_p(stream.cuda_stream)
+    log(f"[bench] resident {info.resident_bytes / 2**30:.2f} GiB, scratch "
+        f"{info.scratch_bytes / 2**30:.2f} GiB, depth {info.depth}, near pairs "
+        f"{info.near_pairs}, far pairs {info.far_pairs}")
+
+    def job(latencies):
+        handle = ctypes.c_void_p()
+        H.check(H.hikf_init(ctypes.byref(pr), ctypes.byref(op),
+                            ctypes.c_void_p(resident.data_ptr()), info.resident_bytes,
+                            ctypes.c_void_p(scratch.data_ptr()), info.scratch_bytes, sh,
+                            ctypes.byref(handle)), "hikf_init")
+        for k in range(K):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            H.check(H.hikf_step(handle, ctypes.c_void_p(ydev[k].data_ptr()), None, None, sh),
+                    "hikf_step", handle)
+            e1.record(stream)
+            latencies.append((e0, e1))
+        return handle
+
+    def finish(handle):
+        st = H.hikf_stats()
+        H.check(H.hikf_query(handle, ctypes.byref(st)), "hikf_query", handle)
+        H.hikf_destroy(handle)
+        return st
+
+    for i in range(a.warmup):
+        st = finish(job([]))
+        log(f"[bench] warmup job {i + 1}/{a.warmup} done (status {st.last_status}, "
+            f"steps {st.steps_applied})")
+    torch.cuda.synchronize()
+    lat = []
+    handles = []
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        handles.append(job(lat))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = [finish(h) for h in handles]
+    last = stats[-1]
+    if last.last_status != 0 or last.steps_applied != K:
+        raise SystemExit(f"bench: filter reported status {last.last_status} after "
+                         f"{last.steps_applied} of {K} steps")
+    log(f"[bench] timed {a.steps} jobs in {t1 - t0:.3f} s")
+    lat_ms = np.array([e0.elapsed_time(e1) for e0, e1 in lat])
+    tot = np.zeros(H.HIKF_NUM_PHASES)
+    cnt = np.zeros(H.HIKF_NUM_PHASES)
+    for s in stats:
+        tot += np.array(s.time_ms[:])
+        cnt += np.array(s.time_count[:])
+    avg = {name: (tot[i] / cnt[i] if cnt[i] else None) for i, name in enumerate(H.PHASES)}
+
+    # roofline of the dominant kernel: the fused row pass, 2 m p^2 FP64 flops
+    row_s = avg["rowpass"] / 1e3
+    row_tflops = 2.0 * m * p * p / row_s / 1e12
+    roof = {"bound": "mfma", "achieved": round(row_tflops, 3), "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(row_tflops / PEAK_FP64_TFLOPS, 4),
+            "traffic": None, "kernel": "k_rowpass (FP64 MFMA)",
+            "avg_ms": round(avg["rowpass"], 4)}
+    tq = 8 if a.precision == "f64" else 4
+    peak_f = PEAK_FP64_TFLOPS if a.precision == "f64" else PEAK_FP32_TFLOPS
+    leaves = m // 64
+    fmm = {}
+    if avg["p2p"]:
+        fl = 2.0 * info.near_pairs * 64 * 64 * p
+        by = 2.0 * m * p * tq
+        fmm["p2p_l2p"] = {"ms": round(avg["p2p"], 4),
+                          "tflops": round(fl / avg["p2p"] / 1e9, 3),
+                          "frac_fp_peak": round(fl / avg["p2p"] / 1e9 / peak_f, 4),
+                          "GBps": round(by / avg["p2p"] / 1e6, 1)}
+    if avg["m2l"]:
+        fl = 2.0 * info.far_pairs * info.r * info.r * p
+        fmm["m2l"] = {"ms": round(avg["m2l"], 4), "tflops": round(fl / avg["m2l"] / 1e9, 3),
+                      "frac_fp_peak": round(fl / avg["m2l"] / 1e9 / peak_f, 4)}
+    if avg["p2m"]:
+        by = (m * p + leaves * info.r * p) * tq
+        fmm["p2m"] = {"ms": round(avg["p2m"], 4), "GBps": round(by / avg["p2m"] / 1e6, 1),
+                      "frac_hbm": round(by / avg["p2m"] / 1e6 / PEAK_HBM_GBS, 4)}
+    init_ms = sum(avg[k] or 0.0 for k in ("operators", "p2m", "m2m", "m2l", "l2l", "p2p", "init"))
+
+    wall = t1 - t0
+    result = {
+        "metric": "assim steps/s at m=1M,p=256; Q·H^T MFMA/HBM % of peak; p50/p99 step latency",
+        "value": round(a.steps * K / wall, 3),
+        "unit": "assim steps/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(wall / a.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": a.workload, "m": m, "p": p, "dim": dim, "n_c": n_c,
+                   "kernel": f"theta*exp(-(r/{w['ell']})^{w['gamma']:g})",
+                   "fmm_dtype": a.precision, "step_dtype": "f64",
+                   "assim_steps_per_job": K, "parallelism": "none (1 GPU)"},
+        "warm_steps_per_s": round(1e3 / float(np.mean(lat_ms)), 2),
+        "step_latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
+                            "p99": round(float(np.percentile(lat_ms, 99)), 4),
+                            "mean": round(float(np.mean(lat_ms)), 4)},
+        "init_ms_kernels": round(init_ms, 3),
+        "phase_avg_ms": {k: (round(v, 4) if v is not None else None) for k, v in avg.items()},
+        "roofline": roof,
+        "fmm_roofline": fmm,
+    }
+    if not a.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample ...")
+        result["cpu_baseline"] = cpu_baseline(w, K, a.cpu_budget)
+        log("[bench] CPU oracle done")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,232 @@
+/*
+ * hikf.h -- C ABI of the MI355X (gfx950) HiKF hot path.
+ *
+ * HiKF (Li, Ambikasaran, Darve, Kitanidis) is the Kalman filter for the
+ * random-walk state-space model x_t = x_{t-1} + w_t, z_t = H x_t + v_t,
+ * w ~ N(0, Q), v ~ N(0, R) (Sec. 2.1, eqs. equation_state_evolution,
+ * equation_measurement, equation_random_walk), where Q_ij = K(|x_i - x_j|)
+ * is a kernel matrix on a uniform grid (Sec. 3.1 end; Sec. 4.2 eq.
+ * equation_Q).  The filter carries only the cross-covariance C = P H^T
+ * (m x p), the state x_hat and the variances diag P (Algorithm
+ * Algorithm_HiKF, Sec. 3.1).  The one O(m^2) product C_Q = Q H^T is formed
+ * once, at init, with a Chebyshev-interpolated H^2 / fast multipole method
+ * (Sec. 3.2).
+ *
+ * Notation: m = number of grid cells (unknowns), p = number of measurements
+ * (the paper's n), r = n_c^dim Chebyshev nodes per box.
+ *
+ * Memory model.  The library never allocates device memory.  The caller
+ * obtains the two sizes from hikf_plan, allocates a RESIDENT region (kept
+ * for the filter's lifetime) and a SCRATCH region (needed only until the
+ * work queued by hikf_init has finished on its stream) and passes both to
+ * hikf_init.  Every pointer argument named *_dev is a device pointer; all
+ * other pointers are host pointers.  All device work is queued on the
+ * caller's stream (a hipStream_t passed as void*, NULL = legacy default
+ * stream) and is asynchronous; host-side argument errors are returned
+ * immediately, errors found in device data are reported by hikf_query.
+ *
+ * Threading.  A filter is not re-entrant; distinct filters may be used
+ * concurrently on distinct streams.  No function aborts or throws across
+ * this boundary.
+ */
+#ifndef HIKF_H
+#define HIKF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hikf_status {
+    HIKF_OK = 0,
+    HIKF_E_INVALID = 1,     /* bad shape/parameter, NaN/Inf input, bad H  */
+    HIKF_E_UNSUPPORTED = 2, /* valid but outside what this build handles   */
+    HIKF_E_NOMEM = 3,       /* workspace smaller than hikf_plan asked for   */
+    HIKF_E_NOT_SPD = 4,     /* Cholesky of H C + R failed; step not applied */
+    HIKF_E_DEVICE = 5       /* a HIP runtime call failed                    */
+} hikf_status;
+
+/* Kernel families, K(r) on the Euclidean distance r between cell centres. */
+enum {
+    /* K(r) = theta * exp(-(r/ell)^gamma), 0 < gamma <= 2: Sec. 4.2 eq.
+     * equation_Q (gamma = 1 exponential, gamma = 2 Gaussian, Sec. 3.3). */
+    HIKF_KERNEL_POWEXP = 0,
+    /* K(r) = theta * r^2: test-only kernel, a polynomial of degree 2 per
+     * coordinate that Chebyshev interpolation with n_c >= 3 reproduces
+     * exactly.  Not a covariance; steps with it are meaningless. */
+    HIKF_KERNEL_TEST_R2 = 1
+};
+
+/* Initial covariance P_0 (Sec. 3.1 end; Sec. 4.2 end). */
+enum {
+    HIKF_PRIOR_ZERO = 0,     /* P_0 = 0            -> C_0 = 0,        var_0 = 0     */
+    HIKF_PRIOR_SCALED_I = 1, /* P_0 = alpha I      -> C_0 = alpha H^T, var_0 = alpha */
+    HIKF_PRIOR_KERNEL = 2    /* P_0 = Q            -> C_0 = C_Q,      var_0 = K(0)  */
+};
+
+/* Arithmetic of the H^2 product (the per-step update is always FP64). */
+enum {
+    HIKF_FMM_F32 = 0,        /* FP32 operands and accumulation, C_Q kept in FP32 */
+    HIKF_FMM_F64 = 1         /* FP64 throughout, C_Q kept in FP64                */
+};
+
+/*
+ * The assimilation problem (Sec. 2.1-2.2 with Sec. 3.1).
+ * Grid: the N^dim cell centres ((i+1/2)/N, ...) of the unit square/cube,
+ * grid order = lexicographic with the first coordinate fastest.  Every
+ * m-vector and every row of an m x p matrix at this ABI is in grid order.
+ * H (p x m) is CSR with 0-based column indices; R = diag(r_diag).
+ * Device arrays are read during hikf_init only (copied into the resident
+ * region); they may be freed once hikf_init's work has completed.
+ */
+typedef struct hikf_problem {
+    int32_t dim;             /* 2 or 3                                        */
+    int32_t n;               /* cells per axis, N; m = N^dim                  */
+    int32_t kernel_family;   /* HIKF_KERNEL_*                                 */
+    int32_t prior_kind;      /* HIKF_PRIOR_*                                  */
+    double theta, ell, gamma;/* kernel parameters (theta > 0, ell > 0)        */
+    double alpha;            /* P_0 = alpha I for HIKF_PRIOR_SCALED_I         */
+    int32_t p;               /* number of measurements (rows of H)            */
+    int32_t reserved0;
+    int64_t nnz;             /* nonzeros of H                                 */
+    const int64_t *h_rowptr_dev; /* [p+1], rowptr[0] = 0, rowptr[p] = nnz     */
+    const int32_t *h_col_dev;    /* [nnz], in [0, m)                          */
+    const double  *h_val_dev;    /* [nnz], finite                             */
+    const double  *r_diag_dev;   /* [p], finite and > 0                       */
+    const double  *x0_dev;       /* [m] prior mean, or NULL for zero          */
+} hikf_problem;
+
+typedef struct hikf_options {
+    int32_t n_c;             /* Chebyshev nodes per axis, 1..8 (r = n_c^dim) */
+    int32_t fmm_precision;   /* HIKF_FMM_F32 or HIKF_FMM_F64                 */
+    int32_t direct;          /* 1: exact near-field sum over all leaves, no
+                                far field (C_Q exact up to rounding; O(m^2),
+                                for small grids and tests)                   */
+    int32_t timing;          /* 1: bracket every phase with HIP events on the
+                                launch stream; hikf_query reports the sums    */
+} hikf_options;
+
+/* Phases timed when hikf_options.timing = 1 (indices of hikf_stats.time_ms). */
+enum {
+    HIKF_PHASE_OPERATORS = 0, /* Chebyshev and M2L operator construction      */
+    HIKF_PHASE_P2M = 1,
+    HIKF_PHASE_M2M = 2,       /* all levels together                          */
+    HIKF_PHASE_M2L = 3,       /* all levels together                          */
+    HIKF_PHASE_L2L = 4,       /* all levels together                          */
+    HIKF_PHASE_P2P = 5,       /* fused L2P + P2P                              */
+    HIKF_PHASE_INIT = 6,      /* copies, checks, W = H^T, initial state       */
+    HIKF_PHASE_GATHER = 7,    /* G = H C_prior, h = H x_hat partial sums       */
+    HIKF_PHASE_REDUCE = 8,
+    HIKF_PHASE_PSPACE = 9,    /* S, Cholesky, L^{-1}, S^{-1}, innovation      */
+    HIKF_PHASE_ROWPASS = 10,  /* gain, state, variance, cross-covariance      */
+    HIKF_PHASE_OUTPUT = 11,   /* copies to the caller's x / var buffers       */
+    HIKF_NUM_PHASES = 12
+};
+
+typedef struct hikf_plan_info {
+    size_t resident_bytes;   /* size of the RESIDENT region                  */
+    size_t scratch_bytes;    /* size of the SCRATCH region                   */
+    int64_t m;               /* N^dim                                        */
+    int32_t depth;           /* tree depth D (leaves are 8x8 / 4x4x4 cells)  */
+    int32_t r;               /* Chebyshev nodes per box                      */
+    int64_t near_pairs;      /* (target leaf, source leaf) pairs in P2P       */
+    int64_t far_pairs;       /* interaction-list pairs over all M2L levels    */
+} hikf_plan_info;
+
+typedef struct hikf_stats {
+    int64_t steps_applied;   /* assimilation steps applied since init         */
+    int32_t last_status;     /* hikf_status of the most recent step           */
+    int32_t init_status;     /* hikf_status of the device-side init checks    */
+    double min_pivot;        /* smallest Cholesky diagonal of the last step   */
+    double time_ms[HIKF_NUM_PHASES];     /* summed event time per phase       */
+    int64_t time_count[HIKF_NUM_PHASES]; /* timed executions per phase        */
+} hikf_stats;
+
+typedef struct hikf_filter hikf_filter;
+
+/*
+ * Validate a problem and report the workspace it needs.  Host only; reads
+ * no device memory and allocates nothing.
+ * Errors: HIKF_E_INVALID (dim not 2/3, N < 1, p < 1, nnz < 0, theta/ell not
+ * positive, gamma outside (0, 2], n_c outside 1..8, NULL arrays),
+ * HIKF_E_UNSUPPORTED (N not leaf * 2^k with leaf 8 (2-D) / 4 (3-D), p not a
+ * multiple of 16 or above 256).
+ */
+hikf_status hikf_plan(const hikf_problem *prob, const hikf_options *opt,
+                      hikf_plan_info *out);
+
+/*
+ * Build the filter: copy H, R and x_0 into RESIDENT, form W = H^T, compute
+ * C_Q = Q H^T with the H^2 / FMM passes (Sec. 3.2: P2M, M2M, M2L, L2L, L2P,
+ * P2P), then set C_0, var_0, x_0 from the prior (Sec. 3.1 end).
+ * resident_dev / scratch_dev: caller-owned device regions of at least the
+ * planned sizes, 256-byte aligned.  RESIDENT must outlive the filter;
+ * SCRATCH may be reused once this call's work has completed on `stream`.
+ * *out receives a host-side handle (free it with hikf_destroy).
+ * Errors: as hikf_plan, HIKF_E_NOMEM (a region too small or misaligned),
+ * HIKF_E_DEVICE (a launch failed).  Bad device data (column out of range,
+ * non-finite values, R not positive) poisons the filter: hikf_query then
+ * reports init_status = HIKF_E_INVALID and every step is a no-op.
+ */
+hikf_status hikf_init(const hikf_problem *prob, const hikf_options *opt,
+                      void *resident_dev, size_t resident_bytes,
+                      void *scratch_dev, size_t scratch_bytes,
+                      void *stream, hikf_filter **out);
+
+/*
+ * One assimilation step with measurement y_k (p doubles, y_dev), i.e. the
+ * prediction and correction of Algorithm Algorithm_HiKF:
+ *   C <- C + C_Q, var <- var + K(0); G = H C; S = (G + G^T)/2 + R = L L^T;
+ *   K = C S^{-1}; x_hat += K (y - H x_hat); var_i -= sum_j K_ij C_ij;
+ *   C <- K R   (equal to C - K G, the posterior cross-covariance).
+ * x_out_dev / var_out_dev (m doubles each, grid order) receive x_hat_{k|k}
+ * and diag P_{k|k}; either may be NULL to skip the copy.
+ * Transactional: if S is not positive definite or y holds a NaN/Inf the
+ * state is left unchanged and hikf_query reports the status.
+ * Errors (immediate): HIKF_E_INVALID (NULL filter or y), HIKF_E_DEVICE.
+ */
+hikf_status hikf_step(hikf_filter *f, const double *y_dev, double *x_out_dev,
+                      double *var_out_dev, void *stream);
+
+/*
+ * Synchronise the filter's last stream and read its device status and, if
+ * timing is on, the phase times accumulated since init.
+ * Errors: HIKF_E_INVALID (NULL), HIKF_E_DEVICE.
+ */
+hikf_status hikf_query(hikf_filter *f, hikf_stats *out);
+
+/*
+ * Copy the state into caller device buffers (any may be NULL):
+ * x_dev [m], var_dev [m], c_dev [m*p] (row i = grid cell i, p contiguous).
+ */
+hikf_status hikf_export_state(hikf_filter *f, double *x_dev, double *var_dev,
+                              double *c_dev, void *stream);
+
+/* Overwrite the state from caller device buffers (same layouts; NULL keeps
+ * that part).  Used for checkpoint / resume. */
+hikf_status hikf_import_state(hikf_filter *f, const double *x_dev,
+                              const double *var_dev, const double *c_dev,
+                              void *stream);
+
+/*
+ * Copy C_Q = Q H^T (m x p, grid order, p contiguous) widened to FP64 into
+ * cq_dev.  This is the H^2 product of Sec. 3.2 as the filter uses it.
+ */
+hikf_status hikf_export_cq(hikf_filter *f, double *cq_dev, void *stream);
+
+/* Release the host-side handle (device regions belong to the caller). */
+void hikf_destroy(hikf_filter *f);
+
+/* Static text for a status code. */
+const char *hikf_status_string(hikf_status s);
+
+/* Text of the last error seen on this filter (empty if none). */
+const char *hikf_last_error(const hikf_filter *f);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HIKF_H */

@@ -1,0 +1,380 @@
+// Host side of the C ABI declared in include/hikf.h.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "hikf_internal.h"
+
+namespace hikf {
+
+Layout make_layout(const Geometry &g) {
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    const size_t m = size_t(g.m), p = size_t(g.p), tq = g.fmm_prec == HIKF_FMM_F64 ? 8 : 4;
+    L.C = take(m * p * 8);
+    L.CQ = take(m * p * tq);
+    L.xhat = take(m * 8);
+    L.var = take(m * 8);
+    L.sinv = take(p * p * 8);
+    L.xbuf = take(size_t(g.pp) * g.pp * 8);
+    L.G = take(p * p * 8);
+    L.hvec = take(p * 8);
+    L.nu = take(p * 8);
+    L.partial = take(p * size_t(g.cpr) * (p + 1) * 8);
+    L.rowptr = take((p + 1) * 8);
+    L.col = take(size_t(g.nnz) * 4);
+    L.val = take(size_t(g.nnz) * 8);
+    L.rdiag = take(p * 8);
+    L.status = take(kNumStatus * 4);
+    L.minpiv = take(8);
+    L.steps = take(8);
+    L.resident_bytes = off;
+
+    off = 0;
+    L.W = take(m * p * tq);
+    if (g.far) {
+        const size_t r = size_t(g.r);
+        L.sleaf = take(r * kLeafPts * tq);
+        L.schild = take((size_t(1) << g.dim) * r * r * tq);
+        L.m2l = take(size_t(g.depth - 1) * g.noff() * r * r * tq);
+        size_t ml_bytes = 0;
+        for (int lev = 2; lev <= g.depth; ++lev) {
+            L.ML_level[lev] = take(size_t(g.boxes(lev)) * r * p * tq);
+        }
+        ml_bytes = off - L.ML_level[2];
+        L.L_base = take(ml_bytes);
+    }
+    L.scratch_bytes = off > 0 ? off : 256;
+    return L;
+}
+
+hipError_t Timing::create() {
+    // events are created on first use of a (phase, slot) pair
+    on = true;
+    return hipSuccess;
+}
+
+void Timing::destroy() {
+    for (int ph = 0; ph < HIKF_NUM_PHASES; ++ph)
+        for (int k = 0; k < kRing; ++k)
+            for (int b = 0; b < 2; ++b)
+                if (ev[ph][k][b]) {
+                    (void)hipEventDestroy(ev[ph][k][b]);
+                    ev[ph][k][b] = nullptr;
+                }
+    on = false;
+}
+
+hipError_t Timing::drain(int ph, int slot) {
+    if (!pending[ph][slot]) return hipSuccess;
+    hipError_t e = hipEventSynchronize(ev[ph][slot][1]);
+    if (e != hipSuccess) return e;
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, ev[ph][slot][0], ev[ph][slot][1]);
+    if (e != hipSuccess) return e;
+    total_ms[ph] += ms;
+    count[ph] += 1;
+    pending[ph][slot] = false;
+    return hipSuccess;
+}
+
+void Timing::begin(int ph, hipStream_t s) {
+    const int slot = next[ph];
+    cur[ph] = -1;
+    if (drain(ph, slot) != hipSuccess) return;
+    for (int b = 0; b < 2; ++b)
+        if (!ev[ph][slot][b] && hipEventCreate(&ev[ph][slot][b]) != hipSuccess) return;
+    if (hipEventRecord(ev[ph][slot][0], s) == hipSuccess) cur[ph] = slot;
+}
+
+void Timing::end(int ph, hipStream_t s) {
+    const int slot = cur[ph];
+    if (slot < 0) return;                          // begin() could not record
+    if (hipEventRecord(ev[ph][slot][1], s) != hipSuccess) return;
+    pending[ph][slot] = true;
+    next[ph] = (slot + 1) % kRing;
+}
+
+hipError_t Timing::collect() {
+    for (int ph = 0; ph < HIKF_NUM_PHASES; ++ph)
+        for (int k = 0; k < kRing; ++k) {
+            hipError_t e = drain(ph, k);
+            if (e != hipSuccess) return e;
+        }
+    return hipSuccess;
+}
+
+}  // namespace hikf
+
+namespace {
+
+using hikf::Geometry;
+
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+hikf_status build_geometry(const hikf_problem *pr, const hikf_options *op, Geometry *g) {
+    if (!pr || !op || !g) return HIKF_E_INVALID;
+    if (pr->dim != 2 && pr->dim != 3) return HIKF_E_INVALID;
+    if (pr->n < 1 || pr->p < 1 || pr->nnz < 0) return HIKF_E_INVALID;
+    if (op->n_c < 1 || op->n_c > 8) return HIKF_E_INVALID;
+    if (op->fmm_precision != HIKF_FMM_F32 && op->fmm_precision != HIKF_FMM_F64) return HIKF_E_INVALID;
+    if (pr->kernel_family != HIKF_KERNEL_POWEXP && pr->kernel_family != HIKF_KERNEL_TEST_R2)
+        return HIKF_E_INVALID;
+    if (!(pr->theta > 0.0) || !std::isfinite(pr->theta)) return HIKF_E_INVALID;
+    if (pr->kernel_family == HIKF_KERNEL_POWEXP) {
+        if (!(pr->ell > 0.0) || !std::isfinite(pr->ell)) return HIKF_E_INVALID;
+        if (!(pr->gamma > 0.0 && pr->gamma <= 2.0)) return HIKF_E_INVALID;
+    }
+    if (pr->prior_kind != HIKF_PRIOR_ZERO && pr->prior_kind != HIKF_PRIOR_SCALED_I &&
+        pr->prior_kind != HIKF_PRIOR_KERNEL)
+        return HIKF_E_INVALID;
+    if (pr->prior_kind == HIKF_PRIOR_SCALED_I && !(pr->alpha >= 0.0 && std::isfinite(pr->alpha)))
+        return HIKF_E_INVALID;
+    if (!pr->h_rowptr_dev || !pr->r_diag_dev || (pr->nnz > 0 && (!pr->h_col_dev || !pr->h_val_dev)))
+        return HIKF_E_INVALID;
+    g->dim = pr->dim;
+    g->n = pr->n;
+    g->ls = pr->dim == 2 ? 8 : 4;
+    if (pr->n % g->ls) return HIKF_E_UNSUPPORTED;
+    const int nl = pr->n / g->ls;
+    if (!is_pow2(nl)) return HIKF_E_UNSUPPORTED;
+    int D = 0;
+    while ((1 << D) < nl) ++D;
+    g->depth = D;
+    g->m = int64_t(pr->n) * pr->n * (pr->dim == 3 ? pr->n : 1);
+    if (g->m >= (int64_t(1) << 31)) return HIKF_E_UNSUPPORTED;
+    if (pr->p % 16 != 0 || pr->p > hikf::kMaxP) return HIKF_E_UNSUPPORTED;
+    g->p = pr->p;
+    g->pp = (pr->p + 31) / 32 * 32;
+    g->nnz = pr->nnz;
+    g->nc = op->n_c;
+    g->r = op->n_c * op->n_c * (pr->dim == 3 ? op->n_c : 1);
+    if (g->r > hikf::kMaxR) return HIKF_E_UNSUPPORTED;
+    g->direct = op->direct != 0;
+    g->far = !g->direct && D >= 2;
+    g->fmm_prec = op->fmm_precision;
+    g->prior = pr->prior_kind;
+    g->alpha = pr->alpha;
+    g->kp.family = pr->kernel_family;
+    g->kp.theta = pr->theta;
+    g->kp.ell = pr->kernel_family == HIKF_KERNEL_POWEXP ? pr->ell : 1.0;
+    g->kp.gamma = pr->kernel_family == HIKF_KERNEL_POWEXP ? pr->gamma : 1.0;
+    int64_t per_ray = (pr->nnz + pr->p - 1) / pr->p;
+    int64_t cpr = (per_ray + 63) / 64;
+    g->cpr = int(cpr < 1 ? 1 : (cpr > 1024 ? 1024 : cpr));
+    return HIKF_OK;
+}
+
+void pair_counts(const Geometry &g, int64_t *near, int64_t *far) {
+    const int64_t nl = int64_t(1) << g.depth;
+    int64_t per_axis = g.direct ? nl * nl : nl + 2 * (nl - 1);
+    int64_t n1 = per_axis, nn = 1;
+    for (int d = 0; d < g.dim; ++d) nn *= n1;
+    *near = nn;
+    int64_t f = 0;
+    if (g.far)
+        for (int lev = 2; lev <= g.depth; ++lev) {
+            int64_t nb = int64_t(1) << lev, a = 6 * nb - 8, b = 3 * nb - 2;
+            int64_t pa = 1, pb = 1;
+            for (int d = 0; d < g.dim; ++d) { pa *= a; pb *= b; }
+            f += pa - pb;
+        }
+    *far = f;
+}
+
+hikf_status set_err(hikf_filter *f, hikf_status st, const char *what, hipError_t e) {
+    if (f) snprintf(f->err, sizeof(f->err), "%s: %s", what, hipGetErrorString(e));
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+hikf_status hikf_plan(const hikf_problem *prob, const hikf_options *opt, hikf_plan_info *out) {
+    if (!out) return HIKF_E_INVALID;
+    Geometry g;
+    hikf_status st = build_geometry(prob, opt, &g);
+    if (st != HIKF_OK) return st;
+    hikf::Layout lay = hikf::make_layout(g);
+    out->resident_bytes = lay.resident_bytes;
+    out->scratch_bytes = lay.scratch_bytes;
+    out->m = g.m;
+    out->depth = g.depth;
+    out->r = g.r;
+    pair_counts(g, &out->near_pairs, &out->far_pairs);
+    return HIKF_OK;
+}
+
+hikf_status hikf_init(const hikf_problem *prob, const hikf_options *opt, void *resident_dev,
+                      size_t resident_bytes, void *scratch_dev, size_t scratch_bytes,
+                      void *stream, hikf_filter **out) {
+    if (!out) return HIKF_E_INVALID;
+    *out = nullptr;
+    Geometry g;
+    hikf_status st = build_geometry(prob, opt, &g);
+    if (st != HIKF_OK) return st;
+    hikf::Layout lay = hikf::make_layout(g);
+    if (!resident_dev || !scratch_dev || resident_bytes < lay.resident_bytes ||
+        scratch_bytes < lay.scratch_bytes)
+        return HIKF_E_NOMEM;
+    if ((reinterpret_cast<uintptr_t>(resident_dev) & 255) ||
+        (reinterpret_cast<uintptr_t>(scratch_dev) & 255))
+        return HIKF_E_NOMEM;
+    hikf_filter *f = new (std::nothrow) hikf_filter();
+    if (!f) return HIKF_E_NOMEM;
+    f->g = g;
+    f->lay = lay;
+    f->res = static_cast<char *>(resident_dev);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    f->last_stream = s;
+    char *res = f->res, *scr = static_cast<char *>(scratch_dev);
+    hipError_t e = hipGetDevice(&f->device);
+    if (e != hipSuccess) { hikf_status r = set_err(f, HIKF_E_DEVICE, "hipGetDevice", e); delete f; return r; }
+#define HIKF_TRY(call, what)                                              \
+    do {                                                                  \
+        hipError_t e_ = (call);                                           \
+        if (e_ != hipSuccess) {                                           \
+            hikf_status r_ = set_err(f, HIKF_E_DEVICE, what, e_);         \
+            (void)r_;                                                     \
+            f->timing.destroy();                                          \
+            delete f;                                                     \
+            return HIKF_E_DEVICE;                                         \
+        }                                                                 \
+    } while (0)
+    if (opt->timing) HIKF_TRY(f->timing.create(), "event create");
+    HIKF_TRY(hipMemsetAsync(res + lay.status, 0, hikf::kNumStatus * 4, s), "status clear");
+    HIKF_TRY(hipMemsetAsync(res + lay.steps, 0, 8, s), "steps clear");
+    HIKF_TRY(hipMemcpyAsync(res + lay.rowptr, prob->h_rowptr_dev, size_t(g.p + 1) * 8,
+                            hipMemcpyDeviceToDevice, s), "copy rowptr");
+    if (g.nnz > 0) {
+        HIKF_TRY(hipMemcpyAsync(res + lay.col, prob->h_col_dev, size_t(g.nnz) * 4,
+                                hipMemcpyDeviceToDevice, s), "copy col");
+        HIKF_TRY(hipMemcpyAsync(res + lay.val, prob->h_val_dev, size_t(g.nnz) * 8,
+                                hipMemcpyDeviceToDevice, s), "copy val");
+    }
+    HIKF_TRY(hipMemcpyAsync(res + lay.rdiag, prob->r_diag_dev, size_t(g.p) * 8,
+                            hipMemcpyDeviceToDevice, s), "copy R");
+    HIKF_TRY(hikf::launch_validate(g, lay, res, prob->x0_dev, s), "validate");
+    HIKF_TRY(hikf::launch_fmm(g, lay, res, scr, s, &f->timing), "fmm");
+    HIKF_TRY(hikf::launch_init_state(g, lay, res, prob->x0_dev, s), "init state");
+#undef HIKF_TRY
+    *out = f;
+    return HIKF_OK;
+}
+
+hikf_status hikf_step(hikf_filter *f, const double *y_dev, double *x_out_dev, double *var_out_dev,
+                      void *stream) {
+    if (!f || !y_dev) return HIKF_E_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    f->last_stream = s;
+    hipError_t e = hikf::launch_step(f->g, f->lay, f->res, y_dev, s, &f->timing);
+    if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "step", e);
+    const size_t mb = size_t(f->g.m) * 8;
+    if (x_out_dev || var_out_dev) hikf::tbegin(&f->timing, HIKF_PHASE_OUTPUT, s);
+    if (x_out_dev) {
+        e = hipMemcpyAsync(x_out_dev, f->res + f->lay.xhat, mb, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "copy x", e);
+    }
+    if (var_out_dev) {
+        e = hipMemcpyAsync(var_out_dev, f->res + f->lay.var, mb, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "copy var", e);
+    }
+    if (x_out_dev || var_out_dev) hikf::tend(&f->timing, HIKF_PHASE_OUTPUT, s);
+    return HIKF_OK;
+}
+
+hikf_status hikf_query(hikf_filter *f, hikf_stats *out) {
+    if (!f || !out) return HIKF_E_INVALID;
+    hipError_t e = hipStreamSynchronize(f->last_stream);
+    if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "sync", e);
+    int st[hikf::kNumStatus];
+    double mp = 0.0;
+    long long steps = 0;
+    e = hipMemcpy(st, f->res + f->lay.status, sizeof(st), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&mp, f->res + f->lay.minpiv, 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&steps, f->res + f->lay.steps, 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "read status", e);
+    out->steps_applied = steps;
+    out->last_status = st[hikf::kStStep];
+    out->init_status = st[hikf::kStInit];
+    out->min_pivot = mp;
+    if (f->timing.on) {
+        e = f->timing.collect();
+        if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "timing", e);
+    }
+    for (int ph = 0; ph < HIKF_NUM_PHASES; ++ph) {
+        out->time_ms[ph] = f->timing.total_ms[ph];
+        out->time_count[ph] = f->timing.count[ph];
+    }
+    return HIKF_OK;
+}
+
+hikf_status hikf_export_state(hikf_filter *f, double *x_dev, double *var_dev, double *c_dev,
+                              void *stream) {
+    if (!f) return HIKF_E_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    f->last_stream = s;
+    const size_t mb = size_t(f->g.m) * 8;
+    hipError_t e = hipSuccess;
+    if (x_dev) e = hipMemcpyAsync(x_dev, f->res + f->lay.xhat, mb, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && var_dev)
+        e = hipMemcpyAsync(var_dev, f->res + f->lay.var, mb, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && c_dev)
+        e = hipMemcpyAsync(c_dev, f->res + f->lay.C, mb * f->g.p, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "export", e);
+    return HIKF_OK;
+}
+
+hikf_status hikf_import_state(hikf_filter *f, const double *x_dev, const double *var_dev,
+                              const double *c_dev, void *stream) {
+    if (!f) return HIKF_E_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    f->last_stream = s;
+    const size_t mb = size_t(f->g.m) * 8;
+    hipError_t e = hipSuccess;
+    if (x_dev) e = hipMemcpyAsync(f->res + f->lay.xhat, x_dev, mb, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && var_dev)
+        e = hipMemcpyAsync(f->res + f->lay.var, var_dev, mb, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && c_dev)
+        e = hipMemcpyAsync(f->res + f->lay.C, c_dev, mb * f->g.p, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "import", e);
+    return HIKF_OK;
+}
+
+hikf_status hikf_export_cq(hikf_filter *f, double *cq_dev, void *stream) {
+    if (!f || !cq_dev) return HIKF_E_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    f->last_stream = s;
+    hipError_t e = hikf::launch_widen_cq(f->g, f->lay, f->res, cq_dev, s);
+    if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "export cq", e);
+    return HIKF_OK;
+}
+
+void hikf_destroy(hikf_filter *f) {
+    if (!f) return;
+    f->timing.destroy();
+    delete f;
+}
+
+const char *hikf_status_string(hikf_status s) {
+    switch (s) {
+        case HIKF_OK: return "ok";
+        case HIKF_E_INVALID: return "invalid argument or input data";
+        case HIKF_E_UNSUPPORTED: return "unsupported problem shape";
+        case HIKF_E_NOMEM: return "workspace too small or misaligned";
+        case HIKF_E_NOT_SPD: return "innovation covariance not positive definite";
+        case HIKF_E_DEVICE: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+const char *hikf_last_error(const hikf_filter *f) { return f ? f->err : ""; }
+
+}  // extern "C"

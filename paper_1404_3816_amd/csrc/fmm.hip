@@ -1,0 +1,494 @@
+// H^2 / black-box FMM product C_Q = Q H^T on a uniform grid (Sec. 3.2).
+//
+// Sec. 3.2 writes Q H^T = [Q h^(1) ... Q h^(p)], each column a kernel sum
+// (Q h)_i = sum_j K(x_i, x_j) h_j, and evaluates it with the fast multipole
+// method whose far field is represented by Chebyshev interpolation (the
+// black-box FMM of Fong & Darve 2009 that the paper cites).  All p right-hand
+// sides travel together through every pass.
+//
+// Tree: the N^dim cell-centred grid is split into leaves of 8x8 (2-D) or
+// 4x4x4 (3-D) cells (64 points); level l has 2^l boxes per axis.  Box arrays
+// are [box][node k][column] with the p columns contiguous; node index
+// k = kx + nc*ky (+ nc^2*kz), box index b = bx + nb*by (+ nb^2*bz).
+//
+// Passes: P2M (leaf anterpolation), M2M (upward, levels D-1..2), M2L
+// (interaction lists, levels 2..D), L2L (downward), and the fused L2P + P2P
+// (leaf interpolation plus the near-field sum with kernel entries generated
+// on the fly).  Operators are built on the device in FP64 and stored in the
+// pass precision T (float or double).
+#include "hikf_internal.h"
+
+namespace hikf {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMaxU = 16;         // outputs per thread in the tile kernels
+
+__device__ __forceinline__ double cheb_node(int nc, int k) {
+    return cos((2 * k + 1) * M_PI / (2.0 * nc));
+}
+
+// S_nc(xi, x) = 1/nc + (2/nc) sum_{l=1}^{nc-1} T_l(xi) T_l(x)
+__device__ double cheb_S(int nc, double xi, double x) {
+    double s = 0.0;
+    double a0 = 1.0, a1 = xi, b0 = 1.0, b1 = x;
+    for (int l = 1; l < nc; ++l) {
+        s += a1 * b1;
+        double a2 = 2.0 * xi * a1 - a0;
+        double b2 = 2.0 * x * b1 - b0;
+        a0 = a1; a1 = a2; b0 = b1; b1 = b2;
+    }
+    return (1.0 + 2.0 * s) / nc;
+}
+
+__device__ __forceinline__ void node_idx(int k, int nc, int *kk) {
+    kk[0] = k % nc;
+    kk[1] = (k / nc) % nc;
+    kk[2] = k / (nc * nc);
+}
+
+__device__ __forceinline__ void leaf_local(int j, int dim, int *l) {
+    if (dim == 2) { l[0] = j & 7; l[1] = j >> 3; l[2] = 0; }
+    else          { l[0] = j & 3; l[1] = (j >> 2) & 3; l[2] = j >> 4; }
+}
+
+__device__ __forceinline__ void box_coords(int64_t b, int nb, int dim, int *c) {
+    c[0] = int(b % nb);
+    c[1] = int((b / nb) % nb);
+    c[2] = dim == 3 ? int(b / (int64_t(nb) * nb)) : 0;
+}
+
+__device__ __forceinline__ int64_t box_index(const int *c, int nb, int dim) {
+    int64_t b = c[0] + int64_t(nb) * c[1];
+    if (dim == 3) b += int64_t(nb) * nb * c[2];
+    return b;
+}
+
+// grid-order index of local point j of leaf with coordinates bc
+__device__ __forceinline__ int64_t leaf_point(const int *bc, int j, int dim, int n, int ls) {
+    int l[3];
+    leaf_local(j, dim, l);
+    int64_t g = int64_t(bc[0]) * ls + l[0];
+    g += int64_t(n) * (int64_t(bc[1]) * ls + l[1]);
+    if (dim == 3) g += int64_t(n) * n * (int64_t(bc[2]) * ls + l[2]);
+    return g;
+}
+
+// ---------------------------------------------------------------- operators
+template <typename T>
+__global__ void k_ops_sleaf(int dim, int nc, int ls, int r, T *out) {
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= r * kLeafPts) return;
+    int k = idx / kLeafPts, j = idx % kLeafPts;
+    int kk[3], l[3];
+    node_idx(k, nc, kk);
+    leaf_local(j, dim, l);
+    double half = 0.5 * ls, v = 1.0;
+    for (int ax = 0; ax < dim; ++ax)
+        v *= cheb_S(nc, cheb_node(nc, kk[ax]), (l[ax] + 0.5 - half) / half);
+    out[idx] = (T)v;
+}
+
+template <typename T>
+__global__ void k_ops_schild(int dim, int nc, int r, T *out) {
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    int nch = 1 << dim;
+    if (idx >= nch * r * r) return;
+    int ch = idx / (r * r), rem = idx % (r * r);
+    int k = rem / r, kq = rem % r;
+    int kk[3], kq3[3];
+    node_idx(k, nc, kk);
+    node_idx(kq, nc, kq3);
+    double v = 1.0;
+    for (int ax = 0; ax < dim; ++ax) {
+        double shift = ((ch >> ax) & 1) ? 0.5 : -0.5;
+        v *= cheb_S(nc, cheb_node(nc, kk[ax]), shift + 0.5 * cheb_node(nc, kq3[ax]));
+    }
+    out[idx] = (T)v;
+}
+
+// T_{l,o}[k][k'] = K(s_l * |o + (xi_k' - xi_k)/2|), o in [-3,3]^dim, slot
+// oi = (ox+3) + 7 (oy+3) (+ 49 (oz+3)); slots with max|o| < 2 are zero.
+template <typename T>
+__global__ void k_ops_m2l(int dim, int nc, int r, int lev0, int nlev, KernelParams kp,
+                          T *out) {
+    int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int noff = dim == 2 ? 49 : 343;
+    int64_t per_lev = int64_t(noff) * r * r;
+    if (idx >= per_lev * nlev) return;
+    int lev = lev0 + int(idx / per_lev);
+    int64_t rem = idx % per_lev;
+    int oi = int(rem / (r * r));
+    int rr = int(rem % (r * r));
+    int k = rr / r, kq = rr % r;
+    int o[3] = {oi % 7 - 3, (oi / 7) % 7 - 3, oi / 49 - 3};
+    int omax = 0;
+    for (int ax = 0; ax < dim; ++ax) omax = max(omax, abs(o[ax]));
+    if (omax < 2) { out[idx] = (T)0; return; }
+    int kk[3], kq3[3];
+    node_idx(k, nc, kk);
+    node_idx(kq, nc, kq3);
+    double s = 1.0 / double(int64_t(1) << lev), r2 = 0.0;
+    for (int ax = 0; ax < dim; ++ax) {
+        double d = s * (o[ax] + 0.5 * (cheb_node(nc, kq3[ax]) - cheb_node(nc, kk[ax])));
+        r2 += d * d;
+    }
+    out[idx] = (T)kernel_from_r2<double>(r2, kp);
+}
+
+// ---------------------------------------------------------------- W = H^T
+template <typename T>
+__global__ void k_scatter_w(int64_t nnz, int p, int64_t m, const int64_t *rowptr,
+                            const int32_t *col, const double *val, T *W) {
+    int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    int lo = 0, hi = p - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (rowptr[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    if (rowptr[lo] > e || rowptr[lo + 1] <= e) return;
+    int64_t c = col[e];
+    if (c < 0 || c >= m) return;
+    W[c * p + lo] = (T)val[e];
+}
+
+// ---------------------------------------------------------------- P2M
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_p2m(int dim, int n, int ls, int depth, int r, int p, int PT, const T *W,
+      const T *Sleaf, T *Mleaf) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sW = reinterpret_cast<T *>(smem_raw);           // [64][PT]
+    const int64_t B = blockIdx.x;
+    const int c0 = blockIdx.y * PT;
+    const int ncols = min(PT, p - c0);
+    const int nb = 1 << depth;
+    int bc[3];
+    box_coords(B, nb, dim, bc);
+    for (int idx = threadIdx.x; idx < kLeafPts * PT; idx += blockDim.x) {
+        int j = idx / PT, c = idx % PT;
+        T v = (T)0;
+        if (c < ncols) v = W[leaf_point(bc, j, dim, n, ls) * p + c0 + c];
+        sW[idx] = v;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < r * PT; idx += blockDim.x) {
+        int k = idx / PT, c = idx % PT;
+        if (c >= ncols) continue;
+        T acc = (T)0;
+        const T *srow = Sleaf + k * kLeafPts;
+        for (int j = 0; j < kLeafPts; ++j) acc += srow[j] * sW[j * PT + c];
+        Mleaf[(B * r + k) * p + c0 + c] = acc;
+    }
+}
+
+// ---------------------------------------------------------------- M2M
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_m2m(int dim, int r, int p, int lev, int PT, const T *Mchild, const T *Schild, T *Mpar) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sM = reinterpret_cast<T *>(smem_raw);           // [nch][r][PT]
+    const int64_t P = blockIdx.x;
+    const int c0 = blockIdx.y * PT;
+    const int ncols = min(PT, p - c0);
+    const int nb = 1 << lev, nbc = nb << 1, nch = 1 << dim;
+    int pc[3];
+    box_coords(P, nb, dim, pc);
+    for (int idx = threadIdx.x; idx < nch * r * PT; idx += blockDim.x) {
+        int ch = idx / (r * PT), rem = idx % (r * PT);
+        int k = rem / PT, c = rem % PT;
+        int cc[3] = {2 * pc[0] + (ch & 1), 2 * pc[1] + ((ch >> 1) & 1), 2 * pc[2] + ((ch >> 2) & 1)};
+        int64_t Bc = box_index(cc, nbc, dim);
+        sM[idx] = (c < ncols) ? Mchild[(Bc * r + k) * p + c0 + c] : (T)0;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < r * PT; idx += blockDim.x) {
+        int k = idx / PT, c = idx % PT;
+        if (c >= ncols) continue;
+        T acc = (T)0;
+        for (int ch = 0; ch < nch; ++ch) {
+            const T *srow = Schild + (ch * r + k) * r;
+            const T *m = sM + ch * r * PT + c;
+            for (int kq = 0; kq < r; ++kq) acc += srow[kq] * m[kq * PT];
+        }
+        Mpar[(P * r + k) * p + c0 + c] = acc;
+    }
+}
+
+// ---------------------------------------------------------------- M2L
+// Interaction list of B at level l: boxes A = B + o with max|o| >= 2 whose
+// parent is adjacent to (or equal to) B's parent.
+__device__ __forceinline__ bool il_member(const int *b, const int *o, int nb, int dim) {
+    int omax = 0;
+    for (int ax = 0; ax < dim; ++ax) {
+        int a = b[ax] + o[ax];
+        if (a < 0 || a >= nb) return false;
+        int lo = (b[ax] & 1) ? -3 : -2, hi = (b[ax] & 1) ? 2 : 3;
+        if (o[ax] < lo || o[ax] > hi) return false;
+        omax = max(omax, abs(o[ax]));
+    }
+    return omax >= 2;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_m2l(int dim, int r, int p, int lev, int PT, const T *M, const T *Tlev, T *L) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sM = reinterpret_cast<T *>(smem_raw);           // [r][PT]
+    const int64_t B = blockIdx.x;
+    const int c0 = blockIdx.y * PT;
+    const int ncols = min(PT, p - c0);
+    const int nb = 1 << lev;
+    const int noff = dim == 2 ? 49 : 343;
+    int b[3];
+    box_coords(B, nb, dim, b);
+    T acc[kMaxU];
+#pragma unroll
+    for (int u = 0; u < kMaxU; ++u) acc[u] = (T)0;
+    for (int oi = 0; oi < noff; ++oi) {
+        int o[3] = {oi % 7 - 3, (oi / 7) % 7 - 3, oi / 49 - 3};
+        if (!il_member(b, o, nb, dim)) continue;
+        int a[3] = {b[0] + o[0], b[1] + o[1], dim == 3 ? b[2] + o[2] : 0};
+        int64_t A = box_index(a, nb, dim);
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < r * PT; idx += blockDim.x) {
+            int k = idx / PT, c = idx % PT;
+            sM[idx] = (c < ncols) ? M[(A * r + k) * p + c0 + c] : (T)0;
+        }
+        __syncthreads();
+        const T *Toff = Tlev + int64_t(oi) * r * r;
+#pragma unroll
+        for (int u = 0; u < kMaxU; ++u) {
+            int idx = threadIdx.x + u * blockDim.x;
+            if (idx < r * PT) {
+                int k = idx / PT, c = idx % PT;
+                const T *trow = Toff + k * r;
+                T s = (T)0;
+                for (int kq = 0; kq < r; ++kq) s += trow[kq] * sM[kq * PT + c];
+                acc[u] += s;
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kMaxU; ++u) {
+        int idx = threadIdx.x + u * blockDim.x;
+        if (idx < r * PT) {
+            int k = idx / PT, c = idx % PT;
+            if (c < ncols) L[(B * r + k) * p + c0 + c] = acc[u];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- L2L
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_l2l(int dim, int r, int p, int lev, int PT, const T *Lpar, const T *Schild, T *Lchild) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sL = reinterpret_cast<T *>(smem_raw);           // [r][PT]
+    const int64_t Bc = blockIdx.x;                     // child at level lev + 1
+    const int c0 = blockIdx.y * PT;
+    const int ncols = min(PT, p - c0);
+    const int nbc = 2 << lev, nb = 1 << lev;
+    int cc[3];
+    box_coords(Bc, nbc, dim, cc);
+    int pc[3] = {cc[0] >> 1, cc[1] >> 1, cc[2] >> 1};
+    int ch = (cc[0] & 1) | ((cc[1] & 1) << 1) | ((cc[2] & 1) << 2);
+    int64_t P = box_index(pc, nb, dim);
+    for (int idx = threadIdx.x; idx < r * PT; idx += blockDim.x) {
+        int k = idx / PT, c = idx % PT;
+        sL[idx] = (c < ncols) ? Lpar[(P * r + k) * p + c0 + c] : (T)0;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < r * PT; idx += blockDim.x) {
+        int kq = idx / PT, c = idx % PT;
+        if (c >= ncols) continue;
+        T acc = (T)0;
+        const T *S = Schild + int64_t(ch) * r * r + kq;
+        for (int k = 0; k < r; ++k) acc += S[k * r] * sL[k * PT + c];
+        Lchild[(Bc * r + kq) * p + c0 + c] += acc;
+    }
+}
+
+// ---------------------------------------------------------------- L2P + P2P
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_l2p_p2p(int dim, int n, int ls, int depth, int r, int p, int PT, int rad, int far,
+          KernelParams kp, T h2, const T *W, const T *Sleaf, const T *Lleaf, T *CQ) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sK = reinterpret_cast<T *>(smem_raw);           // [64][64]
+    T *sW = sK + kLeafPts * kLeafPts;                  // [max(64, r)][PT]
+    const int64_t B = blockIdx.x;
+    const int c0 = blockIdx.y * PT;
+    const int ncols = min(PT, p - c0);
+    const int nb = 1 << depth;
+    int b[3];
+    box_coords(B, nb, dim, b);
+    T acc[kMaxU];
+#pragma unroll
+    for (int u = 0; u < kMaxU; ++u) acc[u] = (T)0;
+    const int zlo = dim == 3 ? max(0, b[2] - rad) : 0;
+    const int zhi = dim == 3 ? min(nb - 1, b[2] + rad) : 0;
+    for (int az = zlo; az <= zhi; ++az)
+    for (int ay = max(0, b[1] - rad); ay <= min(nb - 1, b[1] + rad); ++ay)
+    for (int ax = max(0, b[0] - rad); ax <= min(nb - 1, b[0] + rad); ++ax) {
+        int a[3] = {ax, ay, az};
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < kLeafPts * PT; idx += blockDim.x) {
+            int j = idx / PT, c = idx % PT;
+            sW[idx] = (c < ncols) ? W[leaf_point(a, j, dim, n, ls) * p + c0 + c] : (T)0;
+        }
+        for (int idx = threadIdx.x; idx < kLeafPts * kLeafPts; idx += blockDim.x) {
+            int i = idx / kLeafPts, j = idx % kLeafPts;
+            int li[3], lj[3];
+            leaf_local(i, dim, li);
+            leaf_local(j, dim, lj);
+            int dsq = 0;
+            for (int q = 0; q < dim; ++q) {
+                int d = (a[q] - b[q]) * ls + lj[q] - li[q];
+                dsq += d * d;
+            }
+            sK[idx] = kernel_from_r2<T>((T)dsq * h2, kp);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kMaxU; ++u) {
+            int idx = threadIdx.x + u * blockDim.x;
+            if (idx < kLeafPts * PT) {
+                int i = idx / PT, c = idx % PT;
+                const T *krow = sK + i * kLeafPts;
+                T s = (T)0;
+                for (int j = 0; j < kLeafPts; ++j) s += krow[j] * sW[j * PT + c];
+                acc[u] += s;
+            }
+        }
+    }
+    if (far) {
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < r * PT; idx += blockDim.x) {
+            int k = idx / PT, c = idx % PT;
+            sW[idx] = (c < ncols) ? Lleaf[(B * r + k) * p + c0 + c] : (T)0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kMaxU; ++u) {
+            int idx = threadIdx.x + u * blockDim.x;
+            if (idx < kLeafPts * PT) {
+                int i = idx / PT, c = idx % PT;
+                T s = (T)0;
+                for (int k = 0; k < r; ++k) s += Sleaf[k * kLeafPts + i] * sW[k * PT + c];
+                acc[u] += s;
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kMaxU; ++u) {
+        int idx = threadIdx.x + u * blockDim.x;
+        if (idx < kLeafPts * PT) {
+            int i = idx / PT, c = idx % PT;
+            if (c < ncols) CQ[leaf_point(b, i, dim, n, ls) * p + c0 + c] = acc[u];
+        }
+    }
+}
+
+int floor_pow2(int x) {
+    int v = 1;
+    while (v * 2 <= x) v *= 2;
+    return v;
+}
+
+template <typename T>
+hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, hipStream_t s,
+                   Timing *tm) {
+    const int p = g.p, r = g.r, dim = g.dim, D = g.depth;
+    const int64_t m = g.m;
+    T *W = reinterpret_cast<T *>(scr + lay.W);
+    T *CQ = reinterpret_cast<T *>(res + lay.CQ);
+    const int64_t *rowptr = reinterpret_cast<const int64_t *>(res + lay.rowptr);
+    const int32_t *col = reinterpret_cast<const int32_t *>(res + lay.col);
+    const double *val = reinterpret_cast<const double *>(res + lay.val);
+    tbegin(tm, HIKF_PHASE_INIT, s);
+    hipError_t e = hipMemsetAsync(W, 0, size_t(m) * p * sizeof(T), s);
+    if (e != hipSuccess) return e;
+    if (g.nnz > 0) {
+        int64_t blocks = (g.nnz + kBlock - 1) / kBlock;
+        hipLaunchKernelGGL(k_scatter_w<T>, dim3(unsigned(blocks)), dim3(kBlock), 0, s,
+                           g.nnz, p, m, rowptr, col, val, W);
+    }
+    tend(tm, HIKF_PHASE_INIT, s);
+    T *Sleaf = reinterpret_cast<T *>(scr + lay.sleaf);
+    T *Schild = reinterpret_cast<T *>(scr + lay.schild);
+    T *Tm2l = reinterpret_cast<T *>(scr + lay.m2l);
+    auto Mlev = [&](int lev) { return reinterpret_cast<T *>(scr + lay.ML_level[lev]); };
+    const size_t lds_cap = 64 * 1024;
+    auto Llev = [&](int lev) {
+        return reinterpret_cast<T *>(scr + lay.L_base + (lay.ML_level[lev] - lay.ML_level[2]));
+    };
+    if (g.far) {
+        tbegin(tm, HIKF_PHASE_OPERATORS, s);
+        int tot = r * kLeafPts;
+        hipLaunchKernelGGL(k_ops_sleaf<T>, dim3((tot + 255) / 256), dim3(256), 0, s,
+                           dim, g.nc, g.ls, r, Sleaf);
+        tot = (1 << dim) * r * r;
+        hipLaunchKernelGGL(k_ops_schild<T>, dim3((tot + 255) / 256), dim3(256), 0, s,
+                           dim, g.nc, r, Schild);
+        int64_t tot64 = int64_t(D - 1) * g.noff() * r * r;
+        hipLaunchKernelGGL(k_ops_m2l<T>, dim3(unsigned((tot64 + 255) / 256)), dim3(256), 0, s,
+                           dim, g.nc, r, 2, D - 1, g.kp, Tm2l);
+        tend(tm, HIKF_PHASE_OPERATORS, s);
+        // P2M
+        tbegin(tm, HIKF_PHASE_P2M, s);
+        int PT = min(64, p);
+        hipLaunchKernelGGL(k_p2m<T>, dim3(unsigned(g.boxes(D)), (p + PT - 1) / PT), dim3(kBlock),
+                           kLeafPts * PT * sizeof(T), s, dim, g.n, g.ls, D, r, p, PT, W, Sleaf,
+                           Mlev(D));
+        tend(tm, HIKF_PHASE_P2M, s);
+        // M2M
+        tbegin(tm, HIKF_PHASE_M2M, s);
+        PT = min(p, min(64, floor_pow2(int(lds_cap / ((size_t(1) << dim) * r * sizeof(T))))));
+        for (int lev = D - 1; lev >= 2; --lev)
+            hipLaunchKernelGGL(k_m2m<T>, dim3(unsigned(g.boxes(lev)), (p + PT - 1) / PT),
+                               dim3(kBlock), (size_t(1) << dim) * r * PT * sizeof(T), s, dim, r, p,
+                               lev, PT, Mlev(lev + 1), Schild, Mlev(lev));
+        tend(tm, HIKF_PHASE_M2M, s);
+        // M2L
+        tbegin(tm, HIKF_PHASE_M2L, s);
+        PT = min(p, min(64, floor_pow2(kMaxU * kBlock / r)));
+        for (int lev = 2; lev <= D; ++lev)
+            hipLaunchKernelGGL(k_m2l<T>, dim3(unsigned(g.boxes(lev)), (p + PT - 1) / PT),
+                               dim3(kBlock), size_t(r) * PT * sizeof(T), s, dim, r, p, lev, PT,
+                               Mlev(lev), Tm2l + int64_t(lev - 2) * g.noff() * r * r, Llev(lev));
+        tend(tm, HIKF_PHASE_M2L, s);
+        // L2L
+        tbegin(tm, HIKF_PHASE_L2L, s);
+        PT = min(p, 64);
+        for (int lev = 2; lev < D; ++lev)
+            hipLaunchKernelGGL(k_l2l<T>, dim3(unsigned(g.boxes(lev + 1)), (p + PT - 1) / PT),
+                               dim3(kBlock), size_t(r) * PT * sizeof(T), s, dim, r, p, lev, PT,
+                               Llev(lev), Schild, Llev(lev + 1));
+        tend(tm, HIKF_PHASE_L2L, s);
+    }
+    {
+        int rows = max(kLeafPts, r);
+        int PT = min(p, min(64, floor_pow2(int((lds_cap / sizeof(T) - size_t(kLeafPts) * kLeafPts) / rows))));
+        int rad = g.direct ? (1 << D) : 1;
+        double h = 1.0 / g.n;
+        size_t lds = (size_t(kLeafPts) * kLeafPts + size_t(max(kLeafPts, r)) * PT) * sizeof(T);
+        tbegin(tm, HIKF_PHASE_P2P, s);
+        hipLaunchKernelGGL(k_l2p_p2p<T>, dim3(unsigned(g.boxes(D)), (p + PT - 1) / PT),
+                           dim3(kBlock), lds, s, dim, g.n, g.ls, D, r, p, PT, rad, g.far ? 1 : 0,
+                           g.kp, (T)(h * h), W, Sleaf, g.far ? Llev(D) : W, CQ);
+        tend(tm, HIKF_PHASE_P2P, s);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, hipStream_t s,
+                      Timing *t) {
+    if (g.fmm_prec == HIKF_FMM_F64) return run_fmm<double>(g, lay, res, scr, s, t);
+    return run_fmm<float>(g, lay, res, scr, s, t);
+}
+
+}  // namespace hikf

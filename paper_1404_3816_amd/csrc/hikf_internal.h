@@ -1,0 +1,142 @@
+// Internal declarations shared by the HiKF HIP sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "hikf.h"
+
+namespace hikf {
+
+constexpr int kLeafPts = 64;      // points per leaf: 8x8 (2-D) or 4x4x4 (3-D)
+constexpr int kMaxP = 256;        // measurements handled by the register p-space kernel
+constexpr int kMaxR = 128;        // Chebyshev nodes per box
+constexpr int kNumStatus = 8;     // ints in the device status block
+
+// device status block layout (int32 slots)
+enum : int {
+    kStStep = 0,                  // hikf_status of the last step
+    kStInit = 1,                  // hikf_status of the device-side init checks
+};
+
+struct KernelParams {
+    int family;                   // HIKF_KERNEL_*
+    double theta, ell, gamma;
+};
+
+// Covariance kernel evaluated from the squared distance r2.
+template <typename T>
+__device__ __forceinline__ T kernel_from_r2(T r2, const KernelParams &kp);
+
+template <>
+__device__ __forceinline__ double kernel_from_r2<double>(double r2, const KernelParams &kp) {
+    if (kp.family == HIKF_KERNEL_TEST_R2) return kp.theta * r2;
+    if (kp.gamma == 2.0) return kp.theta * exp(-r2 / (kp.ell * kp.ell));
+    double r = sqrt(r2);
+    if (kp.gamma == 1.0) return kp.theta * exp(-r / kp.ell);
+    return kp.theta * exp(-pow(r / kp.ell, kp.gamma));
+}
+
+template <>
+__device__ __forceinline__ float kernel_from_r2<float>(float r2, const KernelParams &kp) {
+    const float theta = (float)kp.theta;
+    if (kp.family == HIKF_KERNEL_TEST_R2) return theta * r2;
+    const float ell = (float)kp.ell;
+    if (kp.gamma == 2.0) return theta * expf(-r2 / (ell * ell));
+    float r = sqrtf(r2);
+    if (kp.gamma == 1.0) return theta * expf(-r / ell);
+    return theta * expf(-powf(r / ell, (float)kp.gamma));
+}
+
+// Uniform-tree geometry of one filter.
+struct Geometry {
+    int dim = 2;
+    int n = 0;                    // cells per axis
+    int ls = 8;                   // cells per leaf per axis
+    int depth = 0;                // leaves per axis = 2^depth
+    int nc = 4;                   // Chebyshev nodes per axis
+    int r = 16;                   // nc^dim
+    int p = 0;
+    int pp = 32;                  // p rounded up to 32 (p-space layout)
+    int cpr = 1;                  // gather chunks per ray
+    int64_t m = 0;
+    int64_t nnz = 0;
+    bool direct = false;
+    bool far = false;             // far field present (depth >= 2 and not direct)
+    int fmm_prec = HIKF_FMM_F32;
+    int prior = HIKF_PRIOR_KERNEL;
+    double alpha = 0.0;
+    KernelParams kp{};
+    int64_t boxes(int level) const {
+        int64_t nb = int64_t(1) << level;
+        return dim == 2 ? nb * nb : nb * nb * nb;
+    }
+    int noff() const { return dim == 2 ? 49 : 343; }   // 7^dim offset slots
+};
+
+// Byte offsets of every array inside the two caller-owned regions.
+struct Layout {
+    // resident
+    size_t C, CQ, xhat, var, sinv, xbuf, G, hvec, nu, partial;
+    size_t rowptr, col, val, rdiag, status, minpiv, steps;
+    size_t resident_bytes;
+    // scratch
+    size_t W, sleaf, schild, m2l, lev_off;   // lev_off: start of M/L storage
+    size_t ML_level[24];                      // per-level offset of M (L follows after all M)
+    size_t L_base;
+    size_t scratch_bytes;
+};
+
+Layout make_layout(const Geometry &g);
+
+// HIP-event timing of the phases listed in hikf.h (HIKF_PHASE_*).  Each
+// phase owns a ring of event pairs so that steps can be queued without a
+// host synchronisation; a slot is drained before it is reused.
+struct Timing {
+    static constexpr int kRing = 64;
+    bool on = false;
+    hipEvent_t ev[HIKF_NUM_PHASES][kRing][2] = {};
+    bool pending[HIKF_NUM_PHASES][kRing] = {};
+    int next[HIKF_NUM_PHASES] = {};
+    int cur[HIKF_NUM_PHASES] = {};
+    double total_ms[HIKF_NUM_PHASES] = {};
+    int64_t count[HIKF_NUM_PHASES] = {};
+    hipError_t create();
+    void destroy();
+    hipError_t drain(int ph, int slot);
+    void begin(int ph, hipStream_t s);
+    void end(int ph, hipStream_t s);
+    hipError_t collect();
+};
+
+// begin/end helpers that accept a null timer
+inline void tbegin(Timing *t, int ph, hipStream_t s) { if (t && t->on) t->begin(ph, s); }
+inline void tend(Timing *t, int ph, hipStream_t s) { if (t && t->on) t->end(ph, s); }
+
+// ---- launch wrappers (defined in fmm.hip / step.hip) ----
+hipError_t launch_fmm(const Geometry &g, const Layout &lay, char *res, char *scr,
+                      hipStream_t s, Timing *t);
+hipError_t launch_validate(const Geometry &g, const Layout &lay, char *res,
+                           const double *x0, hipStream_t s);
+hipError_t launch_init_state(const Geometry &g, const Layout &lay, char *res,
+                             const double *x0, hipStream_t s);
+hipError_t launch_step(const Geometry &g, const Layout &lay, char *res,
+                       const double *y, hipStream_t s, Timing *t);
+hipError_t launch_widen_cq(const Geometry &g, const Layout &lay, char *res,
+                           double *out, hipStream_t s);
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace hikf
+
+struct hikf_filter {
+    hikf::Geometry g;
+    hikf::Layout lay;
+    char *res = nullptr;          // resident region (caller-owned)
+    hipStream_t last_stream = nullptr;
+    int device = 0;
+    hikf::Timing timing;
+    char err[256] = {0};
+};

@@ -1,0 +1,580 @@
+// Per-step HiKF update on the GPU (Algorithm Algorithm_HiKF, Sec. 3.1).
+//
+// One assimilation step is four launches:
+//   1. k_gather   : partial sums of G = H (C + C_Q) and h = H x_hat over
+//                   chunks of each ray's nonzeros (the prediction
+//                   C_{t+1|t} = C_{t|t} + C_Q is formed on the fly).
+//   2. k_reduce_g : chunk partials -> G (p x p), h (p), in a fixed order.
+//   3. k_pspace   : one 1024-thread workgroup: S = (G + G^T)/2 + R, its
+//                   Cholesky factor L, X = L^{-1}, S^{-1} = X^T X and the
+//                   innovation nu = y - h; writes the step status.
+//   4. k_rowpass  : K = C_prior S^{-1} on FP64 MFMA, fused with the state,
+//                   variance and cross-covariance updates:
+//                   x_hat += K nu, var += K(0) - sum_j K_ij C_prior,ij,
+//                   C <- K R (= C_prior - K G).  Skipped when the status
+//                   is not OK, so a failed step leaves the state untouched.
+#include "hikf_internal.h"
+
+namespace hikf {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------- init
+__global__ void k_validate(int p, int64_t nnz, int64_t m, const int64_t *rowptr,
+                           const int32_t *col, const double *val, const double *rdiag,
+                           const double *x0, int *status) {
+    int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    int bad = 0;
+    for (int64_t i = tid; i <= p; i += stride) {
+        if (i == 0 && rowptr[0] != 0) bad = 1;
+        if (i == p && rowptr[p] != nnz) bad = 1;
+        if (i < p && rowptr[i] > rowptr[i + 1]) bad = 1;
+        if (i < p && !(rdiag[i] > 0.0 && isfinite(rdiag[i]))) bad = 1;
+    }
+    for (int64_t e = tid; e < nnz; e += stride) {
+        int64_t c = col[e];
+        if (c < 0 || c >= m || !isfinite(val[e])) bad = 1;
+        int lo = 0, hi = p - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (rowptr[mid] <= e) lo = mid; else hi = mid - 1;
+        }
+        int64_t end = rowptr[lo + 1];
+        if (e + 1 < nnz && e + 1 < end && col[e + 1] <= c) bad = 1;   // strictly increasing
+    }
+    if (x0)
+        for (int64_t i = tid; i < m; i += stride)
+            if (!isfinite(x0[i])) bad = 1;
+    if (bad) status[kStInit] = HIKF_E_INVALID;
+}
+
+template <typename TQ>
+__global__ void k_init_state(int64_t m, int p, int prior, double alpha, double kdiag,
+                             const TQ *CQ, const double *x0, double *C, double *xhat,
+                             double *var) {
+    int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    int64_t mp = m * p;
+    for (int64_t i = tid; i < mp; i += stride)
+        C[i] = prior == HIKF_PRIOR_KERNEL ? (double)CQ[i] : 0.0;
+    double v0 = prior == HIKF_PRIOR_KERNEL ? kdiag : (prior == HIKF_PRIOR_SCALED_I ? alpha : 0.0);
+    for (int64_t i = tid; i < m; i += stride) {
+        xhat[i] = x0 ? x0[i] : 0.0;
+        var[i] = v0;
+    }
+}
+
+// C_0 = alpha H^T for P_0 = alpha I
+__global__ void k_scatter_c(int64_t nnz, int p, int64_t m, double alpha, const int64_t *rowptr,
+                            const int32_t *col, const double *val, double *C) {
+    int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    int lo = 0, hi = p - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (rowptr[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    if (rowptr[lo] > e || rowptr[lo + 1] <= e) return;
+    int64_t c = col[e];
+    if (c < 0 || c >= m) return;
+    C[c * p + lo] = alpha * val[e];
+}
+
+template <typename TQ>
+__global__ void k_widen(int64_t n, const TQ *src, double *dst) {
+    int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = tid; i < n; i += stride) dst[i] = (double)src[i];
+}
+
+// ---------------------------------------------------------------- 1. gather
+template <typename TQ>
+__global__ void __launch_bounds__(256)
+k_gather(int p, int cpr, int64_t m, int64_t nnz, const int64_t *rowptr, const int32_t *col,
+         const double *val, const double *C, const TQ *CQ, const double *xhat,
+         double *partial, const int *status) {
+    if (status[kStInit] != 0) return;
+    const int a = blockIdx.x, ch = blockIdx.y;
+    int64_t r0 = rowptr[a], r1 = rowptr[a + 1];
+    r0 = r0 < 0 ? 0 : (r0 > nnz ? nnz : r0);
+    r1 = r1 < r0 ? r0 : (r1 > nnz ? nnz : r1);
+    const int64_t len = r1 - r0;
+    const int64_t e0 = r0 + len * ch / cpr, e1 = r0 + len * (ch + 1) / cpr;
+    double *out = partial + (int64_t(a) * cpr + ch) * (p + 1);
+    for (int b = threadIdx.x; b <= p; b += blockDim.x) {
+        double acc = 0.0;
+        for (int64_t e = e0; e < e1; ++e) {
+            int64_t c = col[e];
+            if (c < 0 || c >= m) continue;
+            double v = val[e];
+            double x = b < p ? C[c * p + b] + (double)CQ[c * p + b] : xhat[c];
+            acc += v * x;
+        }
+        out[b] = acc;
+    }
+}
+
+// ---------------------------------------------------------------- 2. reduce
+__global__ void __launch_bounds__(256)
+k_reduce_g(int p, int cpr, const double *partial, double *G, double *hvec, const int *status) {
+    if (status[kStInit] != 0) return;
+    const int a = blockIdx.x;
+    for (int b = threadIdx.x; b <= p; b += blockDim.x) {
+        double s = 0.0;
+        for (int c = 0; c < cpr; ++c) s += partial[(int64_t(a) * cpr + c) * (p + 1) + b];
+        if (b < p) G[int64_t(a) * p + b] = s;
+        else hvec[a] = s;
+    }
+}
+
+// ---------------------------------------------------------------- 3. p-space
+// 1024 threads as a 32 x 32 grid; thread (ti, tj) owns the entries (i, j)
+// with i = ti + 32 I, j = tj + 32 J, I >= J, of the lower triangle of the
+// PP x PP matrix (PP = 32 NB; rows/columns >= p are an identity block).
+template <int NB>
+__global__ void __launch_bounds__(1024)
+k_pspace(int p, const double *G, const double *rdiag, const double *y, const double *hvec,
+         double *Xbuf, double *Sinv, double *nu, int *status, double *minpiv,
+         long long *steps) {
+    constexpr int PP = NB * 32;
+    constexpr int RB = 16;                          // rows of X staged per block
+    __shared__ double colbuf[2][PP];
+    __shared__ double rowbuf[2][PP];
+    __shared__ double diagL[PP];
+    __shared__ double xrows[RB][PP];
+    const int tid = threadIdx.x, ti = tid >> 5, tj = tid & 31;
+
+    int bad = status[kStInit] != 0;
+    for (int i = tid; i < p; i += 1024)
+        if (!isfinite(y[i])) bad = 1;
+    bad = __syncthreads_or(bad);
+    if (bad) {
+        if (tid == 0) status[kStStep] = HIKF_E_INVALID;
+        return;
+    }
+    for (int i = tid; i < p; i += 1024) nu[i] = y[i] - hvec[i];
+
+    double a[NB][NB];
+#pragma unroll
+    for (int I = 0; I < NB; ++I)
+#pragma unroll
+        for (int J = 0; J <= I; ++J) {
+            const int i = ti + 32 * I, j = tj + 32 * J;
+            double v = 0.0;
+            if (i >= j) {
+                if (i < p && j < p)
+                    v = 0.5 * (G[int64_t(i) * p + j] + G[int64_t(j) * p + i]) + (i == j ? rdiag[i] : 0.0);
+                else
+                    v = (i == j) ? 1.0 : 0.0;
+            }
+            a[I][J] = v;
+        }
+
+    // ---- Cholesky S = L L^T, right-looking, one barrier per column
+    if (tj == 0)
+#pragma unroll
+        for (int I = 0; I < NB; ++I) colbuf[0][ti + 32 * I] = a[I][0];
+    __syncthreads();
+    double mp = 1.0e300;
+    int fail = 0;
+#pragma unroll 1
+    for (int k = 0; k < PP; ++k) {
+        const int buf = k & 1;
+        const double d2 = colbuf[buf][k];
+        if (!(d2 > 0.0) || !isfinite(d2)) { fail = 1; mp = d2; break; }
+        const double d = sqrt(d2), inv = 1.0 / d;
+        mp = fmin(mp, d);
+        double lj[NB];
+#pragma unroll
+        for (int J = 0; J < NB; ++J) {
+            const int j = tj + 32 * J;
+            lj[J] = (j > k) ? colbuf[buf][j] * inv : 0.0;
+        }
+        const int Kb = k >> 5, kt = k & 31;
+#pragma unroll
+        for (int I = 0; I < NB; ++I) {
+            const int i = ti + 32 * I;
+            const double li = (i > k) ? colbuf[buf][i] * inv : 0.0;
+#pragma unroll
+            for (int J = 0; J <= I; ++J) {
+                const int j = tj + 32 * J;
+                if (j > k && i >= j) a[I][J] -= li * lj[J];
+            }
+            if (tj == kt) {
+#pragma unroll
+                for (int J = 0; J <= I; ++J)
+                    if (J == Kb) {
+                        if (i > k) a[I][J] = li;
+                        else if (i == k) a[I][J] = d;
+                    }
+            }
+        }
+        const int k1 = k + 1;
+        if (k1 < PP && tj == (k1 & 31)) {
+            const int Kb1 = k1 >> 5;
+#pragma unroll
+            for (int I = 0; I < NB; ++I)
+#pragma unroll
+                for (int J = 0; J <= I; ++J)
+                    if (J == Kb1) {
+                        const int i = ti + 32 * I;
+                        if (i >= k1) colbuf[buf ^ 1][i] = a[I][J];
+                    }
+        }
+        __syncthreads();
+    }
+    if (fail) {
+        if (tid == 0) {
+            status[kStStep] = HIKF_E_NOT_SPD;
+            minpiv[0] = mp;
+        }
+        return;
+    }
+    if (ti == tj)
+#pragma unroll
+        for (int I = 0; I < NB; ++I) diagL[ti + 32 * I] = a[I][I];
+    __syncthreads();
+
+    // ---- X = L^{-1} in place, right-looking, one barrier per column
+    if (ti == 0 && tj == 0) {
+        a[0][0] = 1.0 / diagL[0];
+        rowbuf[0][0] = a[0][0];
+    }
+    if (tj == 0)
+#pragma unroll
+        for (int I = 0; I < NB; ++I) {
+            const int i = ti + 32 * I;
+            if (i > 0) colbuf[0][i] = a[I][0];
+        }
+    __syncthreads();
+#pragma unroll 1
+    for (int k = 0; k < PP; ++k) {
+        const int buf = k & 1;
+        double xr[NB];
+#pragma unroll
+        for (int J = 0; J < NB; ++J) {
+            const int j = tj + 32 * J;
+            xr[J] = (j <= k) ? rowbuf[buf][j] : 0.0;
+        }
+#pragma unroll
+        for (int I = 0; I < NB; ++I) {
+            const int i = ti + 32 * I;
+            if (i > k) {
+                const double lik = colbuf[buf][i];
+#pragma unroll
+                for (int J = 0; J <= I; ++J) {
+                    const int j = tj + 32 * J;
+                    if (j < k) a[I][J] -= lik * xr[J];
+                    else if (j == k) a[I][J] = -lik * xr[J];
+                }
+            }
+        }
+        const int k1 = k + 1;
+        if (k1 < PP) {
+            const int Kb1 = k1 >> 5;
+            const double dinv = 1.0 / diagL[k1];
+            if (ti == (k1 & 31)) {
+#pragma unroll
+                for (int I = 0; I < NB; ++I)
+                    if (I == Kb1) {
+#pragma unroll
+                        for (int J = 0; J <= I; ++J) {
+                            const int j = tj + 32 * J;
+                            if (j < k1) a[I][J] *= dinv;
+                            else if (j == k1) a[I][J] = dinv;
+                            if (j <= k1) rowbuf[buf ^ 1][j] = a[I][J];
+                        }
+                    }
+            }
+            if (tj == (k1 & 31)) {
+#pragma unroll
+                for (int I = 0; I < NB; ++I)
+#pragma unroll
+                    for (int J = 0; J <= I; ++J)
+                        if (J == Kb1) {
+                            const int i = ti + 32 * I;
+                            if (i > k1) colbuf[buf ^ 1][i] = a[I][J];
+                        }
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- S^{-1} = X^T X  (S^{-1}_ij = sum_k X_ki X_kj)
+#pragma unroll
+    for (int I = 0; I < NB; ++I)
+#pragma unroll
+        for (int J = 0; J <= I; ++J) {
+            const int i = ti + 32 * I, j = tj + 32 * J;
+            if (i >= j) Xbuf[int64_t(i) * PP + j] = a[I][J];
+            a[I][J] = 0.0;
+        }
+    __threadfence_block();
+    __syncthreads();
+#pragma unroll 1
+    for (int kb = 0; kb < PP; kb += RB) {
+        for (int idx = tid; idx < RB * PP; idx += 1024) {
+            const int rr = idx / PP, c = idx % PP, k = kb + rr;
+            xrows[rr][c] = (c <= k) ? Xbuf[int64_t(k) * PP + c] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int rr = 0; rr < RB; ++rr) {
+            double xj[NB];
+#pragma unroll
+            for (int J = 0; J < NB; ++J) xj[J] = xrows[rr][tj + 32 * J];
+#pragma unroll
+            for (int I = 0; I < NB; ++I) {
+                const double xi = xrows[rr][ti + 32 * I];
+#pragma unroll
+                for (int J = 0; J <= I; ++J) a[I][J] += xi * xj[J];
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int I = 0; I < NB; ++I)
+#pragma unroll
+        for (int J = 0; J <= I; ++J) {
+            const int i = ti + 32 * I, j = tj + 32 * J;
+            if (i >= j && i < p && j < p) {
+                Sinv[int64_t(i) * p + j] = a[I][J];
+                Sinv[int64_t(j) * p + i] = a[I][J];
+            }
+        }
+    if (tid == 0) {
+        status[kStStep] = HIKF_OK;
+        minpiv[0] = mp;
+        steps[0] += 1;
+    }
+}
+
+// ---------------------------------------------------------------- 4. row pass
+// 256 threads = 4 waves; wave w owns rows [64 b + 16 w, +16) and all P = 16 NT
+// columns.  K = (C + C_Q) S^{-1} on v_mfma_f64_16x16x4: lane l supplies
+// A[l%16][l/16] and B[l/16][l%16] and receives D[4 (l/16) + r][l%16].  Within
+// a 16-wide k block, MFMA step s pairs lane group q with k = kb + 4 q + s so
+// that each lane reads four consecutive entries of its row.
+template <typename TQ, int NT>
+__global__ void __launch_bounds__(256)
+k_rowpass(int64_t m, double *C, const TQ *CQ, const double *Sinv, const double *nu,
+          const double *rdiag, double *xhat, double *var, double kdiag, const int *status) {
+    constexpr int P = NT * 16;
+    constexpr int LDB = P + 4;
+    __shared__ double sB[16 * LDB];
+    if (status[kStStep] != HIKF_OK) return;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, q = lane >> 4;
+    const int64_t row0 = int64_t(blockIdx.x) * 64 + wave * 16;
+    const int64_t arow = row0 + lr;
+    const bool arow_ok = arow < m;
+    d4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int kb = 0; kb < P; kb += 16) {
+        for (int idx = tid; idx < 16 * P; idx += 256) {
+            const int rr = idx / P, c = idx % P;
+            sB[rr * LDB + c] = Sinv[int64_t(kb + rr) * P + c];
+        }
+        double av[4] = {0.0, 0.0, 0.0, 0.0};
+        if (arow_ok) {
+            const double *cr = C + arow * P + kb + 4 * q;
+            const TQ *qr = CQ + arow * P + kb + 4 * q;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) av[s] = cr[s] + (double)qr[s];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const double bv = sB[(4 * q + s) * LDB + 16 * t + lr];
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv, acc[t], 0, 0, 0);
+            }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        const int64_t row = row0 + 4 * q + rr;
+        const bool ok = row < m;
+        double dv = 0.0, dx = 0.0;
+        if (ok) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int c = 16 * t + lr;
+                const double kv = acc[t][rr];
+                const double cp = C[row * P + c] + (double)CQ[row * P + c];
+                dv += kv * cp;
+                dx += kv * nu[c];
+            }
+        }
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+            dv += __shfl_xor(dv, off, 64);
+            dx += __shfl_xor(dx, off, 64);
+        }
+        if (ok) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int c = 16 * t + lr;
+                C[row * P + c] = acc[t][rr] * rdiag[c];
+            }
+            if (lr == 0) {
+                var[row] = var[row] + kdiag - dv;
+                xhat[row] += dx;
+            }
+        }
+    }
+}
+
+template <typename TQ, int NT>
+void launch_rowpass_nt(const Geometry &g, const Layout &lay, char *res, hipStream_t s) {
+    const unsigned blocks = unsigned((g.m + 63) / 64);
+    hipLaunchKernelGGL((k_rowpass<TQ, NT>), dim3(blocks), dim3(256), 0, s, g.m,
+                       reinterpret_cast<double *>(res + lay.C),
+                       reinterpret_cast<const TQ *>(res + lay.CQ),
+                       reinterpret_cast<const double *>(res + lay.sinv),
+                       reinterpret_cast<const double *>(res + lay.nu),
+                       reinterpret_cast<const double *>(res + lay.rdiag),
+                       reinterpret_cast<double *>(res + lay.xhat),
+                       reinterpret_cast<double *>(res + lay.var), g.kp.family == HIKF_KERNEL_TEST_R2 ? 0.0 : g.kp.theta,
+                       reinterpret_cast<const int *>(res + lay.status));
+}
+
+template <typename TQ>
+void launch_rowpass(const Geometry &g, const Layout &lay, char *res, hipStream_t s) {
+    switch (g.p / 16) {
+#define HIKF_NT(N) case N: launch_rowpass_nt<TQ, N>(g, lay, res, s); break;
+        HIKF_NT(1) HIKF_NT(2) HIKF_NT(3) HIKF_NT(4) HIKF_NT(5) HIKF_NT(6) HIKF_NT(7) HIKF_NT(8)
+        HIKF_NT(9) HIKF_NT(10) HIKF_NT(11) HIKF_NT(12) HIKF_NT(13) HIKF_NT(14) HIKF_NT(15)
+        HIKF_NT(16)
+#undef HIKF_NT
+        default: break;
+    }
+}
+
+template <int NB>
+void launch_pspace_nb(const Geometry &g, const Layout &lay, char *res, const double *y,
+                      hipStream_t s) {
+    hipLaunchKernelGGL((k_pspace<NB>), dim3(1), dim3(1024), 0, s, g.p,
+                       reinterpret_cast<const double *>(res + lay.G),
+                       reinterpret_cast<const double *>(res + lay.rdiag), y,
+                       reinterpret_cast<const double *>(res + lay.hvec),
+                       reinterpret_cast<double *>(res + lay.xbuf),
+                       reinterpret_cast<double *>(res + lay.sinv),
+                       reinterpret_cast<double *>(res + lay.nu),
+                       reinterpret_cast<int *>(res + lay.status),
+                       reinterpret_cast<double *>(res + lay.minpiv),
+                       reinterpret_cast<long long *>(res + lay.steps));
+}
+
+template <typename TQ>
+hipError_t run_step(const Geometry &g, const Layout &lay, char *res, const double *y,
+                    hipStream_t s, Timing *tm) {
+    const int p = g.p;
+    tbegin(tm, HIKF_PHASE_GATHER, s);
+    hipLaunchKernelGGL(k_gather<TQ>, dim3(p, g.cpr), dim3(256), 0, s, p, g.cpr, g.m, g.nnz,
+                       reinterpret_cast<const int64_t *>(res + lay.rowptr),
+                       reinterpret_cast<const int32_t *>(res + lay.col),
+                       reinterpret_cast<const double *>(res + lay.val),
+                       reinterpret_cast<const double *>(res + lay.C),
+                       reinterpret_cast<const TQ *>(res + lay.CQ),
+                       reinterpret_cast<const double *>(res + lay.xhat),
+                       reinterpret_cast<double *>(res + lay.partial),
+                       reinterpret_cast<const int *>(res + lay.status));
+    tend(tm, HIKF_PHASE_GATHER, s);
+    tbegin(tm, HIKF_PHASE_REDUCE, s);
+    hipLaunchKernelGGL(k_reduce_g, dim3(p), dim3(256), 0, s, p, g.cpr,
+                       reinterpret_cast<const double *>(res + lay.partial),
+                       reinterpret_cast<double *>(res + lay.G),
+                       reinterpret_cast<double *>(res + lay.hvec),
+                       reinterpret_cast<const int *>(res + lay.status));
+    tend(tm, HIKF_PHASE_REDUCE, s);
+    tbegin(tm, HIKF_PHASE_PSPACE, s);
+    switch (g.pp / 32) {
+        case 1: launch_pspace_nb<1>(g, lay, res, y, s); break;
+        case 2: launch_pspace_nb<2>(g, lay, res, y, s); break;
+        case 3: launch_pspace_nb<3>(g, lay, res, y, s); break;
+        case 4: launch_pspace_nb<4>(g, lay, res, y, s); break;
+        case 5: launch_pspace_nb<5>(g, lay, res, y, s); break;
+        case 6: launch_pspace_nb<6>(g, lay, res, y, s); break;
+        case 7: launch_pspace_nb<7>(g, lay, res, y, s); break;
+        case 8: launch_pspace_nb<8>(g, lay, res, y, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    tend(tm, HIKF_PHASE_PSPACE, s);
+    tbegin(tm, HIKF_PHASE_ROWPASS, s);
+    launch_rowpass<TQ>(g, lay, res, s);
+    tend(tm, HIKF_PHASE_ROWPASS, s);
+    return hipGetLastError();
+}
+
+unsigned grid_for(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    if (b > 65536) b = 65536;
+    if (b < 1) b = 1;
+    return unsigned(b);
+}
+
+}  // namespace
+
+hipError_t launch_validate(const Geometry &g, const Layout &lay, char *res, const double *x0,
+                           hipStream_t s) {
+    int64_t n = g.nnz > g.m ? g.nnz : g.m;
+    if (n < g.p + 1) n = g.p + 1;
+    hipLaunchKernelGGL(k_validate, dim3(grid_for(n)), dim3(256), 0, s, g.p, g.nnz, g.m,
+                       reinterpret_cast<const int64_t *>(res + lay.rowptr),
+                       reinterpret_cast<const int32_t *>(res + lay.col),
+                       reinterpret_cast<const double *>(res + lay.val),
+                       reinterpret_cast<const double *>(res + lay.rdiag), x0,
+                       reinterpret_cast<int *>(res + lay.status));
+    return hipGetLastError();
+}
+
+hipError_t launch_init_state(const Geometry &g, const Layout &lay, char *res, const double *x0,
+                             hipStream_t s) {
+    const double kdiag = g.kp.family == HIKF_KERNEL_TEST_R2 ? 0.0 : g.kp.theta;
+    const unsigned grid = grid_for(g.m * g.p);
+    if (g.fmm_prec == HIKF_FMM_F64)
+        hipLaunchKernelGGL(k_init_state<double>, dim3(grid), dim3(256), 0, s, g.m, g.p, g.prior,
+                           g.alpha, kdiag, reinterpret_cast<const double *>(res + lay.CQ), x0,
+                           reinterpret_cast<double *>(res + lay.C),
+                           reinterpret_cast<double *>(res + lay.xhat),
+                           reinterpret_cast<double *>(res + lay.var));
+    else
+        hipLaunchKernelGGL(k_init_state<float>, dim3(grid), dim3(256), 0, s, g.m, g.p, g.prior,
+                           g.alpha, kdiag, reinterpret_cast<const float *>(res + lay.CQ), x0,
+                           reinterpret_cast<double *>(res + lay.C),
+                           reinterpret_cast<double *>(res + lay.xhat),
+                           reinterpret_cast<double *>(res + lay.var));
+    if (g.prior == HIKF_PRIOR_SCALED_I && g.nnz > 0)
+        hipLaunchKernelGGL(k_scatter_c, dim3(unsigned((g.nnz + 255) / 256)), dim3(256), 0, s,
+                           g.nnz, g.p, g.m, g.alpha,
+                           reinterpret_cast<const int64_t *>(res + lay.rowptr),
+                           reinterpret_cast<const int32_t *>(res + lay.col),
+                           reinterpret_cast<const double *>(res + lay.val),
+                           reinterpret_cast<double *>(res + lay.C));
+    return hipGetLastError();
+}
+
+hipError_t launch_step(const Geometry &g, const Layout &lay, char *res, const double *y,
+                       hipStream_t s, Timing *t) {
+    if (g.fmm_prec == HIKF_FMM_F64) return run_step<double>(g, lay, res, y, s, t);
+    return run_step<float>(g, lay, res, y, s, t);
+}
+
+hipError_t launch_widen_cq(const Geometry &g, const Layout &lay, char *res, double *out,
+                           hipStream_t s) {
+    const int64_t n = g.m * g.p;
+    if (g.fmm_prec == HIKF_FMM_F64)
+        hipLaunchKernelGGL(k_widen<double>, dim3(grid_for(n)), dim3(256), 0, s, n,
+                           reinterpret_cast<const double *>(res + lay.CQ), out);
+    else
+        hipLaunchKernelGGL(k_widen<float>, dim3(grid_for(n)), dim3(256), 0, s, n,
+                           reinterpret_cast<const float *>(res + lay.CQ), out);
+    return hipGetLastError();
+}
+
+}  // namespace hikf

@@ -1,0 +1,138 @@
+"""A filter handle whose device memory is owned by torch.
+
+Marshalling only: tensors are allocated with torch on the current CUDA (HIP)
+device, their pointers and the current stream are handed to libhikf.so, and
+every computation runs there.
+"""
+
+import ctypes
+
+import torch
+
+from . import hikf as H
+
+PRECISIONS = {"f32": H.HIKF_FMM_F32, "f64": H.HIKF_FMM_F64}
+PRIORS = {"zero": H.HIKF_PRIOR_ZERO, "scaled_i": H.HIKF_PRIOR_SCALED_I,
+          "kernel": H.HIKF_PRIOR_KERNEL}
+FAMILIES = {"powexp": H.HIKF_KERNEL_POWEXP, "r2": H.HIKF_KERNEL_TEST_R2}
+
+
+def _stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def problem_from_csr(dim, n, rowptr, col, val, r_diag, family="powexp", theta=1.0,
+                     ell=1.0, gamma=1.0, prior="kernel", alpha=0.0, x0=None,
+                     device="cuda"):
+    """Device copies of the problem arrays plus the hikf_problem struct.
+
+    Returns (problem, keepalive) where keepalive holds the tensors the struct
+    points to.
+    """
+    t_rowptr = torch.as_tensor(rowptr, dtype=torch.int64).to(device).contiguous()
+    t_col = torch.as_tensor(col, dtype=torch.int32).to(device).contiguous()
+    t_val = torch.as_tensor(val, dtype=torch.float64).to(device).contiguous()
+    t_r = torch.as_tensor(r_diag, dtype=torch.float64).to(device).contiguous()
+    t_x0 = None if x0 is None else torch.as_tensor(x0, dtype=torch.float64).to(device).contiguous()
+    pr = H.hikf_problem()
+    pr.dim, pr.n = int(dim), int(n)
+    pr.kernel_family = FAMILIES[family]
+    pr.prior_kind = PRIORS[prior]
+    pr.theta, pr.ell, pr.gamma, pr.alpha = float(theta), float(ell), float(gamma), float(alpha)
+    pr.p = int(len(t_rowptr) - 1)
+    pr.nnz = int(t_col.numel())
+    pr.h_rowptr_dev = t_rowptr.data_ptr()
+    pr.h_col_dev = t_col.data_ptr() if t_col.numel() else None
+    pr.h_val_dev = t_val.data_ptr() if t_val.numel() else None
+    pr.r_diag_dev = t_r.data_ptr()
+    pr.x0_dev = None if t_x0 is None else t_x0.data_ptr()
+    return pr, (t_rowptr, t_col, t_val, t_r, t_x0)
+
+
+def make_options(n_c=4, precision="f32", direct=False, timing=False):
+    op = H.hikf_options()
+    op.n_c = int(n_c)
+    op.fmm_precision = PRECISIONS[precision]
+    op.direct = 1 if direct else 0
+    op.timing = 1 if timing else 0
+    return op
+
+
+def plan(problem, options):
+    info = H.hikf_plan_info()
+    H.check(H.hikf_plan(ctypes.byref(problem), ctypes.byref(options), ctypes.byref(info)),
+            "hikf_plan")
+    return info
+
+
+class HikfFilter:
+    """Owns the resident (and, until released, scratch) workspace of one filter."""
+
+    def __init__(self, problem, options, keepalive=(), device="cuda", stream=None,
+                 keep_scratch=False):
+        self.problem, self.options = problem, options
+        self.info = plan(problem, options)
+        self.m = int(self.info.m)
+        self.p = int(problem.p)
+        self.resident = torch.empty(int(self.info.resident_bytes), dtype=torch.uint8, device=device)
+        self.scratch = torch.empty(int(self.info.scratch_bytes), dtype=torch.uint8, device=device)
+        self._keep = keepalive
+        self.handle = ctypes.c_void_p()
+        st = H.hikf_init(ctypes.byref(problem), ctypes.byref(options),
+                         ctypes.c_void_p(self.resident.data_ptr()), self.info.resident_bytes,
+                         ctypes.c_void_p(self.scratch.data_ptr()), self.info.scratch_bytes,
+                         _stream_handle(stream), ctypes.byref(self.handle))
+        H.check(st, "hikf_init")
+        if not keep_scratch:
+            # the scratch region may be reused once init's work has finished;
+            # torch's allocator orders the reuse on this stream
+            self.scratch = None
+
+    def step(self, y, x_out=None, var_out=None, stream=None):
+        """Queue one assimilation step with measurement y (p doubles on the device)."""
+        y = y.contiguous()
+        assert y.dtype == torch.float64 and y.numel() == self.p and y.is_cuda
+        st = H.hikf_step(self.handle, ctypes.c_void_p(y.data_ptr()),
+                         ctypes.c_void_p(x_out.data_ptr() if x_out is not None else None),
+                         ctypes.c_void_p(var_out.data_ptr() if var_out is not None else None),
+                         _stream_handle(stream))
+        H.check(st, "hikf_step", self.handle)
+
+    def query(self):
+        stats = H.hikf_stats()
+        H.check(H.hikf_query(self.handle, ctypes.byref(stats)), "hikf_query", self.handle)
+        return stats
+
+    def export_state(self, stream=None):
+        dev = self.resident.device
+        x = torch.empty(self.m, dtype=torch.float64, device=dev)
+        v = torch.empty(self.m, dtype=torch.float64, device=dev)
+        c = torch.empty(self.m, self.p, dtype=torch.float64, device=dev)
+        H.check(H.hikf_export_state(self.handle, ctypes.c_void_p(x.data_ptr()),
+                                    ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(c.data_ptr()),
+                                    _stream_handle(stream)), "hikf_export_state", self.handle)
+        return x, v, c
+
+    def import_state(self, x=None, var=None, c=None, stream=None):
+        ptr = (lambda t: ctypes.c_void_p(t.contiguous().data_ptr()) if t is not None
+               else ctypes.c_void_p(None))
+        H.check(H.hikf_import_state(self.handle, ptr(x), ptr(var), ptr(c), _stream_handle(stream)),
+                "hikf_import_state", self.handle)
+
+    def export_cq(self, stream=None):
+        out = torch.empty(self.m, self.p, dtype=torch.float64, device=self.resident.device)
+        H.check(H.hikf_export_cq(self.handle, ctypes.c_void_p(out.data_ptr()),
+                                 _stream_handle(stream)), "hikf_export_cq", self.handle)
+        return out
+
+    def close(self):
+        if self.handle:
+            H.hikf_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -41,15 +41,18 @@ def normal_draws(seed: int, *shape) -> np.ndarray:
     return np.random.default_rng(seed).standard_normal(shape)
 
 
-def plume_truth(dim: int, n: int, steps: int, amplitude: float = 1.0):
+def plume_truth(dim: int, n: int, steps: int, amplitude: float = 1.0, cells=None):
     """(steps, m) slowness perturbations of a plume spreading from x = 0.
 
     A stand-in for the paper's CO2 plume (Sec. 4.1, which is not public): a
     smooth bump attached to the injection well at mid depth whose lateral
     and vertical extents grow like sqrt(k).  Row k-1 is the state at step k.
+    With ``cells`` (grid indices) only those columns are produced.
     """
     pts = cell_centres(dim, n)
-    out = np.empty((steps, grid_size(dim, n)))
+    if cells is not None:
+        pts = pts[np.asarray(cells)]
+    out = np.empty((steps, pts.shape[0]))
     depth = pts[:, dim - 1]
     for k in range(1, steps + 1):
         frac = np.sqrt(k / steps)
@@ -77,3 +80,11 @@ def observations(rowptr, col, val, truth, r_var, seed: int):
         hx = np.bincount(rows, weights=val * truth[k, col], minlength=p)
         y[k] = hx + np.sqrt(r_var) * eps[k]
     return y
+
+
+def plume_observations(dim, n, rowptr, col, val, steps, r_var, seed: int):
+    """``observations`` of ``plume_truth`` evaluated only at the ray cells,
+    for grids where a dense (steps, m) truth would be wasteful."""
+    cells, inv = np.unique(np.asarray(col), return_inverse=True)
+    truth = plume_truth(dim, n, steps, cells=cells)
+    return observations(rowptr, inv, val, truth, r_var, seed)

@@ -1,0 +1,101 @@
+"""Shared set-up for the GPU parity tests: problem construction from the
+seeded generators, the GPU filter run, and the oracle references."""
+
+import numpy as np
+
+import synth
+from oracle import bbfmm, cq_exact, kernels, kf_crosscov, kf_dense
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def max_step_rel(a, b):
+    return max(rel(a[k], b[k]) for k in range(len(b)))
+
+
+class Case:
+    """A seeded crosswell problem: grid, rays, kernel, R, measurements."""
+
+    def __init__(self, dim, n, p, ell=0.3, gamma=1.0, theta=1.0, family="powexp",
+                 r_var=1e-4, steps=3, seed=0, planes=2, prior="kernel", alpha=0.0):
+        self.dim, self.n, self.p = dim, n, p
+        self.m = n ** dim
+        self.ell, self.gamma, self.theta, self.family = ell, gamma, theta, family
+        self.r_var, self.steps, self.seed = r_var, steps, seed
+        self.prior, self.alpha = prior, alpha
+        self.rowptr, self.col, self.val = synth.crosswell_h(dim, n, p, planes=planes)
+        self.r_diag = np.full(p, r_var)
+        truth = synth.plume_truth(dim, n, steps)
+        self.ys = synth.observations(self.rowptr, self.col, self.val, truth, r_var, seed + 1)
+        self.x0 = None
+
+    def kparams(self):
+        return dict(family=self.family, theta=self.theta, ell=self.ell, gamma=self.gamma)
+
+    def h_dense(self):
+        return cq_exact.h_dense(self.rowptr, self.col, self.val, self.m)
+
+    def cq_exact(self):
+        Ht = self.h_dense().T
+        if self.m <= 4096:
+            return cq_exact.cq_dense(synth.cell_centres(self.dim, self.n), Ht, **self.kparams())
+        return cq_exact.cq_fft(self.dim, self.n, Ht, **self.kparams())
+
+    def cq_bbfmm(self, n_c):
+        return bbfmm.bbfmm_apply(self.dim, self.n, self.h_dense().T, n_c, None, **self.kparams())
+
+    def prior_arrays(self, CQ):
+        if self.prior == "kernel":
+            return CQ.copy(), np.full(self.m, kernels.diag_value(**self.kparams()))
+        if self.prior == "scaled_i":
+            return self.alpha * self.h_dense().T, np.full(self.m, self.alpha)
+        return np.zeros((self.m, self.p)), np.zeros(self.m)
+
+    def tier_b(self, CQ, steps=None):
+        steps = self.steps if steps is None else steps
+        C0, v0 = self.prior_arrays(CQ)
+        x0 = np.zeros(self.m) if self.x0 is None else self.x0
+        return kf_crosscov.crosscov_kf(CQ, self.h_dense(), np.diag(self.r_diag), x0, C0, v0,
+                                       kernels.diag_value(**self.kparams()), self.ys[:steps])
+
+    def tier_a(self, steps=None):
+        steps = self.steps if steps is None else steps
+        Q = kernels.dense_q(synth.cell_centres(self.dim, self.n), **self.kparams())
+        if self.prior == "kernel":
+            P0 = Q
+        elif self.prior == "scaled_i":
+            P0 = self.alpha * np.eye(self.m)
+        else:
+            P0 = np.zeros((self.m, self.m))
+        x0 = np.zeros(self.m) if self.x0 is None else self.x0
+        xs, vs, _ = kf_dense.dense_kf(Q, self.h_dense(), np.diag(self.r_diag), x0, P0,
+                                      self.ys[:steps])
+        return xs, vs
+
+    # ---- GPU side
+    def gpu_filter(self, n_c=4, precision="f32", direct=False):
+        from paper_1404_3816_amd import filter as F
+        pr, keep = F.problem_from_csr(self.dim, self.n, self.rowptr, self.col, self.val,
+                                      self.r_diag, prior=self.prior, alpha=self.alpha,
+                                      x0=self.x0, **self.kparams())
+        return F.HikfFilter(pr, F.make_options(n_c, precision, direct), keep)
+
+    def gpu_run(self, n_c=4, precision="f32", direct=False, steps=None):
+        import torch
+        steps = self.steps if steps is None else steps
+        f = self.gpu_filter(n_c, precision, direct)
+        cq = f.export_cq().cpu().numpy()
+        xs, vs = [], []
+        ydev = torch.as_tensor(self.ys, dtype=torch.float64, device="cuda")
+        x = torch.empty(self.m, dtype=torch.float64, device="cuda")
+        v = torch.empty(self.m, dtype=torch.float64, device="cuda")
+        for k in range(steps):
+            f.step(ydev[k], x, v)
+            xs.append(x.cpu().numpy().copy())
+            vs.append(v.cpu().numpy().copy())
+        stats = f.query()
+        f.close()
+        return cq, np.array(xs), np.array(vs), stats

@@ -1,0 +1,116 @@
+"""Host-side checks of the C ABI (no GPU calls).
+
+The library must load, export every function include/hikf.h declares, and
+hikf_plan (host only) must validate shapes and report the tree it will build.
+"""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import synth
+from oracle import bbfmm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "hikf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hikf_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1404_3816_amd import hikf as H
+    lib = ctypes.CDLL(H.LIB_PATH)
+    declared = _declared_functions()
+    assert "hikf_init" in declared and "hikf_step" in declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(H.EXPORTED) == declared
+
+
+def _problem(dim=2, n=32, p=16, nnz=100, **kw):
+    from paper_1404_3816_amd import hikf as H
+    pr = H.hikf_problem()
+    pr.dim, pr.n, pr.p, pr.nnz = dim, n, p, nnz
+    pr.kernel_family = kw.get("family", H.HIKF_KERNEL_POWEXP)
+    pr.prior_kind = kw.get("prior", H.HIKF_PRIOR_KERNEL)
+    pr.theta, pr.ell, pr.gamma = kw.get("theta", 1.0), kw.get("ell", 0.3), kw.get("gamma", 1.0)
+    pr.alpha = kw.get("alpha", 0.0)
+    fake = 256  # any non-NULL value; hikf_plan never dereferences them
+    pr.h_rowptr_dev = pr.h_col_dev = pr.h_val_dev = pr.r_diag_dev = fake
+    pr.x0_dev = None
+    return pr
+
+
+def _plan(pr, n_c=4, precision=0, direct=0):
+    from paper_1404_3816_amd import hikf as H
+    op = H.hikf_options()
+    op.n_c, op.fmm_precision, op.direct = n_c, precision, direct
+    info = H.hikf_plan_info()
+    st = H.hikf_plan(ctypes.byref(pr), ctypes.byref(op), ctypes.byref(info))
+    return st, info
+
+
+@pytest.mark.parametrize("dim,n", [(2, 32), (2, 256), (2, 1024), (3, 128), (3, 16)])
+def test_plan_tree_counts_match_oracle(dim, n):
+    from paper_1404_3816_amd import hikf as H
+    st, info = _plan(_problem(dim=dim, n=n, p=64))
+    assert st == H.HIKF_OK
+    leaf = 8 if dim == 2 else 4
+    near, far = bbfmm.interaction_counts(dim, n, leaf)
+    assert info.near_pairs == near
+    assert info.far_pairs == far
+    assert info.m == n ** dim
+    assert info.r == 4 ** dim
+    # resident state holds at least C (FP64) and C_Q (FP32): 12 m p bytes
+    assert info.resident_bytes >= 12 * info.m * 64
+
+
+def test_plan_rejects_bad_input():
+    from paper_1404_3816_amd import hikf as H
+    assert _plan(_problem(dim=4))[0] == H.HIKF_E_INVALID
+    assert _plan(_problem(theta=0.0))[0] == H.HIKF_E_INVALID
+    assert _plan(_problem(ell=-1.0))[0] == H.HIKF_E_INVALID
+    assert _plan(_problem(gamma=2.5))[0] == H.HIKF_E_INVALID
+    assert _plan(_problem(), n_c=0)[0] == H.HIKF_E_INVALID
+    assert _plan(_problem(), n_c=9)[0] == H.HIKF_E_INVALID
+    assert _plan(_problem(), precision=7)[0] == H.HIKF_E_INVALID
+    assert _plan(_problem(p=0))[0] == H.HIKF_E_INVALID
+    assert _plan(_problem(nnz=-1))[0] == H.HIKF_E_INVALID
+    assert _plan(_problem(prior=9))[0] == H.HIKF_E_INVALID
+    pr = _problem()
+    pr.h_rowptr_dev = None
+    assert _plan(pr)[0] == H.HIKF_E_INVALID
+
+
+def test_plan_reports_unsupported_shapes():
+    from paper_1404_3816_amd import hikf as H
+    assert _plan(_problem(n=33))[0] == H.HIKF_E_UNSUPPORTED      # not 8 * 2^k
+    assert _plan(_problem(n=24))[0] == H.HIKF_E_UNSUPPORTED
+    assert _plan(_problem(p=20))[0] == H.HIKF_E_UNSUPPORTED      # not a multiple of 16
+    assert _plan(_problem(p=512))[0] == H.HIKF_E_UNSUPPORTED     # above 256
+    assert _plan(_problem(dim=3, n=16), n_c=6)[0] == H.HIKF_E_UNSUPPORTED  # r > 128
+
+
+def test_plan_direct_mode_has_no_far_field():
+    from paper_1404_3816_amd import hikf as H
+    st, info = _plan(_problem(n=32), direct=1)
+    assert st == H.HIKF_OK
+    assert info.far_pairs == 0
+    assert info.near_pairs == 16 * 16
+
+
+def test_status_strings():
+    from paper_1404_3816_amd import hikf as H
+    for s in range(6):
+        assert H.hikf_status_string(s)
+    assert H.hikf_last_error(None) == b""
+
+
+def test_ray_operator_fits_abi_layout():
+    rp, col, val = synth.crosswell_h(2, 32, 16)
+    assert rp.dtype.name == "int64" and col.dtype.name == "int32" and val.dtype.name == "float64"

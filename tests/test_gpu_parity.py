@@ -1,0 +1,249 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances (derivations in DESIGN.md, "Parity tolerances"):
+* FP64 FMM vs the FP64 oracle bbFMM: rounding only, 1e-12 normwise.
+* FP32 FMM vs the FP64 oracle bbFMM: FP32 operands and accumulation over at
+  most ~2000 terms, 2e-6 normwise and |d| <= 1e-5 |ref| + 2e-6 max|ref|
+  elementwise.
+* Filter outputs: the x_hat and diag P of the FP64 step inherit the error of
+  C_Q amplified by the Kalman gain; the tolerance is set from the oracle's
+  own response to the same C_Q perturbation (see ``_fp32_tolerances``).
+"""
+
+import numpy as np
+import pytest
+
+from helpers import Case, max_step_rel, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1404_3816_amd  # noqa: F401  (fails loudly without libhikf.so)
+
+
+def _elementwise_ok(gpu, ref, rtol, atol_rel):
+    return np.all(np.abs(gpu - ref) <= rtol * np.abs(ref) + atol_rel * np.abs(ref).max())
+
+
+# ------------------------------------------------------------------ C_Q
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-13), ("f32", 3e-7)])
+def test_cq_direct_is_exact(precision, tol):
+    case = Case(2, 32, 16, ell=0.3, gamma=1.0, steps=1)
+    f = case.gpu_filter(precision=precision, direct=True)
+    cq = f.export_cq().cpu().numpy()
+    f.close()
+    assert rel(cq, case.cq_exact()) < tol
+
+
+@pytest.mark.parametrize("dim,n,p,n_c,ell,gamma", [
+    (2, 32, 16, 4, 0.3, 1.0),      # depth 2: M2L only at the leaves
+    (2, 64, 32, 4, 0.1, 1.0),      # depth 3
+    (2, 128, 48, 5, 0.05, 2.0),    # depth 4, Gaussian, padded p-space (48 -> 64)
+    (3, 16, 16, 3, 0.2, 1.0),      # octree depth 2
+    (3, 32, 32, 4, 0.2, 1.0),      # octree depth 3
+])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_cq_fmm_matches_oracle_bbfmm(dim, n, p, n_c, ell, gamma, precision):
+    case = Case(dim, n, p, ell=ell, gamma=gamma, steps=1)
+    f = case.gpu_filter(n_c=n_c, precision=precision)
+    cq = f.export_cq().cpu().numpy()
+    f.close()
+    ref = case.cq_bbfmm(n_c)
+    if precision == "f64":
+        assert rel(cq, ref) < 1e-12
+    else:
+        assert rel(cq, ref) < 2e-6
+        assert _elementwise_ok(cq, ref, 1e-5, 2e-6)
+
+
+@pytest.mark.parametrize("dim,n,n_c", [(2, 64, 3), (2, 64, 4), (3, 16, 3)])
+def test_cq_polynomial_kernel_exact(dim, n, n_c):
+    # Chebyshev interpolation reproduces K = r^2 exactly for n_c >= 3, so the
+    # whole tree must give the dense product (catches operator/list errors).
+    case = Case(dim, n, 16, family="r2", steps=1)
+    f = case.gpu_filter(n_c=n_c, precision="f64")
+    cq = f.export_cq().cpu().numpy()
+    f.close()
+    assert rel(cq, case.cq_exact()) < 1e-12
+
+
+@pytest.mark.parametrize("dim,n", [(2, 8), (2, 16), (3, 4), (3, 8)])
+def test_cq_shallow_trees(dim, n):
+    # depth 0 and 1: near field only (every leaf is adjacent to every other)
+    case = Case(dim, n, 16, ell=0.3, steps=1)
+    f = case.gpu_filter(n_c=4, precision="f64")
+    cq = f.export_cq().cpu().numpy()
+    f.close()
+    assert rel(cq, case.cq_exact()) < 1e-13
+
+
+# ------------------------------------------------------------------ steps
+def test_steps_direct_f64_match_dense_kf():
+    case = Case(2, 32, 16, ell=0.3, gamma=1.0, steps=6)
+    _, xs, vs, stats = case.gpu_run(precision="f64", direct=True)
+    xa, va = case.tier_a()
+    assert stats.last_status == 0 and stats.steps_applied == 6
+    assert max_step_rel(xs, xa) < 1e-10
+    assert max_step_rel(vs, va) < 1e-10
+
+
+def _fp32_tolerances(case, cq_exact, cq_gpu):
+    """Oracle sensitivity: rerun tier B with C_Q perturbed the way the GPU's
+    C_Q differs from the exact one, and allow 4x that response."""
+    xe, ve = case.tier_b(cq_exact)
+    xp, vp = case.tier_b(cq_gpu)
+    return 4 * max(max_step_rel(xp, xe), 1e-9), 4 * max(max_step_rel(vp, ve), 1e-10)
+
+
+def test_steps_direct_f32_match_dense_kf():
+    case = Case(2, 32, 16, ell=0.3, gamma=1.0, steps=6)
+    cq, xs, vs, stats = case.gpu_run(precision="f32", direct=True)
+    xa, va = case.tier_a()
+    ex, ev = max_step_rel(xs, xa), max_step_rel(vs, va)
+    print(f"direct FP32: x err {ex:.3e} var err {ev:.3e}")
+    assert stats.last_status == 0
+    # spec target for the FP32 path: 1e-6 relative (no H^2 error here)
+    assert ev < 1e-6
+    tx, tv = _fp32_tolerances(case, case.cq_exact(), cq)
+    assert ex < tx and ev < tv
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("n,p,n_c,ell,gamma", [(32, 16, 4, 0.3, 1.0), (64, 32, 5, 0.1, 2.0)])
+def test_steps_fmm_match_oracle(precision, n, p, n_c, ell, gamma):
+    case = Case(2, n, p, ell=ell, gamma=gamma, steps=4)
+    cq, xs, vs, stats = case.gpu_run(n_c=n_c, precision=precision)
+    ref_cq = case.cq_bbfmm(n_c)
+    xb, vb = case.tier_b(ref_cq)
+    assert stats.last_status == 0 and stats.steps_applied == 4
+    ex, ev = max_step_rel(xs, xb), max_step_rel(vs, vb)
+    print(f"{precision} n={n}: x err {ex:.3e} var err {ev:.3e} vs tier B on bbFMM C_Q")
+    if precision == "f64":
+        assert ex < 1e-9 and ev < 1e-10
+    else:
+        tx, tv = _fp32_tolerances(case, ref_cq, cq)
+        assert ex < tx and ev < tv
+
+
+@pytest.mark.parametrize("prior,alpha", [("zero", 0.0), ("scaled_i", 0.5)])
+def test_priors_match_dense_kf(prior, alpha):
+    case = Case(2, 32, 16, ell=0.3, steps=4, prior=prior, alpha=alpha)
+    _, xs, vs, stats = case.gpu_run(precision="f64", direct=True)
+    xa, va = case.tier_a()
+    assert stats.last_status == 0
+    assert max_step_rel(xs, xa) < 1e-10
+    assert max_step_rel(vs, va) < 1e-10
+
+
+def test_nonzero_prior_mean():
+    case = Case(2, 32, 16, ell=0.3, steps=3)
+    case.x0 = np.sin(np.arange(case.m) * 0.01)
+    _, xs, vs, _ = case.gpu_run(precision="f64", direct=True)
+    xa, va = case.tier_a()
+    assert max_step_rel(xs, xa) < 1e-10
+
+
+@pytest.mark.parametrize("p", [48, 256])
+def test_step_p_sizes(p):
+    # p = 48 pads the p-space to 64; p = 256 is the largest supported
+    case = Case(2, 64, p, ell=0.2, steps=2)
+    _, xs, vs, stats = case.gpu_run(n_c=4, precision="f64")
+    xb, vb = case.tier_b(case.cq_bbfmm(4), steps=2)
+    assert stats.last_status == 0
+    assert max_step_rel(xs, xb) < 1e-9
+    assert max_step_rel(vs, vb) < 1e-10
+
+
+# ------------------------------------------------------------------ failure handling
+def test_not_spd_leaves_state_untouched():
+    import torch
+    # K = r^2 is not a covariance: H Q H^T is indefinite, so the Cholesky fails
+    case = Case(2, 32, 16, family="r2", steps=1)
+    f = case.gpu_filter(n_c=4, precision="f64", direct=True)
+    x0, v0, c0 = [t.cpu().numpy() for t in f.export_state()]
+    f.step(torch.as_tensor(case.ys[0], device="cuda"))
+    st = f.query()
+    x1, v1, c1 = [t.cpu().numpy() for t in f.export_state()]
+    f.close()
+    assert st.last_status == 4 and st.steps_applied == 0
+    np.testing.assert_array_equal(x0, x1)
+    np.testing.assert_array_equal(v0, v1)
+    np.testing.assert_array_equal(c0, c1)
+
+
+def test_nan_measurement_is_rejected():
+    import torch
+    case = Case(2, 32, 16, ell=0.3, steps=2)
+    f = case.gpu_filter(precision="f64", direct=True)
+    y = torch.as_tensor(case.ys[0], device="cuda").clone()
+    y[3] = float("nan")
+    x0, _, c0 = [t.cpu().numpy() for t in f.export_state()]
+    f.step(y)
+    st = f.query()
+    assert st.last_status == 1 and st.steps_applied == 0
+    x1, _, c1 = [t.cpu().numpy() for t in f.export_state()]
+    np.testing.assert_array_equal(c0, c1)
+    f.step(torch.as_tensor(case.ys[0], device="cuda"))       # a good step still works
+    assert f.query().last_status == 0
+    f.close()
+
+
+def test_bad_column_poisons_filter():
+    import torch
+    from paper_1404_3816_amd import filter as F
+    case = Case(2, 32, 16, ell=0.3, steps=1)
+    col = case.col.copy()
+    col[5] = case.m + 7            # out of range: init must flag it, kernels skip it
+    pr, keep = F.problem_from_csr(2, 32, case.rowptr, col, case.val, case.r_diag, ell=0.3)
+    f = F.HikfFilter(pr, F.make_options(4, "f64", True), keep)
+    f.step(torch.as_tensor(case.ys[0], device="cuda"))
+    st = f.query()
+    f.close()
+    assert st.init_status == 1 and st.last_status == 1 and st.steps_applied == 0
+
+
+# ------------------------------------------------------------------ properties
+def test_determinism_and_checkpoint_roundtrip():
+    import torch
+    case = Case(2, 64, 32, ell=0.1, steps=4)
+    y = torch.as_tensor(case.ys, device="cuda")
+    fa = case.gpu_filter(n_c=4, precision="f32")
+    fb = case.gpu_filter(n_c=4, precision="f32")
+    for k in range(3):
+        fa.step(y[k])
+        fb.step(y[k])
+    xa, va, ca = fa.export_state()
+    xb, vb, cb = fb.export_state()
+    assert torch.equal(xa, xb) and torch.equal(va, vb) and torch.equal(ca, cb)
+    # resume a third filter from the checkpoint: the next step is bitwise equal
+    fc = case.gpu_filter(n_c=4, precision="f32")
+    fc.import_state(xa, va, ca)
+    fa.step(y[3])
+    fc.step(y[3])
+    x1, v1, c1 = fa.export_state()
+    x2, v2, c2 = fc.export_state()
+    assert torch.equal(x1, x2) and torch.equal(v1, v2) and torch.equal(c1, c2)
+    for f in (fa, fb, fc):
+        f.close()
+
+
+def test_h_zero_invariant():
+    # with every H entry zero: x_hat stays x_0 and var grows by K(0) per step
+    import torch
+    from paper_1404_3816_amd import filter as F
+    case = Case(2, 32, 16, ell=0.3, steps=1)
+    pr, keep = F.problem_from_csr(2, 32, case.rowptr, case.col, np.zeros_like(case.val),
+                                  case.r_diag, ell=0.3)
+    f = F.HikfFilter(pr, F.make_options(4, "f64", False), keep)
+    for k in range(5):
+        f.step(torch.zeros(16, dtype=torch.float64, device="cuda"))
+    x, v, c = [t.cpu().numpy() for t in f.export_state()]
+    f.close()
+    assert np.all(x == 0.0)
+    np.testing.assert_allclose(v, 6.0, rtol=1e-15)
+    assert np.all(c == 0.0)
