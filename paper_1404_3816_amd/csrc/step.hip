@@ -354,7 +354,8 @@ k_pspace(int p, const double *G, const double *rdiag, const double *y, const dou
 // ---------------------------------------------------------------- 4. row pass
 // 256 threads = 4 waves; wave w owns rows [64 b + 16 w, +16) and all P = 16 NT
 // columns.  K = (C + C_Q) S^{-1} on v_mfma_f64_16x16x4: lane l supplies
-// A[l%16][l/16] and B[l/16][l%16] and receives D[4 (l/16) + r][l%16].  Within
+// A[l%16][l/16] and B[l/16][l%16] and receives D[l/16 + 4 r][l%16] (the FP64
+// variant interleaves the rows, unlike the FP32 one).  Within
 // a 16-wide k block, MFMA step s pairs lane group q with k = kb + 4 q + s so
 // that each lane reads four consecutive entries of its row.
 template <typename TQ, int NT>
@@ -397,7 +398,7 @@ k_rowpass(int64_t m, double *C, const TQ *CQ, const double *Sinv, const double *
     }
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
-        const int64_t row = row0 + 4 * q + rr;
+        const int64_t row = row0 + q + 4 * rr;
         const bool ok = row < m;
         double dv = 0.0, dx = 0.0;
         if (ok) {
