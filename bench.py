@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--assim-steps", type=int, default=None,
                     help="assimilation steps per job (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0,
+    ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="approximate seconds of CPU work for the oracle sample")
     return ap.parse_args()
 
@@ -63,41 +63,40 @@ def cpu_baseline(w, assim_steps, budget):
 
     dim, n, p, m = w["dim"], w["n"], w["p"], w["m"]
     rowptr, col, val = synth.crosswell_h(dim, n, p, planes=8)
-    # exact C_Q = Q H^T by FFT on the first `cols` rays
-    cols = 2
-    t_fft = 0.0
-    while True:
+    def fft_cols(cols):
         Ht = np.zeros((m, cols))
         for a in range(cols):
             Ht[col[rowptr[a]:rowptr[a + 1]], a] = val[rowptr[a]:rowptr[a + 1]]
         t0 = time.perf_counter()
         cq_exact.cq_fft(dim, n, Ht, "powexp", w["theta"], w["ell"], w["gamma"])
-        t_fft = time.perf_counter() - t0
-        if t_fft > budget / 3 or cols >= p:
-            break
-        cols = min(p, cols * 4)
-    t_cq_full = t_fft * p / cols
-    # tier-B steps on a row subset (cost is linear in the number of rows)
-    rows = min(m, 16384)
-    rng = np.random.default_rng(0)
-    steps = 1
-    while True:
-        CQ = rng.standard_normal((rows, p)) * 1e-2
+        return time.perf_counter() - t0
+
+    def tier_b_rows(rows, steps):
+        rng = np.random.default_rng(0)
         Hs = np.zeros((p, rows))
         for a in range(p):
             Hs[a, rng.choice(rows, 8, replace=False)] = 1.0 / n
+        # Q = I on the sample keeps H C_Q positive semidefinite; the cost of
+        # the dense FP64 work does not depend on the values
+        CQ = np.ascontiguousarray(Hs.T)
         ys = rng.standard_normal((steps, p)) * 1e-2
         t0 = time.perf_counter()
         kf_crosscov.crosscov_kf(CQ, Hs, w["r_var"] * np.eye(p), np.zeros(rows), CQ,
                                 np.ones(rows), 1.0, ys)
-        t_b = time.perf_counter() - t0
-        if t_b > budget / 3 or rows >= m:
-            break
-        grow = min(4, max(2, int(budget / 3 / max(t_b, 1e-3))))
-        if rows * grow <= m and rows * grow <= 262144:
-            rows *= grow
-        else:
-            steps *= 2
+        return time.perf_counter() - t0
+
+    # exact C_Q = Q H^T by FFT (tier C) on `cols` of the p rays: a one-column
+    # probe sizes the sample to about half the budget
+    t1 = fft_cols(1)
+    cols = int(min(p, max(1, budget / 2 / max(t1, 1e-3))))
+    t_fft = fft_cols(cols) if cols > 1 else t1
+    t_cq_full = t_fft * p / cols
+    # tier-B steps on `rows` of the m rows (cost is linear in the row count)
+    probe = min(m, 8192)
+    tp = tier_b_rows(probe, 1)
+    rows = int(min(m, 262144, max(probe, probe * budget / 2 / max(tp, 1e-3))))
+    steps = 1
+    t_b = tier_b_rows(rows, steps) if rows > probe else tp
     t_step_full = t_b / steps * m / rows
     job = t_cq_full + assim_steps * t_step_full
     threads = max((d.get("num_threads", 1) for d in threadpool_info()), default=1)
