@@ -186,19 +186,22 @@ k_pspace(int p, const double *G, const double *rdiag, const double *y, const dou
         if (!(d2 > 0.0) || !isfinite(d2)) { fail = 1; mp = d2; break; }
         const double d = sqrt(d2), inv = 1.0 / d;
         mp = fmin(mp, d);
+        const int Kb = k >> 5, kt = k & 31;
+        // blocks with I < Kb or J < Kb are final: skip them (Kb is uniform)
         double lj[NB];
 #pragma unroll
         for (int J = 0; J < NB; ++J) {
             const int j = tj + 32 * J;
-            lj[J] = (j > k) ? colbuf[buf][j] * inv : 0.0;
+            lj[J] = (J >= Kb && j > k) ? colbuf[buf][j] * inv : 0.0;
         }
-        const int Kb = k >> 5, kt = k & 31;
 #pragma unroll
         for (int I = 0; I < NB; ++I) {
+            if (I < Kb) continue;
             const int i = ti + 32 * I;
             const double li = (i > k) ? colbuf[buf][i] * inv : 0.0;
 #pragma unroll
             for (int J = 0; J <= I; ++J) {
+                if (J < Kb) continue;
                 const int j = tj + 32 * J;
                 if (j > k && i >= j) a[I][J] -= li * lj[J];
             }
@@ -252,19 +255,23 @@ k_pspace(int p, const double *G, const double *rdiag, const double *y, const dou
 #pragma unroll 1
     for (int k = 0; k < PP; ++k) {
         const int buf = k & 1;
+        const int Kb = k >> 5;
+        // only rows I >= Kb and columns J <= Kb change (Kb is uniform)
         double xr[NB];
 #pragma unroll
         for (int J = 0; J < NB; ++J) {
             const int j = tj + 32 * J;
-            xr[J] = (j <= k) ? rowbuf[buf][j] : 0.0;
+            xr[J] = (J <= Kb && j <= k) ? rowbuf[buf][j] : 0.0;
         }
 #pragma unroll
         for (int I = 0; I < NB; ++I) {
+            if (I < Kb) continue;
             const int i = ti + 32 * I;
             if (i > k) {
                 const double lik = colbuf[buf][i];
 #pragma unroll
                 for (int J = 0; J <= I; ++J) {
+                    if (J > Kb) continue;
                     const int j = tj + 32 * J;
                     if (j < k) a[I][J] -= lik * xr[J];
                     else if (j == k) a[I][J] = -lik * xr[J];
@@ -320,13 +327,15 @@ k_pspace(int p, const double *G, const double *rdiag, const double *y, const dou
             xrows[rr][c] = (c <= k) ? Xbuf[int64_t(k) * PP + c] : 0.0;
         }
         __syncthreads();
+        const int Kmax = (kb + RB - 1) >> 5;   // rows k < kb + RB touch blocks <= Kmax
 #pragma unroll 2
         for (int rr = 0; rr < RB; ++rr) {
             double xj[NB];
 #pragma unroll
-            for (int J = 0; J < NB; ++J) xj[J] = xrows[rr][tj + 32 * J];
+            for (int J = 0; J < NB; ++J) xj[J] = J <= Kmax ? xrows[rr][tj + 32 * J] : 0.0;
 #pragma unroll
             for (int I = 0; I < NB; ++I) {
+                if (I > Kmax) continue;
                 const double xi = xrows[rr][ti + 32 * I];
 #pragma unroll
                 for (int J = 0; J <= I; ++J) a[I][J] += xi * xj[J];
@@ -352,80 +361,117 @@ k_pspace(int p, const double *G, const double *rdiag, const double *y, const dou
 }
 
 // ---------------------------------------------------------------- 4. row pass
-// 256 threads = 4 waves; wave w owns rows [64 b + 16 w, +16) and all P = 16 NT
-// columns.  K = (C + C_Q) S^{-1} on v_mfma_f64_16x16x4: lane l supplies
-// A[l%16][l/16] and B[l/16][l%16] and receives D[l/16 + 4 r][l%16] (the FP64
-// variant interleaves the rows, unlike the FP32 one).  Within
-// a 16-wide k block, MFMA step s pairs lane group q with k = kb + 4 q + s so
-// that each lane reads four consecutive entries of its row.
+// 256 threads = 4 waves; wave w owns rows [64 b + 16 w, +16), lane l owns row
+// l % 16 of them, and every wave covers all P = 16 NT columns.
+//
+// v_mfma_f64_16x16x4 computes D += A B with lane l supplying A[l%16][l/16] and
+// B[l/16][l%16] and holding D[l/16 + 4 r][l%16] (the FP64 variant interleaves
+// the rows).  The kernel computes tiles of K^T = S^{-1} C_prior^T: A is a
+// 16 x 4 slab of S^{-1} (symmetric) read from LDS and B is 4 values of the
+// lane's own row of C_prior, so the result K[row][16 t + l/16 + 4 r] stays in
+// the lane that owns the row.  Within the 16-wide k block kb, MFMA step s
+// pairs lane group q = l/16 with k = 16 kb + q + 4 s; the C_prior values a
+// lane loads are then exactly the columns of K it ends up holding, so the
+// epilogue needs no second read of C or C_Q.  S^{-1} is streamed through a
+// double-buffered LDS slab of 16 rows, prefetched into registers one block
+// ahead.
 template <typename TQ, int NT>
 __global__ void __launch_bounds__(256)
 k_rowpass(int64_t m, double *C, const TQ *CQ, const double *Sinv, const double *nu,
           const double *rdiag, double *xhat, double *var, double kdiag, const int *status) {
     constexpr int P = NT * 16;
-    constexpr int LDB = P + 4;
-    __shared__ double sB[16 * LDB];
+    constexpr int LDB = P + 16;                 // row pitch of the LDS slab (doubles)
+    constexpr int PER = NT;                     // slab doubles per thread: 16 P / 256
+    __shared__ double sB[2][16 * LDB];
     if (status[kStStep] != HIKF_OK) return;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, q = lane >> 4;
-    const int64_t row0 = int64_t(blockIdx.x) * 64 + wave * 16;
-    const int64_t arow = row0 + lr;
-    const bool arow_ok = arow < m;
+    const int64_t row = int64_t(blockIdx.x) * 64 + wave * 16 + lr;
+    const bool ok = row < m;
+    const double *crow = C + (ok ? row : 0) * P;
+    const TQ *qrow = CQ + (ok ? row : 0) * P;
+
+    double cp[NT][4];                           // C_prior[row][16 kb + q + 4 s]
+    double bpre[PER];
     d4 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int kb = 0; kb < P; kb += 16) {
-        for (int idx = tid; idx < 16 * P; idx += 256) {
-            const int rr = idx / P, c = idx % P;
-            sB[rr * LDB + c] = Sinv[int64_t(kb + rr) * P + c];
-        }
-        double av[4] = {0.0, 0.0, 0.0, 0.0};
-        if (arow_ok) {
-            const double *cr = C + arow * P + kb + 4 * q;
-            const TQ *qr = CQ + arow * P + kb + 4 * q;
+
 #pragma unroll
-            for (int s = 0; s < 4; ++s) av[s] = cr[s] + (double)qr[s];
+    for (int u = 0; u < PER; ++u) {
+        const int idx = tid + 256 * u, rr = idx / P, c = idx % P;
+        bpre[u] = Sinv[int64_t(rr) * P + c];
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        cp[0][s] = ok ? crow[q + 4 * s] + (double)qrow[q + 4 * s] : 0.0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int idx = tid + 256 * u, rr = idx / P, c = idx % P;
+        sB[0][rr * LDB + c] = bpre[u];
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int kb = 0; kb < NT; ++kb) {
+        if (kb + 1 < NT) {
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int idx = tid + 256 * u, rr = idx / P, c = idx % P;
+                bpre[u] = Sinv[int64_t(16 * (kb + 1) + rr) * P + c];
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int k = 16 * (kb + 1) + q + 4 * s;
+                cp[kb + 1][s] = ok ? crow[k] + (double)qrow[k] : 0.0;
+            }
         }
-        __syncthreads();
+        const double *B = sB[kb & 1];
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                const double bv = sB[(4 * q + s) * LDB + 16 * t + lr];
-                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv, acc[t], 0, 0, 0);
+                const double a = B[(q + 4 * s) * LDB + 16 * t + lr];
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, cp[kb][s], acc[t], 0, 0, 0);
             }
+        if (kb + 1 < NT) {
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int idx = tid + 256 * u, rr = idx / P, c = idx % P;
+                sB[(kb + 1) & 1][rr * LDB + c] = bpre[u];
+            }
+        }
         __syncthreads();
     }
+
+    // epilogue: lane holds K[row][16 t + q + 4 r] = acc[t][r] and
+    // C_prior[row][16 t + q + 4 r] = cp[t][r]
+    double dv = 0.0, dx = 0.0;
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-        const int64_t row = row0 + q + 4 * rr;
-        const bool ok = row < m;
-        double dv = 0.0, dx = 0.0;
-        if (ok) {
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const int c = 16 * t + lr;
-                const double kv = acc[t][rr];
-                const double cp = C[row * P + c] + (double)CQ[row * P + c];
-                dv += kv * cp;
-                dx += kv * nu[c];
-            }
+        for (int r = 0; r < 4; ++r) {
+            const int c = 16 * t + q + 4 * r;
+            const double kv = acc[t][r];
+            dv += kv * cp[t][r];
+            dx += kv * nu[c];
         }
+    dv += __shfl_xor(dv, 16, 64);
+    dx += __shfl_xor(dx, 16, 64);
+    dv += __shfl_xor(dv, 32, 64);
+    dx += __shfl_xor(dx, 32, 64);
+    if (ok) {
+        double *cout = C + row * P;
 #pragma unroll
-        for (int off = 1; off < 16; off <<= 1) {
-            dv += __shfl_xor(dv, off, 64);
-            dx += __shfl_xor(dx, off, 64);
-        }
-        if (ok) {
+        for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const int c = 16 * t + lr;
-                C[row * P + c] = acc[t][rr] * rdiag[c];
+            for (int r = 0; r < 4; ++r) {
+                const int c = 16 * t + q + 4 * r;
+                cout[c] = acc[t][r] * rdiag[c];
             }
-            if (lr == 0) {
-                var[row] = var[row] + kdiag - dv;
-                xhat[row] += dx;
-            }
+        if (q == 0) {
+            var[row] = var[row] + kdiag - dv;
+            xhat[row] += dx;
         }
     }
 }
