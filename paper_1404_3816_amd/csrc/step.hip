@@ -130,9 +130,13 @@ k_reduce_g(int p, int cpr, const double *partial, double *G, double *hvec, const
 }
 
 // ---------------------------------------------------------------- 3. p-space
-// 1024 threads as a 32 x 32 grid; thread (ti, tj) owns the entries (i, j)
-// with i = ti + 32 I, j = tj + 32 J, I >= J, of the lower triangle of the
-// PP x PP matrix (PP = 32 NB; rows/columns >= p are an identity block).
+// 1024 threads as a 32 x 32 grid; thread (ti, tj) owns the entries (i, j) with
+// i = ti + 32 I, j = tj + 32 J, I >= J, of the PP x PP matrix (PP = 32 NB;
+// rows/columns >= p are an identity block).  Entries of the diagonal blocks
+// with i < j are carried along as junk and never read.  The three phases
+// (Cholesky, in-place L^{-1}, X^T X) are written without per-entry branches:
+// inactive updates multiply by zero, and whole blocks that can no longer
+// change are skipped with uniform branches.
 template <int NB>
 __global__ void __launch_bounds__(1024)
 k_pspace(int p, const double *G, const double *rdiag, const double *y, const double *hvec,
@@ -163,12 +167,10 @@ k_pspace(int p, const double *G, const double *rdiag, const double *y, const dou
         for (int J = 0; J <= I; ++J) {
             const int i = ti + 32 * I, j = tj + 32 * J;
             double v = 0.0;
-            if (i >= j) {
-                if (i < p && j < p)
-                    v = 0.5 * (G[int64_t(i) * p + j] + G[int64_t(j) * p + i]) + (i == j ? rdiag[i] : 0.0);
-                else
-                    v = (i == j) ? 1.0 : 0.0;
-            }
+            if (i < p && j < p)
+                v = 0.5 * (G[int64_t(i) * p + j] + G[int64_t(j) * p + i]) + (i == j ? rdiag[i] : 0.0);
+            else
+                v = (i == j) ? 1.0 : 0.0;
             a[I][J] = v;
         }
 
@@ -186,44 +188,42 @@ k_pspace(int p, const double *G, const double *rdiag, const double *y, const dou
         if (!(d2 > 0.0) || !isfinite(d2)) { fail = 1; mp = d2; break; }
         const double d = sqrt(d2), inv = 1.0 / d;
         mp = fmin(mp, d);
-        const int Kb = k >> 5, kt = k & 31;
-        // blocks with I < Kb or J < Kb are final: skip them (Kb is uniform)
+        const int Kb = k >> 5;
+        const bool own = tj == (k & 31);
         double lj[NB];
 #pragma unroll
         for (int J = 0; J < NB; ++J) {
             const int j = tj + 32 * J;
-            lj[J] = (J >= Kb && j > k) ? colbuf[buf][j] * inv : 0.0;
+            const double v = colbuf[buf][j] * inv;
+            lj[J] = (j > k) ? v : 0.0;
         }
 #pragma unroll
         for (int I = 0; I < NB; ++I) {
-            if (I < Kb) continue;
+            if (I < Kb) continue;                   // uniform
             const int i = ti + 32 * I;
-            const double li = (i > k) ? colbuf[buf][i] * inv : 0.0;
+            const double v = colbuf[buf][i] * inv;
+            const double li = (i > k) ? v : 0.0;
 #pragma unroll
             for (int J = 0; J <= I; ++J) {
-                if (J < Kb) continue;
-                const int j = tj + 32 * J;
-                if (j > k && i >= j) a[I][J] -= li * lj[J];
-            }
-            if (tj == kt) {
-#pragma unroll
-                for (int J = 0; J <= I; ++J)
-                    if (J == Kb) {
-                        if (i > k) a[I][J] = li;
-                        else if (i == k) a[I][J] = d;
-                    }
+                if (J < Kb) continue;               // uniform
+                a[I][J] = fma(-li, lj[J], a[I][J]);
+                if (J == Kb) {                      // uniform: finalise column k
+                    const double fin = (i > k) ? li : d;
+                    a[I][J] = (own && i >= k) ? fin : a[I][J];
+                }
             }
         }
         const int k1 = k + 1;
-        if (k1 < PP && tj == (k1 & 31)) {
+        if (k1 < PP) {
             const int Kb1 = k1 >> 5;
+            const bool own1 = tj == (k1 & 31);
 #pragma unroll
             for (int I = 0; I < NB; ++I)
 #pragma unroll
                 for (int J = 0; J <= I; ++J)
-                    if (J == Kb1) {
+                    if (J == Kb1) {                 // uniform
                         const int i = ti + 32 * I;
-                        if (i >= k1) colbuf[buf ^ 1][i] = a[I][J];
+                        if (own1 && i >= k1) colbuf[buf ^ 1][i] = a[I][J];
                     }
         }
         __syncthreads();
@@ -240,8 +240,10 @@ k_pspace(int p, const double *G, const double *rdiag, const double *y, const dou
         for (int I = 0; I < NB; ++I) diagL[ti + 32 * I] = a[I][I];
     __syncthreads();
 
-    // ---- X = L^{-1} in place, right-looking, one barrier per column
-    if (ti == 0 && tj == 0) {
+    // ---- X = L^{-1} in place, right-looking, one barrier per column:
+    // at step k, rows i > k take B_i -= L_ik X_k (columns j <= k) and row
+    // k + 1 becomes X_{k+1} = B_{k+1} / L_{k+1,k+1}.
+    if (tid == 0) {
         a[0][0] = 1.0 / diagL[0];
         rowbuf[0][0] = a[0][0];
     }
@@ -256,55 +258,55 @@ k_pspace(int p, const double *G, const double *rdiag, const double *y, const dou
     for (int k = 0; k < PP; ++k) {
         const int buf = k & 1;
         const int Kb = k >> 5;
-        // only rows I >= Kb and columns J <= Kb change (Kb is uniform)
         double xr[NB];
 #pragma unroll
         for (int J = 0; J < NB; ++J) {
             const int j = tj + 32 * J;
-            xr[J] = (J <= Kb && j <= k) ? rowbuf[buf][j] : 0.0;
+            const double v = rowbuf[buf][j];
+            xr[J] = (j <= k) ? v : 0.0;
         }
 #pragma unroll
         for (int I = 0; I < NB; ++I) {
-            if (I < Kb) continue;
+            if (I < Kb) continue;                   // uniform
             const int i = ti + 32 * I;
-            if (i > k) {
-                const double lik = colbuf[buf][i];
+            const double v = colbuf[buf][i];
+            const double lik = (i > k) ? v : 0.0;
 #pragma unroll
-                for (int J = 0; J <= I; ++J) {
-                    if (J > Kb) continue;
-                    const int j = tj + 32 * J;
-                    if (j < k) a[I][J] -= lik * xr[J];
-                    else if (j == k) a[I][J] = -lik * xr[J];
-                }
+            for (int J = 0; J <= I; ++J) {
+                if (J > Kb) continue;               // uniform
+                const int j = tj + 32 * J;
+                // column k still holds L_ik: B_ik = 0 - L_ik X_kk there
+                const double base = (j == k) ? 0.0 : a[I][J];
+                const double upd = fma(-lik, xr[J], base);
+                a[I][J] = (i > k) ? upd : a[I][J];
             }
         }
         const int k1 = k + 1;
         if (k1 < PP) {
             const int Kb1 = k1 >> 5;
             const double dinv = 1.0 / diagL[k1];
-            if (ti == (k1 & 31)) {
+            const bool rown = ti == (k1 & 31), cown = tj == (k1 & 31);
 #pragma unroll
-                for (int I = 0; I < NB; ++I)
-                    if (I == Kb1) {
+            for (int I = 0; I < NB; ++I)
+                if (I == Kb1) {                     // uniform: row k + 1
 #pragma unroll
-                        for (int J = 0; J <= I; ++J) {
-                            const int j = tj + 32 * J;
-                            if (j < k1) a[I][J] *= dinv;
-                            else if (j == k1) a[I][J] = dinv;
-                            if (j <= k1) rowbuf[buf ^ 1][j] = a[I][J];
+                    for (int J = 0; J <= I; ++J) {
+                        const int j = tj + 32 * J;
+                        const double x = (j < k1) ? a[I][J] * dinv : dinv;
+                        if (rown && j <= k1) {
+                            a[I][J] = x;
+                            rowbuf[buf ^ 1][j] = x;
                         }
                     }
-            }
-            if (tj == (k1 & 31)) {
+                }
 #pragma unroll
-                for (int I = 0; I < NB; ++I)
+            for (int I = 0; I < NB; ++I)
 #pragma unroll
-                    for (int J = 0; J <= I; ++J)
-                        if (J == Kb1) {
-                            const int i = ti + 32 * I;
-                            if (i > k1) colbuf[buf ^ 1][i] = a[I][J];
-                        }
-            }
+                for (int J = 0; J <= I; ++J)
+                    if (J == Kb1) {                 // uniform: column k + 1 of L
+                        const int i = ti + 32 * I;
+                        if (cown && i > k1) colbuf[buf ^ 1][i] = a[I][J];
+                    }
         }
         __syncthreads();
     }
@@ -332,13 +334,13 @@ k_pspace(int p, const double *G, const double *rdiag, const double *y, const dou
         for (int rr = 0; rr < RB; ++rr) {
             double xj[NB];
 #pragma unroll
-            for (int J = 0; J < NB; ++J) xj[J] = J <= Kmax ? xrows[rr][tj + 32 * J] : 0.0;
+            for (int J = 0; J < NB; ++J) xj[J] = xrows[rr][tj + 32 * J];
 #pragma unroll
             for (int I = 0; I < NB; ++I) {
-                if (I > Kmax) continue;
+                if (I > Kmax) continue;             // uniform
                 const double xi = xrows[rr][ti + 32 * I];
 #pragma unroll
-                for (int J = 0; J <= I; ++J) a[I][J] += xi * xj[J];
+                for (int J = 0; J <= I; ++J) a[I][J] = fma(xi, xj[J], a[I][J]);
             }
         }
         __syncthreads();
@@ -361,8 +363,9 @@ k_pspace(int p, const double *G, const double *rdiag, const double *y, const dou
 }
 
 // ---------------------------------------------------------------- 4. row pass
-// 256 threads = 4 waves; wave w owns rows [64 b + 16 w, +16), lane l owns row
-// l % 16 of them, and every wave covers all P = 16 NT columns.
+// 512 threads = 8 waves per 64-row tile.  Wave w takes row group g = w % 4
+// (rows [64 b + 16 g, +16); lane l owns row l % 16 of them) and column half
+// h = w / 4 (column tiles [T0, T1) of the P = 16 NT columns).
 //
 // v_mfma_f64_16x16x4 computes D += A B with lane l supplying A[l%16][l/16] and
 // B[l/16][l%16] and holding D[l/16 + 4 r][l%16] (the FP64 variant interleaves
@@ -371,89 +374,110 @@ k_pspace(int p, const double *G, const double *rdiag, const double *y, const dou
 // lane's own row of C_prior, so the result K[row][16 t + l/16 + 4 r] stays in
 // the lane that owns the row.  Within the 16-wide k block kb, MFMA step s
 // pairs lane group q = l/16 with k = 16 kb + q + 4 s; the C_prior values a
-// lane loads are then exactly the columns of K it ends up holding, so the
-// epilogue needs no second read of C or C_Q.  S^{-1} is streamed through a
-// double-buffered LDS slab of 16 rows, prefetched into registers one block
-// ahead.
-template <typename TQ, int NT>
-__global__ void __launch_bounds__(256)
-k_rowpass(int64_t m, double *C, const TQ *CQ, const double *Sinv, const double *nu,
-          const double *rdiag, double *xhat, double *var, double kdiag, const int *status) {
+// lane loads in its own column half are then exactly the columns of K it
+// ends up holding, so the epilogue needs no second read of C or C_Q.  S^{-1}
+// is streamed through a double-buffered LDS slab of 16 rows, prefetched into
+// registers one block ahead; LDS operands are read two MFMAs ahead.
+template <typename TQ, int NT, int HALF>
+__device__ __forceinline__ void rowpass_half(double *sB, double *red, int64_t m, double *C,
+                                             const TQ *CQ, const double *Sinv, const double *nu,
+                                             const double *rdiag) {
     constexpr int P = NT * 16;
     constexpr int LDB = P + 16;                 // row pitch of the LDS slab (doubles)
-    constexpr int PER = NT;                     // slab doubles per thread: 16 P / 256
-    __shared__ double sB[2][16 * LDB];
-    if (status[kStStep] != HIKF_OK) return;
+    constexpr int SLAB = 16 * LDB;
+    constexpr int PER = (16 * P + 511) / 512;   // slab doubles per thread (ceil(NT / 2))
+    constexpr int T0 = HALF ? (NT + 1) / 2 : 0;
+    constexpr int T1 = HALF ? NT : (NT + 1) / 2;
+    constexpr int NH = T1 - T0;
+    constexpr int NQ = 4 * NH;                  // (s, t) pairs per k block
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int lr = lane & 15, q = lane >> 4;
-    const int64_t row = int64_t(blockIdx.x) * 64 + wave * 16 + lr;
+    const int lr = lane & 15, q = lane >> 4, grp = wave & 3;
+    const int64_t row = int64_t(blockIdx.x) * 64 + grp * 16 + lr;
     const bool ok = row < m;
-    const double *crow = C + (ok ? row : 0) * P;
-    const TQ *qrow = CQ + (ok ? row : 0) * P;
+    const int64_t rbase = (ok ? row : 0) * P;
 
-    double cp[NT][4];                           // C_prior[row][16 kb + q + 4 s]
+    double keep[NH > 0 ? NH : 1][4];            // C_prior[row][16 t + q + 4 s], t in [T0, T1)
+    double cur[4];
+    double nc[4];                               // next block's C and C_Q, kept apart so the
+    TQ nq[4];                                   // loads are waited for only where they are used
     double bpre[PER];
-    d4 acc[NT];
+    d4 acc[NH > 0 ? NH : 1];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < NH; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
 
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-        const int idx = tid + 256 * u, rr = idx / P, c = idx % P;
-        bpre[u] = Sinv[int64_t(rr) * P + c];
+        const int idx = tid + 512 * u, rr = idx / P, c = idx % P;
+        if (idx < 16 * P) bpre[u] = Sinv[int64_t(rr) * P + c];
     }
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
-        cp[0][s] = ok ? crow[q + 4 * s] + (double)qrow[q + 4 * s] : 0.0;
+    for (int s = 0; s < 4; ++s) cur[s] = ok ? C[rbase + q + 4 * s] + (double)CQ[rbase + q + 4 * s] : 0.0;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-        const int idx = tid + 256 * u, rr = idx / P, c = idx % P;
-        sB[0][rr * LDB + c] = bpre[u];
+        const int idx = tid + 512 * u, rr = idx / P, c = idx % P;
+        if (idx < 16 * P) sB[rr * LDB + c] = bpre[u];
     }
     __syncthreads();
 
 #pragma unroll
     for (int kb = 0; kb < NT; ++kb) {
+        if (kb > 0) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) cur[s] = ok ? nc[s] + (double)nq[s] : 0.0;
+        }
         if (kb + 1 < NT) {
+            // slab first: it is needed first (end of this block), C_prior next
 #pragma unroll
             for (int u = 0; u < PER; ++u) {
-                const int idx = tid + 256 * u, rr = idx / P, c = idx % P;
-                bpre[u] = Sinv[int64_t(16 * (kb + 1) + rr) * P + c];
+                const int idx = tid + 512 * u, rr = idx / P, c = idx % P;
+                if (idx < 16 * P) bpre[u] = Sinv[int64_t(16 * (kb + 1) + rr) * P + c];
             }
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-                const int k = 16 * (kb + 1) + q + 4 * s;
-                cp[kb + 1][s] = ok ? crow[k] + (double)qrow[k] : 0.0;
+                const int64_t o = rbase + 16 * (kb + 1) + q + 4 * s;
+                nc[s] = C[o];
+                nq[s] = CQ[o];
             }
         }
-        const double *B = sB[kb & 1];
+        if (kb >= T0 && kb < T1) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+            for (int s = 0; s < 4; ++s) keep[kb - T0][s] = cur[s];
+        }
+        if (NH > 0) {
+            const double *B = sB + (kb & 1) * SLAB + q * LDB + lr + 16 * T0;
+            double ring[3];
+            ring[0] = B[0];
+            if (NQ > 1) ring[1] = B[(1 / NH) * 4 * LDB + 16 * (1 % NH)];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const double a = B[(q + 4 * s) * LDB + 16 * t + lr];
-                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, cp[kb][s], acc[t], 0, 0, 0);
+            for (int i = 0; i < NQ; ++i) {
+                if (i + 2 < NQ) {
+                    const int s2 = (i + 2) / NH, t2 = (i + 2) % NH;
+                    ring[(i + 2) % 3] = B[4 * s2 * LDB + 16 * t2];
+                }
+                const int si = i / NH, ti = i % NH;
+                acc[ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(ring[i % 3], cur[si], acc[ti], 0, 0, 0);
             }
+        }
         if (kb + 1 < NT) {
 #pragma unroll
             for (int u = 0; u < PER; ++u) {
-                const int idx = tid + 256 * u, rr = idx / P, c = idx % P;
-                sB[(kb + 1) & 1][rr * LDB + c] = bpre[u];
+                const int idx = tid + 512 * u, rr = idx / P, c = idx % P;
+                if (idx < 16 * P) sB[((kb + 1) & 1) * SLAB + rr * LDB + c] = bpre[u];
             }
         }
         __syncthreads();
     }
 
-    // epilogue: lane holds K[row][16 t + q + 4 r] = acc[t][r] and
-    // C_prior[row][16 t + q + 4 r] = cp[t][r]
+    // epilogue: lane holds K[row][16 t + q + 4 r] = acc[t - T0][r] and
+    // C_prior[row][16 t + q + 4 r] = keep[t - T0][r]
     double dv = 0.0, dx = 0.0;
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int t = 0; t < NH; ++t)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int c = 16 * t + q + 4 * r;
+            const int c = 16 * (T0 + t) + q + 4 * r;
             const double kv = acc[t][r];
-            dv += kv * cp[t][r];
+            dv += kv * keep[t][r];
             dx += kv * nu[c];
         }
     dv += __shfl_xor(dv, 16, 64);
@@ -463,13 +487,38 @@ k_rowpass(int64_t m, double *C, const TQ *CQ, const double *Sinv, const double *
     if (ok) {
         double *cout = C + row * P;
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+        for (int t = 0; t < NH; ++t)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int c = 16 * t + q + 4 * r;
+                const int c = 16 * (T0 + t) + q + 4 * r;
                 cout[c] = acc[t][r] * rdiag[c];
             }
-        if (q == 0) {
+    }
+    if (q == 0) {
+        red[(HALF * 64 + grp * 16 + lr) * 2 + 0] = dv;
+        red[(HALF * 64 + grp * 16 + lr) * 2 + 1] = dx;
+    }
+}
+
+template <typename TQ, int NT>
+__global__ void __launch_bounds__(512)
+k_rowpass(int64_t m, double *C, const TQ *CQ, const double *Sinv, const double *nu,
+          const double *rdiag, double *xhat, double *var, double kdiag, const int *status) {
+    constexpr int LDB = NT * 16 + 16;
+    __shared__ double sB[2 * 16 * LDB];
+    __shared__ double red[2 * 64 * 2];
+    if (status[kStStep] != HIKF_OK) return;
+    if ((threadIdx.x >> 6) < 4)
+        rowpass_half<TQ, NT, 0>(sB, red, m, C, CQ, Sinv, nu, rdiag);
+    else
+        rowpass_half<TQ, NT, 1>(sB, red, m, C, CQ, Sinv, nu, rdiag);
+    __syncthreads();
+    const int tid = threadIdx.x;
+    if (tid < 64) {
+        const int64_t row = int64_t(blockIdx.x) * 64 + tid;
+        if (row < m) {
+            const double dv = red[tid * 2] + red[(64 + tid) * 2];
+            const double dx = red[tid * 2 + 1] + red[(64 + tid) * 2 + 1];
             var[row] = var[row] + kdiag - dv;
             xhat[row] += dx;
         }
@@ -479,7 +528,7 @@ k_rowpass(int64_t m, double *C, const TQ *CQ, const double *Sinv, const double *
 template <typename TQ, int NT>
 void launch_rowpass_nt(const Geometry &g, const Layout &lay, char *res, hipStream_t s) {
     const unsigned blocks = unsigned((g.m + 63) / 64);
-    hipLaunchKernelGGL((k_rowpass<TQ, NT>), dim3(blocks), dim3(256), 0, s, g.m,
+    hipLaunchKernelGGL((k_rowpass<TQ, NT>), dim3(blocks), dim3(512), 0, s, g.m,
                        reinterpret_cast<double *>(res + lay.C),
                        reinterpret_cast<const TQ *>(res + lay.CQ),
                        reinterpret_cast<const double *>(res + lay.sinv),
