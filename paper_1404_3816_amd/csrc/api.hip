@@ -34,6 +34,10 @@ Layout make_layout(const Geometry &g) {
     L.status = take(kNumStatus * 4);
     L.minpiv = take(8);
     L.steps = take(8);
+    L.psA = take(size_t(g.pp) * g.pp * 8);
+    L.psL = take(size_t(g.pp) * g.pp * 8);
+    L.psD = take(size_t(g.pp) * 32 * 8);
+    L.pivs = take(size_t(g.pp / 32) * 8);
     L.resident_bytes = off;
 
     off = 0;
@@ -236,7 +240,10 @@ hikf_status hikf_init(const hikf_problem *prob, const hikf_options *opt, void *r
     f->last_stream = s;
     char *res = f->res, *scr = static_cast<char *>(scratch_dev);
     hipError_t e = hipGetDevice(&f->device);
-    if (e != hipSuccess) { hikf_status r = set_err(f, HIKF_E_DEVICE, "hipGetDevice", e); delete f; return r; }
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&f->g.num_cu, hipDeviceAttributeMultiprocessorCount, f->device);
+    if (e != hipSuccess) { hikf_status r = set_err(f, HIKF_E_DEVICE, "device query", e); delete f; return r; }
+    if (f->g.num_cu < 1) f->g.num_cu = 1;
 #define HIKF_TRY(call, what)                                              \
     do {                                                                  \
         hipError_t e_ = (call);                                           \

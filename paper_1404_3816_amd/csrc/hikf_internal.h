@@ -61,6 +61,7 @@ struct Geometry {
     int p = 0;
     int pp = 32;                  // p rounded up to 32 (p-space layout)
     int cpr = 1;                  // gather chunks per ray
+    int num_cu = 256;             // compute units of the device (persistent grids)
     int64_t m = 0;
     int64_t nnz = 0;
     bool direct = false;
@@ -81,6 +82,7 @@ struct Layout {
     // resident
     size_t C, CQ, xhat, var, sinv, xbuf, G, hvec, nu, partial;
     size_t rowptr, col, val, rdiag, status, minpiv, steps;
+    size_t psA, psL, psD, pivs;               // blocked p-space work arrays
     size_t resident_bytes;
     // scratch
     size_t W, sleaf, schild, m2l, lev_off;   // lev_off: start of M/L storage
@@ -124,6 +126,8 @@ hipError_t launch_init_state(const Geometry &g, const Layout &lay, char *res,
                              const double *x0, hipStream_t s);
 hipError_t launch_step(const Geometry &g, const Layout &lay, char *res,
                        const double *y, hipStream_t s, Timing *t);
+hipError_t launch_pspace(const Geometry &g, const Layout &lay, char *res,
+                         const double *y, hipStream_t s);
 hipError_t launch_widen_cq(const Geometry &g, const Layout &lay, char *res,
                            double *out, hipStream_t s);
 

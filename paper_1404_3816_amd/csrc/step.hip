@@ -1,13 +1,14 @@
 // Per-step HiKF update on the GPU (Algorithm Algorithm_HiKF, Sec. 3.1).
 //
-// One assimilation step is four launches:
+// One assimilation step is:
 //   1. k_gather   : partial sums of G = H (C + C_Q) and h = H x_hat over
 //                   chunks of each ray's nonzeros (the prediction
 //                   C_{t+1|t} = C_{t|t} + C_Q is formed on the fly).
 //   2. k_reduce_g : chunk partials -> G (p x p), h (p), in a fixed order.
-//   3. k_pspace   : one 1024-thread workgroup: S = (G + G^T)/2 + R, its
-//                   Cholesky factor L, X = L^{-1}, S^{-1} = X^T X and the
-//                   innovation nu = y - h; writes the step status.
+//   3. p-space    : S = (G + G^T)/2 + R, its Cholesky factor L,
+//                   X = L^{-1}, S^{-1} = X^T X and the innovation nu = y - h
+//                   as blocked FP64 MFMA kernels (pspace.hip); writes the
+//                   step status.
 //   4. k_rowpass  : K = C_prior S^{-1} on FP64 MFMA, fused with the state,
 //                   variance and cross-covariance updates:
 //                   x_hat += K nu, var += K(0) - sum_j K_ij C_prior,ij,
@@ -130,237 +131,7 @@ k_reduce_g(int p, int cpr, const double *partial, double *G, double *hvec, const
 }
 
 // ---------------------------------------------------------------- 3. p-space
-// 1024 threads as a 32 x 32 grid; thread (ti, tj) owns the entries (i, j) with
-// i = ti + 32 I, j = tj + 32 J, I >= J, of the PP x PP matrix (PP = 32 NB;
-// rows/columns >= p are an identity block).  Entries of the diagonal blocks
-// with i < j are carried along as junk and never read.  The three phases
-// (Cholesky, in-place L^{-1}, X^T X) are written without per-entry branches:
-// inactive updates multiply by zero, and whole blocks that can no longer
-// change are skipped with uniform branches.
-template <int NB>
-__global__ void __launch_bounds__(1024)
-k_pspace(int p, const double *G, const double *rdiag, const double *y, const double *hvec,
-         double *Xbuf, double *Sinv, double *nu, int *status, double *minpiv,
-         long long *steps) {
-    constexpr int PP = NB * 32;
-    constexpr int RB = 16;                          // rows of X staged per block
-    __shared__ double colbuf[2][PP];
-    __shared__ double rowbuf[2][PP];
-    __shared__ double diagL[PP];
-    __shared__ double xrows[RB][PP];
-    const int tid = threadIdx.x, ti = tid >> 5, tj = tid & 31;
-
-    int bad = status[kStInit] != 0;
-    for (int i = tid; i < p; i += 1024)
-        if (!isfinite(y[i])) bad = 1;
-    bad = __syncthreads_or(bad);
-    if (bad) {
-        if (tid == 0) status[kStStep] = HIKF_E_INVALID;
-        return;
-    }
-    for (int i = tid; i < p; i += 1024) nu[i] = y[i] - hvec[i];
-
-    double a[NB][NB];
-#pragma unroll
-    for (int I = 0; I < NB; ++I)
-#pragma unroll
-        for (int J = 0; J <= I; ++J) {
-            const int i = ti + 32 * I, j = tj + 32 * J;
-            double v = 0.0;
-            if (i < p && j < p)
-                v = 0.5 * (G[int64_t(i) * p + j] + G[int64_t(j) * p + i]) + (i == j ? rdiag[i] : 0.0);
-            else
-                v = (i == j) ? 1.0 : 0.0;
-            a[I][J] = v;
-        }
-
-    // ---- Cholesky S = L L^T, right-looking, one barrier per column
-    if (tj == 0)
-#pragma unroll
-        for (int I = 0; I < NB; ++I) colbuf[0][ti + 32 * I] = a[I][0];
-    __syncthreads();
-    double mp = 1.0e300;
-    int fail = 0;
-#pragma unroll 1
-    for (int k = 0; k < PP; ++k) {
-        const int buf = k & 1;
-        const double d2 = colbuf[buf][k];
-        if (!(d2 > 0.0) || !isfinite(d2)) { fail = 1; mp = d2; break; }
-        const double d = sqrt(d2), inv = 1.0 / d;
-        mp = fmin(mp, d);
-        const int Kb = k >> 5;
-        const bool own = tj == (k & 31);
-        double lj[NB];
-#pragma unroll
-        for (int J = 0; J < NB; ++J) {
-            const int j = tj + 32 * J;
-            const double v = colbuf[buf][j] * inv;
-            lj[J] = (j > k) ? v : 0.0;
-        }
-#pragma unroll
-        for (int I = 0; I < NB; ++I) {
-            if (I < Kb) continue;                   // uniform
-            const int i = ti + 32 * I;
-            const double v = colbuf[buf][i] * inv;
-            const double li = (i > k) ? v : 0.0;
-#pragma unroll
-            for (int J = 0; J <= I; ++J) {
-                if (J < Kb) continue;               // uniform
-                a[I][J] = fma(-li, lj[J], a[I][J]);
-                if (J == Kb) {                      // uniform: finalise column k
-                    const double fin = (i > k) ? li : d;
-                    a[I][J] = (own && i >= k) ? fin : a[I][J];
-                }
-            }
-        }
-        const int k1 = k + 1;
-        if (k1 < PP) {
-            const int Kb1 = k1 >> 5;
-            const bool own1 = tj == (k1 & 31);
-#pragma unroll
-            for (int I = 0; I < NB; ++I)
-#pragma unroll
-                for (int J = 0; J <= I; ++J)
-                    if (J == Kb1) {                 // uniform
-                        const int i = ti + 32 * I;
-                        if (own1 && i >= k1) colbuf[buf ^ 1][i] = a[I][J];
-                    }
-        }
-        __syncthreads();
-    }
-    if (fail) {
-        if (tid == 0) {
-            status[kStStep] = HIKF_E_NOT_SPD;
-            minpiv[0] = mp;
-        }
-        return;
-    }
-    if (ti == tj)
-#pragma unroll
-        for (int I = 0; I < NB; ++I) diagL[ti + 32 * I] = a[I][I];
-    __syncthreads();
-
-    // ---- X = L^{-1} in place, right-looking, one barrier per column:
-    // at step k, rows i > k take B_i -= L_ik X_k (columns j <= k) and row
-    // k + 1 becomes X_{k+1} = B_{k+1} / L_{k+1,k+1}.
-    if (tid == 0) {
-        a[0][0] = 1.0 / diagL[0];
-        rowbuf[0][0] = a[0][0];
-    }
-    if (tj == 0)
-#pragma unroll
-        for (int I = 0; I < NB; ++I) {
-            const int i = ti + 32 * I;
-            if (i > 0) colbuf[0][i] = a[I][0];
-        }
-    __syncthreads();
-#pragma unroll 1
-    for (int k = 0; k < PP; ++k) {
-        const int buf = k & 1;
-        const int Kb = k >> 5;
-        double xr[NB];
-#pragma unroll
-        for (int J = 0; J < NB; ++J) {
-            const int j = tj + 32 * J;
-            const double v = rowbuf[buf][j];
-            xr[J] = (j <= k) ? v : 0.0;
-        }
-#pragma unroll
-        for (int I = 0; I < NB; ++I) {
-            if (I < Kb) continue;                   // uniform
-            const int i = ti + 32 * I;
-            const double v = colbuf[buf][i];
-            const double lik = (i > k) ? v : 0.0;
-#pragma unroll
-            for (int J = 0; J <= I; ++J) {
-                if (J > Kb) continue;               // uniform
-                const int j = tj + 32 * J;
-                // column k still holds L_ik: B_ik = 0 - L_ik X_kk there
-                const double base = (j == k) ? 0.0 : a[I][J];
-                const double upd = fma(-lik, xr[J], base);
-                a[I][J] = (i > k) ? upd : a[I][J];
-            }
-        }
-        const int k1 = k + 1;
-        if (k1 < PP) {
-            const int Kb1 = k1 >> 5;
-            const double dinv = 1.0 / diagL[k1];
-            const bool rown = ti == (k1 & 31), cown = tj == (k1 & 31);
-#pragma unroll
-            for (int I = 0; I < NB; ++I)
-                if (I == Kb1) {                     // uniform: row k + 1
-#pragma unroll
-                    for (int J = 0; J <= I; ++J) {
-                        const int j = tj + 32 * J;
-                        const double x = (j < k1) ? a[I][J] * dinv : dinv;
-                        if (rown && j <= k1) {
-                            a[I][J] = x;
-                            rowbuf[buf ^ 1][j] = x;
-                        }
-                    }
-                }
-#pragma unroll
-            for (int I = 0; I < NB; ++I)
-#pragma unroll
-                for (int J = 0; J <= I; ++J)
-                    if (J == Kb1) {                 // uniform: column k + 1 of L
-                        const int i = ti + 32 * I;
-                        if (cown && i > k1) colbuf[buf ^ 1][i] = a[I][J];
-                    }
-        }
-        __syncthreads();
-    }
-
-    // ---- S^{-1} = X^T X  (S^{-1}_ij = sum_k X_ki X_kj)
-#pragma unroll
-    for (int I = 0; I < NB; ++I)
-#pragma unroll
-        for (int J = 0; J <= I; ++J) {
-            const int i = ti + 32 * I, j = tj + 32 * J;
-            if (i >= j) Xbuf[int64_t(i) * PP + j] = a[I][J];
-            a[I][J] = 0.0;
-        }
-    __threadfence_block();
-    __syncthreads();
-#pragma unroll 1
-    for (int kb = 0; kb < PP; kb += RB) {
-        for (int idx = tid; idx < RB * PP; idx += 1024) {
-            const int rr = idx / PP, c = idx % PP, k = kb + rr;
-            xrows[rr][c] = (c <= k) ? Xbuf[int64_t(k) * PP + c] : 0.0;
-        }
-        __syncthreads();
-        const int Kmax = (kb + RB - 1) >> 5;   // rows k < kb + RB touch blocks <= Kmax
-#pragma unroll 2
-        for (int rr = 0; rr < RB; ++rr) {
-            double xj[NB];
-#pragma unroll
-            for (int J = 0; J < NB; ++J) xj[J] = xrows[rr][tj + 32 * J];
-#pragma unroll
-            for (int I = 0; I < NB; ++I) {
-                if (I > Kmax) continue;             // uniform
-                const double xi = xrows[rr][ti + 32 * I];
-#pragma unroll
-                for (int J = 0; J <= I; ++J) a[I][J] = fma(xi, xj[J], a[I][J]);
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int I = 0; I < NB; ++I)
-#pragma unroll
-        for (int J = 0; J <= I; ++J) {
-            const int i = ti + 32 * I, j = tj + 32 * J;
-            if (i >= j && i < p && j < p) {
-                Sinv[int64_t(i) * p + j] = a[I][J];
-                Sinv[int64_t(j) * p + i] = a[I][J];
-            }
-        }
-    if (tid == 0) {
-        status[kStStep] = HIKF_OK;
-        minpiv[0] = mp;
-        steps[0] += 1;
-    }
-}
+// (pspace.hip)
 
 // ---------------------------------------------------------------- 4. row pass
 // 512 threads = 8 waves per 64-row tile.  Wave w takes row group g = w % 4
@@ -551,21 +322,6 @@ void launch_rowpass(const Geometry &g, const Layout &lay, char *res, hipStream_t
     }
 }
 
-template <int NB>
-void launch_pspace_nb(const Geometry &g, const Layout &lay, char *res, const double *y,
-                      hipStream_t s) {
-    hipLaunchKernelGGL((k_pspace<NB>), dim3(1), dim3(1024), 0, s, g.p,
-                       reinterpret_cast<const double *>(res + lay.G),
-                       reinterpret_cast<const double *>(res + lay.rdiag), y,
-                       reinterpret_cast<const double *>(res + lay.hvec),
-                       reinterpret_cast<double *>(res + lay.xbuf),
-                       reinterpret_cast<double *>(res + lay.sinv),
-                       reinterpret_cast<double *>(res + lay.nu),
-                       reinterpret_cast<int *>(res + lay.status),
-                       reinterpret_cast<double *>(res + lay.minpiv),
-                       reinterpret_cast<long long *>(res + lay.steps));
-}
-
 template <typename TQ>
 hipError_t run_step(const Geometry &g, const Layout &lay, char *res, const double *y,
                     hipStream_t s, Timing *tm) {
@@ -589,16 +345,9 @@ hipError_t run_step(const Geometry &g, const Layout &lay, char *res, const doubl
                        reinterpret_cast<const int *>(res + lay.status));
     tend(tm, HIKF_PHASE_REDUCE, s);
     tbegin(tm, HIKF_PHASE_PSPACE, s);
-    switch (g.pp / 32) {
-        case 1: launch_pspace_nb<1>(g, lay, res, y, s); break;
-        case 2: launch_pspace_nb<2>(g, lay, res, y, s); break;
-        case 3: launch_pspace_nb<3>(g, lay, res, y, s); break;
-        case 4: launch_pspace_nb<4>(g, lay, res, y, s); break;
-        case 5: launch_pspace_nb<5>(g, lay, res, y, s); break;
-        case 6: launch_pspace_nb<6>(g, lay, res, y, s); break;
-        case 7: launch_pspace_nb<7>(g, lay, res, y, s); break;
-        case 8: launch_pspace_nb<8>(g, lay, res, y, s); break;
-        default: return hipErrorInvalidValue;
+    {
+        hipError_t e = launch_pspace(g, lay, res, y, s);
+        if (e != hipSuccess) return e;
     }
     tend(tm, HIKF_PHASE_PSPACE, s);
     tbegin(tm, HIKF_PHASE_ROWPASS, s);
