@@ -391,6 +391,202 @@ k_l2p_p2p(int dim, int n, int ls, int depth, int r, int p, int PT, int rad, int 
     }
 }
 
+// ---------------------------------------------------------------- MFMA forms
+// v_mfma_{f32,f64}_16x16x4: D += A B with lane l supplying A[l%16][l/16] and
+// B[l/16][l%16]; lane l holds D[row(l/16, r)][l%16] for r = 0..3, where the
+// FP32 variant returns rows 4 (l/16) + r and the FP64 variant rows l/16 + 4 r.
+template <typename T> struct Mma;
+template <> struct Mma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int q, int r) { return 4 * q + r; }
+    static constexpr int pad = 16;          // LDS pitch padding of a B operand tile
+};
+template <> struct Mma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int q, int r) { return q + 4 * r; }
+    static constexpr int pad = 8;
+};
+
+// ---------------------------------------------------------------- L2P + P2P (MFMA)
+// One workgroup per (target leaf B, PT-column tile); wave w owns target rows
+// [16 w, 16 w + 16) of the leaf and all PT columns.  For every source leaf A
+// within `rad` boxes the 64 x 64 kernel block K(x_i - x_j) is generated in
+// LDS from the integer cell offsets, W_A (64 x PT) is staged next to it, and
+// the product accumulates on MFMA; the far field then adds
+// S_leaf^T (64 x r) L_B (r x PT) the same way.
+template <typename T, int PT>
+__global__ void __launch_bounds__(kBlock)
+k_l2p_p2p_mma(int dim, int n, int ls, int depth, int r, int rpad, int p, int rad, int far,
+              KernelParams kp, T h2, const T *W, const T *Sleaf, const T *Lleaf, T *CQ) {
+    typedef typename Mma<T>::v4 v4;
+    constexpr int NTI = PT / 16;
+    constexpr int WP = PT + Mma<T>::pad;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int KP = max(kLeafPts, rpad) + 4;
+    T *sK = reinterpret_cast<T *>(smem_raw);           // [64][KP]
+    T *sW = sK + kLeafPts * KP;                        // [max(64, rpad)][WP]
+    const int64_t B = blockIdx.x;
+    const int c0 = blockIdx.y * PT;
+    const int ncols = min(PT, p - c0);
+    const int nb = 1 << depth;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, q = lane >> 4;
+    int b[3];
+    box_coords(B, nb, dim, b);
+    v4 acc[NTI];
+#pragma unroll
+    for (int t = 0; t < NTI; ++t) acc[t] = v4{0, 0, 0, 0};
+    const int zlo = dim == 3 ? max(0, b[2] - rad) : 0;
+    const int zhi = dim == 3 ? min(nb - 1, b[2] + rad) : 0;
+    for (int az = zlo; az <= zhi; ++az)
+    for (int ay = max(0, b[1] - rad); ay <= min(nb - 1, b[1] + rad); ++ay)
+    for (int ax = max(0, b[0] - rad); ax <= min(nb - 1, b[0] + rad); ++ax) {
+        int a[3] = {ax, ay, az};
+        __syncthreads();
+        for (int idx = tid; idx < kLeafPts * PT; idx += kBlock) {
+            const int j = idx / PT, c = idx % PT;
+            sW[j * WP + c] = (c < ncols) ? W[leaf_point(a, j, dim, n, ls) * p + c0 + c] : (T)0;
+        }
+        for (int idx = tid; idx < kLeafPts * kLeafPts; idx += kBlock) {
+            const int i = idx / kLeafPts, j = idx % kLeafPts;
+            int li[3], lj[3];
+            leaf_local(i, dim, li);
+            leaf_local(j, dim, lj);
+            int dsq = 0;
+            for (int qq = 0; qq < dim; ++qq) {
+                const int d = (a[qq] - b[qq]) * ls + lj[qq] - li[qq];
+                dsq += d * d;
+            }
+            sK[i * KP + j] = kernel_from_r2<T>((T)dsq * h2, kp);
+        }
+        __syncthreads();
+        const T *arow = sK + (16 * wave + lr) * KP + q;
+        const T *bcol = sW + q * WP + lr;
+#pragma unroll 4
+        for (int k0 = 0; k0 < kLeafPts; k0 += 4) {
+            const T av = arow[k0];
+#pragma unroll
+            for (int t = 0; t < NTI; ++t) acc[t] = Mma<T>::op(av, bcol[k0 * WP + 16 * t], acc[t]);
+        }
+    }
+    if (far) {
+        __syncthreads();
+        for (int idx = tid; idx < kLeafPts * rpad; idx += kBlock) {
+            const int i = idx / rpad, k = idx % rpad;
+            sK[i * KP + k] = k < r ? Sleaf[k * kLeafPts + i] : (T)0;
+        }
+        for (int idx = tid; idx < rpad * PT; idx += kBlock) {
+            const int k = idx / PT, c = idx % PT;
+            sW[k * WP + c] = (k < r && c < ncols) ? Lleaf[(B * r + k) * p + c0 + c] : (T)0;
+        }
+        __syncthreads();
+        const T *arow = sK + (16 * wave + lr) * KP + q;
+        const T *bcol = sW + q * WP + lr;
+        for (int k0 = 0; k0 < rpad; k0 += 4) {
+            const T av = arow[k0];
+#pragma unroll
+            for (int t = 0; t < NTI; ++t) acc[t] = Mma<T>::op(av, bcol[k0 * WP + 16 * t], acc[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NTI; ++t) {
+        const int c = 16 * t + lr;
+        if (c >= ncols) continue;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int i = 16 * wave + Mma<T>::row(q, rr);
+            CQ[leaf_point(b, i, dim, n, ls) * p + c0 + c] = acc[t][rr];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- M2L (MFMA)
+// One workgroup per (target box B, PT-column tile).  The output r x PT tile is
+// cut into 16 x 16 MFMA tiles (target-node rows padded to RT = ceil(r/16)
+// tiles), dealt round-robin to the 4 waves; for every interaction-list box A
+// the translation T_{l,o} (r x r) and M_A (r x PT) are staged in LDS (k padded
+// to a multiple of 4 with zeros) and multiplied on MFMA.
+template <typename T, int PT>
+__global__ void __launch_bounds__(kBlock)
+k_m2l_mma(int dim, int r, int p, int lev, const T *M, const T *Tlev, T *L) {
+    typedef typename Mma<T>::v4 v4;
+    constexpr int NCT = PT / 16;
+    constexpr int MAXT = 8;                            // tiles per wave (r <= 128)
+    constexpr int WP = PT + Mma<T>::pad;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int RT = (r + 15) / 16, KR = (r + 3) / 4 * 4, TP = KR + 4;
+    T *sM = reinterpret_cast<T *>(smem_raw);           // [KR][WP]
+    T *sT = sM + KR * WP;                              // [16 RT][TP]
+    const int64_t B = blockIdx.x;
+    const int c0 = blockIdx.y * PT;
+    const int ncols = min(PT, p - c0);
+    const int nb = 1 << lev;
+    const int noff = dim == 2 ? 49 : 343;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, q = lane >> 4;
+    const int ntiles = RT * NCT;
+    int b[3];
+    box_coords(B, nb, dim, b);
+    v4 acc[MAXT];
+#pragma unroll
+    for (int u = 0; u < MAXT; ++u) acc[u] = v4{0, 0, 0, 0};
+    for (int oi = 0; oi < noff; ++oi) {
+        int o[3] = {oi % 7 - 3, (oi / 7) % 7 - 3, oi / 49 - 3};
+        if (!il_member(b, o, nb, dim)) continue;       // uniform
+        int a[3] = {b[0] + o[0], b[1] + o[1], dim == 3 ? b[2] + o[2] : 0};
+        const int64_t A = box_index(a, nb, dim);
+        const T *Toff = Tlev + int64_t(oi) * r * r;
+        __syncthreads();
+        for (int idx = tid; idx < KR * PT; idx += kBlock) {
+            const int k = idx / PT, c = idx % PT;
+            sM[k * WP + c] = (k < r && c < ncols) ? M[(A * r + k) * p + c0 + c] : (T)0;
+        }
+        for (int idx = tid; idx < 16 * RT * KR; idx += kBlock) {
+            const int i = idx / KR, k = idx % KR;
+            sT[i * TP + k] = (i < r && k < r) ? Toff[i * r + k] : (T)0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < MAXT; ++u) {
+            const int tile = wave + 4 * u;
+            if (tile >= ntiles) break;                 // uniform per wave
+            const int rt = tile / NCT, ct = tile % NCT;
+            const T *arow = sT + (16 * rt + lr) * TP + q;
+            const T *bcol = sM + q * WP + 16 * ct + lr;
+            for (int k0 = 0; k0 < KR; k0 += 4)
+                acc[u] = Mma<T>::op(arow[k0], bcol[k0 * WP], acc[u]);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < MAXT; ++u) {
+        const int tile = wave + 4 * u;
+        if (tile >= ntiles) break;
+        const int rt = tile / NCT, ct = tile % NCT;
+        const int c = 16 * ct + lr;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int k = 16 * rt + Mma<T>::row(q, rr);
+            if (k < r && c < ncols) L[(B * r + k) * p + c0 + c] = acc[u][rr];
+        }
+    }
+}
+
+// Allow a kernel more than the default 64 KiB of dynamic LDS (gfx950 has
+// 160 KiB per workgroup).
+template <typename K>
+hipError_t allow_lds(K kernel, size_t bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    if (bytes > 160 * 1024) return hipErrorInvalidValue;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+}
+
 int floor_pow2(int x) {
     int v = 1;
     while (v * 2 <= x) v *= 2;
@@ -453,11 +649,17 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
         tend(tm, HIKF_PHASE_M2M, s);
         // M2L
         tbegin(tm, HIKF_PHASE_M2L, s);
-        PT = min(p, min(64, floor_pow2(kMaxU * kBlock / r)));
-        for (int lev = 2; lev <= D; ++lev)
-            hipLaunchKernelGGL(k_m2l<T>, dim3(unsigned(g.boxes(lev)), (p + PT - 1) / PT),
-                               dim3(kBlock), size_t(r) * PT * sizeof(T), s, dim, r, p, lev, PT,
-                               Mlev(lev), Tm2l + int64_t(lev - 2) * g.noff() * r * r, Llev(lev));
+        {
+            constexpr int MPT = sizeof(T) == 4 ? 128 : 64;
+            const int RT = (r + 15) / 16, KR = (r + 3) / 4 * 4;
+            const size_t lds = (size_t(KR) * (MPT + Mma<T>::pad) + size_t(16 * RT) * (KR + 4)) * sizeof(T);
+            e = allow_lds(k_m2l_mma<T, MPT>, lds);
+            if (e != hipSuccess) return e;
+            for (int lev = 2; lev <= D; ++lev)
+                hipLaunchKernelGGL((k_m2l_mma<T, MPT>), dim3(unsigned(g.boxes(lev)), (p + MPT - 1) / MPT),
+                                   dim3(kBlock), lds, s, dim, r, p, lev, Mlev(lev),
+                                   Tm2l + int64_t(lev - 2) * g.noff() * r * r, Llev(lev));
+        }
         tend(tm, HIKF_PHASE_M2L, s);
         // L2L
         tbegin(tm, HIKF_PHASE_L2L, s);
@@ -469,14 +671,17 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
         tend(tm, HIKF_PHASE_L2L, s);
     }
     {
-        int rows = max(kLeafPts, r);
-        int PT = min(p, min(64, floor_pow2(int((lds_cap / sizeof(T) - size_t(kLeafPts) * kLeafPts) / rows))));
-        int rad = g.direct ? (1 << D) : 1;
-        double h = 1.0 / g.n;
-        size_t lds = (size_t(kLeafPts) * kLeafPts + size_t(max(kLeafPts, r)) * PT) * sizeof(T);
+        constexpr int PPT = sizeof(T) == 4 ? 128 : 64;
+        const int rpad = (r + 3) / 4 * 4;
+        const int rows = max(kLeafPts, rpad);
+        const int rad = g.direct ? (1 << D) : 1;
+        const double h = 1.0 / g.n;
+        const size_t lds = (size_t(kLeafPts) * (rows + 4) + size_t(rows) * (PPT + Mma<T>::pad)) * sizeof(T);
+        e = allow_lds(k_l2p_p2p_mma<T, PPT>, lds);
+        if (e != hipSuccess) return e;
         tbegin(tm, HIKF_PHASE_P2P, s);
-        hipLaunchKernelGGL(k_l2p_p2p<T>, dim3(unsigned(g.boxes(D)), (p + PT - 1) / PT),
-                           dim3(kBlock), lds, s, dim, g.n, g.ls, D, r, p, PT, rad, g.far ? 1 : 0,
+        hipLaunchKernelGGL((k_l2p_p2p_mma<T, PPT>), dim3(unsigned(g.boxes(D)), (p + PPT - 1) / PPT),
+                           dim3(kBlock), lds, s, dim, g.n, g.ls, D, r, rpad, p, rad, g.far ? 1 : 0,
                            g.kp, (T)(h * h), W, Sleaf, g.far ? Llev(D) : W, CQ);
         tend(tm, HIKF_PHASE_P2P, s);
     }

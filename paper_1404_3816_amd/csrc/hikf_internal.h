@@ -12,7 +12,7 @@ namespace hikf {
 
 constexpr int kLeafPts = 64;      // points per leaf: 8x8 (2-D) or 4x4x4 (3-D)
 constexpr int kMaxP = 256;        // measurements handled by the register p-space kernel
-constexpr int kMaxR = 128;        // Chebyshev nodes per box
+constexpr int kMaxR = 64;         // Chebyshev nodes per box
 constexpr int kNumStatus = 8;     // ints in the device status block
 
 // device status block layout (int32 slots)
