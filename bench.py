@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="approximate seconds of CPU work for the oracle sample")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="before the jobs, run one plain device copy of this many MiB "
+                         "(reference kernel for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -141,6 +144,14 @@ def main():
     ydev = torch.as_tensor(ys, dtype=torch.float64, device="cuda").contiguous()
     stream = torch.cuda.current_stream()
     sh = ctypes.c_void_p(stream.cuda_stream)
+    if a.calibrate_copy_mib:
+        nel = a.calibrate_copy_mib * 2**20 // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {a.calibrate_copy_mib} MiB done")
+        del src, dst
     log(f"[bench] resident {info.resident_bytes / 2**30:.2f} GiB, scratch "
         f"{info.scratch_bytes / 2**30:.2f} GiB, depth {info.depth}, near pairs "
         f"{info.near_pairs}, far pairs {info.far_pairs}")

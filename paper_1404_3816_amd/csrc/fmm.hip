@@ -520,7 +520,9 @@ k_m2l_mma(int dim, int r, int p, int lev, const T *M, const T *Tlev, T *L) {
     constexpr int MAXT = 8;                            // tiles per wave (r <= 128)
     constexpr int WP = PT + Mma<T>::pad;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int RT = (r + 15) / 16, KR = (r + 3) / 4 * 4, TP = KR + 4;
+    // TP = 68 (4 mod 64 words) spreads the 16 rows x 4 k of an A-operand
+    // read over distinct LDS banks
+    const int RT = (r + 15) / 16, KR = (r + 3) / 4 * 4, TP = 68;
     T *sM = reinterpret_cast<T *>(smem_raw);           // [KR][WP]
     T *sT = sM + KR * WP;                              // [16 RT][TP]
     const int64_t B = blockIdx.x;
@@ -652,7 +654,7 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
         {
             constexpr int MPT = sizeof(T) == 4 ? 128 : 64;
             const int RT = (r + 15) / 16, KR = (r + 3) / 4 * 4;
-            const size_t lds = (size_t(KR) * (MPT + Mma<T>::pad) + size_t(16 * RT) * (KR + 4)) * sizeof(T);
+            const size_t lds = (size_t(KR) * (MPT + Mma<T>::pad) + size_t(16 * RT) * 68) * sizeof(T);
             e = allow_lds(k_m2l_mma<T, MPT>, lds);
             if (e != hipSuccess) return e;
             for (int lev = 2; lev <= D; ++lev)
