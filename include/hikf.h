@@ -152,7 +152,7 @@ typedef struct hikf_filter hikf_filter;
  * Errors: HIKF_E_INVALID (dim not 2/3, N < 1, p < 1, nnz < 0, theta/ell not
  * positive, gamma outside (0, 2], n_c outside 1..8, NULL arrays),
  * HIKF_E_UNSUPPORTED (N not leaf * 2^k with leaf 8 (2-D) / 4 (3-D), p not a
- * multiple of 16 or above 256, n_c^dim above 64).
+ * multiple of 16 or above 512, n_c^dim above 64).
  */
 hikf_status hikf_plan(const hikf_problem *prob, const hikf_options *opt,
                       hikf_plan_info *out);

@@ -11,7 +11,7 @@
 namespace hikf {
 
 constexpr int kLeafPts = 64;      // points per leaf: 8x8 (2-D) or 4x4x4 (3-D)
-constexpr int kMaxP = 256;        // measurements handled by the register p-space kernel
+constexpr int kMaxP = 512;        // measurements (rays) per step
 constexpr int kMaxR = 64;         // Chebyshev nodes per box
 constexpr int kNumStatus = 8;     // ints in the device status block
 

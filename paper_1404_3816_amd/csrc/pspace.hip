@@ -236,30 +236,35 @@ __global__ void __launch_bounds__(NT) k_ps_update(PsArgs a, int kb) {
 }
 
 __global__ void __launch_bounds__(NT) k_ps_trtri(PsArgs a) {
+    // The blocks X_kj of column j are written to X as soon as they are final
+    // and read back from there (they are needed by every later block of the
+    // column; at PP = 512 they would not fit in LDS together).  The barrier
+    // that follows each store makes them visible to the whole workgroup.
     __shared__ double sL[BS * BP];                // staged L_ik block
-    __shared__ double sX[kMaxNbk * BS * BP];      // X_kj for k = j .. nbk-1
+    __shared__ double sX[BS * BP];                // staged X_kj block
     __shared__ double sD[BS * BP];
     if (a.status[kStStep] != HIKF_OK) return;
     const int j = blockIdx.x;
-    blk_load_plain(sX + j * BS * BP, a.D + int64_t(j) * BS * BS, BS, 0, 0);
+    blk_load_plain(sD, a.D + int64_t(j) * BS * BS, BS, 0, 0);
     __syncthreads();
-    blk_store(sX + j * BS * BP, a.X, a.PP, j, j);
+    blk_store(sD, a.X, a.PP, j, j);
     for (int i = j + 1; i < a.nbk; ++i) {
         d4 acc = d4{0, 0, 0, 0};
         for (int k = j; k < i; ++k) {
             __syncthreads();
             blk_load_plain(sL, a.L, a.PP, i, k);
+            blk_load_plain(sX, a.X, a.PP, k, j);
             __syncthreads();
-            acc = tile_mma<false, false>(acc, sL, sX + k * BS * BP, 1.0);
+            acc = tile_mma<false, false>(acc, sL, sX, 1.0);
         }
         __syncthreads();
         tile_write(sL, acc);                       // T = sum_k L_ik X_kj
         blk_load_plain(sD, a.D + int64_t(i) * BS * BS, BS, 0, 0);
         __syncthreads();
         d4 x = tile_mma<false, false>(d4{0, 0, 0, 0}, sD, sL, -1.0);
-        tile_write(sX + i * BS * BP, x);
+        tile_write(sX, x);
         __syncthreads();
-        blk_store(sX + i * BS * BP, a.X, a.PP, i, j);
+        blk_store(sX, a.X, a.PP, i, j);
     }
 }
 

@@ -134,9 +134,12 @@ k_reduce_g(int p, int cpr, const double *partial, double *G, double *hvec, const
 // (pspace.hip)
 
 // ---------------------------------------------------------------- 4. row pass
-// 512 threads = 8 waves per 64-row tile.  Wave w takes row group g = w % 4
-// (rows [64 b + 16 g, +16); lane l owns row l % 16 of them) and column half
-// h = w / 4 (column tiles [T0, T1) of the P = 16 NT columns).
+// 512 threads = 8 waves per tile of 16 RG rows.  Wave w takes row group
+// g = w % RG (rows [16 (RG b + g), +16); lane l owns row l % 16 of them) and
+// column part c = w / RG (column tiles [T0, T1) of the P = 16 NT columns, the
+// CS = 8 / RG parts splitting them as evenly as possible).  P <= 256 runs 4
+// row groups x 2 column halves, P <= 512 runs 2 row groups x 4 quarters, so
+// every wave holds at most 8 column tiles.
 //
 // v_mfma_f64_16x16x4 computes D += A B with lane l supplying A[l%16][l/16] and
 // B[l/16][l%16] and holding D[l/16 + 4 r][l%16] (the FP64 variant interleaves
@@ -145,25 +148,34 @@ k_reduce_g(int p, int cpr, const double *partial, double *G, double *hvec, const
 // lane's own row of C_prior, so the result K[row][16 t + l/16 + 4 r] stays in
 // the lane that owns the row.  Within the 16-wide k block kb, MFMA step s
 // pairs lane group q = l/16 with k = 16 kb + q + 4 s; the C_prior values a
-// lane loads in its own column half are then exactly the columns of K it
+// lane loads in its own column part are then exactly the columns of K it
 // ends up holding, so the epilogue needs no second read of C or C_Q.  S^{-1}
 // is streamed through a double-buffered LDS slab of 16 rows, prefetched into
 // registers one block ahead; LDS operands are read two MFMAs ahead.
-template <typename TQ, int NT, int HALF>
-__device__ __forceinline__ void rowpass_half(double *sB, double *red, int64_t m, double *C,
+template <int NT, int CS>
+struct RowSplit {
+    static constexpr int RG = 8 / CS;
+    static constexpr int P = NT * 16;
+    static constexpr int LDB = P + 16;          // row pitch of the LDS slab (doubles)
+    static constexpr int SLAB = 16 * LDB;
+    static constexpr int PER = (16 * P + 511) / 512;  // slab doubles per thread
+    static constexpr int t0(int c) { return (c * NT + CS - 1) / CS; }
+};
+
+template <typename TQ, int NT, int CS, int PART>
+__device__ __forceinline__ void rowpass_part(double *sB, double *red, int64_t m, double *C,
                                              const TQ *CQ, const double *Sinv, const double *nu,
                                              const double *rdiag) {
-    constexpr int P = NT * 16;
-    constexpr int LDB = P + 16;                 // row pitch of the LDS slab (doubles)
-    constexpr int SLAB = 16 * LDB;
-    constexpr int PER = (16 * P + 511) / 512;   // slab doubles per thread (ceil(NT / 2))
-    constexpr int T0 = HALF ? (NT + 1) / 2 : 0;
-    constexpr int T1 = HALF ? NT : (NT + 1) / 2;
+    using RS = RowSplit<NT, CS>;
+    constexpr int RG = RS::RG, P = RS::P, LDB = RS::LDB, SLAB = RS::SLAB, PER = RS::PER;
+    constexpr int T0 = RS::t0(PART);
+    constexpr int T1 = RS::t0(PART + 1);
     constexpr int NH = T1 - T0;
     constexpr int NQ = 4 * NH;                  // (s, t) pairs per k block
+    constexpr int PH = PER > 8 && NQ >= 4 ? (PER + 1) / 2 : PER;  // slab doubles in flight
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int lr = lane & 15, q = lane >> 4, grp = wave & 3;
-    const int64_t row = int64_t(blockIdx.x) * 64 + grp * 16 + lr;
+    const int lr = lane & 15, q = lane >> 4, grp = wave % RG;
+    const int64_t row = int64_t(blockIdx.x) * (16 * RG) + grp * 16 + lr;
     const bool ok = row < m;
     const int64_t rbase = (ok ? row : 0) * P;
 
@@ -171,7 +183,7 @@ __device__ __forceinline__ void rowpass_half(double *sB, double *red, int64_t m,
     double cur[4];
     double nc[4];                               // next block's C and C_Q, kept apart so the
     TQ nq[4];                                   // loads are waited for only where they are used
-    double bpre[PER];
+    double bpre[PH];
     d4 acc[NH > 0 ? NH : 1];
 #pragma unroll
     for (int t = 0; t < NH; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
@@ -179,15 +191,10 @@ __device__ __forceinline__ void rowpass_half(double *sB, double *red, int64_t m,
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const int idx = tid + 512 * u, rr = idx / P, c = idx % P;
-        if (idx < 16 * P) bpre[u] = Sinv[int64_t(rr) * P + c];
+        if (idx < 16 * P) sB[rr * LDB + c] = Sinv[int64_t(rr) * P + c];
     }
 #pragma unroll
     for (int s = 0; s < 4; ++s) cur[s] = ok ? C[rbase + q + 4 * s] + (double)CQ[rbase + q + 4 * s] : 0.0;
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        const int idx = tid + 512 * u, rr = idx / P, c = idx % P;
-        if (idx < 16 * P) sB[rr * LDB + c] = bpre[u];
-    }
     __syncthreads();
 
 #pragma unroll
@@ -199,7 +206,7 @@ __device__ __forceinline__ void rowpass_half(double *sB, double *red, int64_t m,
         if (kb + 1 < NT) {
             // slab first: it is needed first (end of this block), C_prior next
 #pragma unroll
-            for (int u = 0; u < PER; ++u) {
+            for (int u = 0; u < PH; ++u) {
                 const int idx = tid + 512 * u, rr = idx / P, c = idx % P;
                 if (idx < 16 * P) bpre[u] = Sinv[int64_t(16 * (kb + 1) + rr) * P + c];
             }
@@ -227,13 +234,28 @@ __device__ __forceinline__ void rowpass_half(double *sB, double *red, int64_t m,
                 }
                 const int si = i / NH, ti = i % NH;
                 acc[ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(ring[i % 3], cur[si], acc[ti], 0, 0, 0);
+                if (PH < PER && i == NQ / 2 - 1 && kb + 1 < NT) {
+                    // wide slabs go in two halves to bound the registers they hold;
+                    // the target buffer was last read before the previous barrier
+#pragma unroll
+                    for (int u = 0; u < PH; ++u) {
+                        const int idx = tid + 512 * u, rr = idx / P, c = idx % P;
+                        if (idx < 16 * P) sB[((kb + 1) & 1) * SLAB + rr * LDB + c] = bpre[u];
+                    }
+#pragma unroll
+                    for (int u = PH; u < PER; ++u) {
+                        const int idx = tid + 512 * u, rr = idx / P, c = idx % P;
+                        if (idx < 16 * P) bpre[u - PH] = Sinv[int64_t(16 * (kb + 1) + rr) * P + c];
+                    }
+                }
             }
         }
         if (kb + 1 < NT) {
+            constexpr int U0 = PH < PER ? PH : 0;
 #pragma unroll
-            for (int u = 0; u < PER; ++u) {
+            for (int u = U0; u < PER; ++u) {
                 const int idx = tid + 512 * u, rr = idx / P, c = idx % P;
-                if (idx < 16 * P) sB[((kb + 1) & 1) * SLAB + rr * LDB + c] = bpre[u];
+                if (idx < 16 * P) sB[((kb + 1) & 1) * SLAB + rr * LDB + c] = bpre[u - U0];
             }
         }
         __syncthreads();
@@ -266,30 +288,40 @@ __device__ __forceinline__ void rowpass_half(double *sB, double *red, int64_t m,
             }
     }
     if (q == 0) {
-        red[(HALF * 64 + grp * 16 + lr) * 2 + 0] = dv;
-        red[(HALF * 64 + grp * 16 + lr) * 2 + 1] = dx;
+        red[((PART * RG + grp) * 16 + lr) * 2 + 0] = dv;
+        red[((PART * RG + grp) * 16 + lr) * 2 + 1] = dx;
     }
 }
 
-template <typename TQ, int NT>
+template <typename TQ, int NT, int CS>
 __global__ void __launch_bounds__(512)
 k_rowpass(int64_t m, double *C, const TQ *CQ, const double *Sinv, const double *nu,
           const double *rdiag, double *xhat, double *var, double kdiag, const int *status) {
-    constexpr int LDB = NT * 16 + 16;
-    __shared__ double sB[2 * 16 * LDB];
-    __shared__ double red[2 * 64 * 2];
+    using RS = RowSplit<NT, CS>;
+    constexpr int RG = RS::RG;
+    __shared__ double sB[2 * RS::SLAB];
+    __shared__ double red[8 * 16 * 2];
     if (status[kStStep] != HIKF_OK) return;
-    if ((threadIdx.x >> 6) < 4)
-        rowpass_half<TQ, NT, 0>(sB, red, m, C, CQ, Sinv, nu, rdiag);
-    else
-        rowpass_half<TQ, NT, 1>(sB, red, m, C, CQ, Sinv, nu, rdiag);
+    const int part = (threadIdx.x >> 6) / RG;
+    if (part == 0)
+        rowpass_part<TQ, NT, CS, 0>(sB, red, m, C, CQ, Sinv, nu, rdiag);
+    else if (part == 1)
+        rowpass_part<TQ, NT, CS, 1>(sB, red, m, C, CQ, Sinv, nu, rdiag);
+    else if (CS > 2 && part == 2)
+        rowpass_part<TQ, NT, CS, (CS > 2 ? 2 : 0)>(sB, red, m, C, CQ, Sinv, nu, rdiag);
+    else if (CS > 3)
+        rowpass_part<TQ, NT, CS, (CS > 3 ? 3 : 0)>(sB, red, m, C, CQ, Sinv, nu, rdiag);
     __syncthreads();
     const int tid = threadIdx.x;
-    if (tid < 64) {
-        const int64_t row = int64_t(blockIdx.x) * 64 + tid;
+    if (tid < 16 * RG) {
+        const int64_t row = int64_t(blockIdx.x) * (16 * RG) + tid;
         if (row < m) {
-            const double dv = red[tid * 2] + red[(64 + tid) * 2];
-            const double dx = red[tid * 2 + 1] + red[(64 + tid) * 2 + 1];
+            double dv = 0.0, dx = 0.0;
+#pragma unroll
+            for (int c = 0; c < CS; ++c) {
+                dv += red[(c * 16 * RG + tid) * 2];
+                dx += red[(c * 16 * RG + tid) * 2 + 1];
+            }
             var[row] = var[row] + kdiag - dv;
             xhat[row] += dx;
         }
@@ -298,8 +330,10 @@ k_rowpass(int64_t m, double *C, const TQ *CQ, const double *Sinv, const double *
 
 template <typename TQ, int NT>
 void launch_rowpass_nt(const Geometry &g, const Layout &lay, char *res, hipStream_t s) {
-    const unsigned blocks = unsigned((g.m + 63) / 64);
-    hipLaunchKernelGGL((k_rowpass<TQ, NT>), dim3(blocks), dim3(512), 0, s, g.m,
+    constexpr int CS = NT <= 16 ? 2 : 4;
+    constexpr int rows = 16 * (8 / CS);
+    const unsigned blocks = unsigned((g.m + rows - 1) / rows);
+    hipLaunchKernelGGL((k_rowpass<TQ, NT, CS>), dim3(blocks), dim3(512), 0, s, g.m,
                        reinterpret_cast<double *>(res + lay.C),
                        reinterpret_cast<const TQ *>(res + lay.CQ),
                        reinterpret_cast<const double *>(res + lay.sinv),
@@ -316,7 +350,9 @@ void launch_rowpass(const Geometry &g, const Layout &lay, char *res, hipStream_t
 #define HIKF_NT(N) case N: launch_rowpass_nt<TQ, N>(g, lay, res, s); break;
         HIKF_NT(1) HIKF_NT(2) HIKF_NT(3) HIKF_NT(4) HIKF_NT(5) HIKF_NT(6) HIKF_NT(7) HIKF_NT(8)
         HIKF_NT(9) HIKF_NT(10) HIKF_NT(11) HIKF_NT(12) HIKF_NT(13) HIKF_NT(14) HIKF_NT(15)
-        HIKF_NT(16)
+        HIKF_NT(16) HIKF_NT(17) HIKF_NT(18) HIKF_NT(19) HIKF_NT(20) HIKF_NT(21) HIKF_NT(22)
+        HIKF_NT(23) HIKF_NT(24) HIKF_NT(25) HIKF_NT(26) HIKF_NT(27) HIKF_NT(28) HIKF_NT(29)
+        HIKF_NT(30) HIKF_NT(31) HIKF_NT(32)
 #undef HIKF_NT
         default: break;
     }

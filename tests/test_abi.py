@@ -92,7 +92,7 @@ def test_plan_reports_unsupported_shapes():
     assert _plan(_problem(n=33))[0] == H.HIKF_E_UNSUPPORTED      # not 8 * 2^k
     assert _plan(_problem(n=24))[0] == H.HIKF_E_UNSUPPORTED
     assert _plan(_problem(p=20))[0] == H.HIKF_E_UNSUPPORTED      # not a multiple of 16
-    assert _plan(_problem(p=512))[0] == H.HIKF_E_UNSUPPORTED     # above 256
+    assert _plan(_problem(p=528))[0] == H.HIKF_E_UNSUPPORTED     # above 512
     assert _plan(_problem(dim=3, n=16), n_c=6)[0] == H.HIKF_E_UNSUPPORTED  # r > 128
 
 

@@ -148,10 +148,13 @@ def test_nonzero_prior_mean():
     assert max_step_rel(xs, xa) < 1e-10
 
 
-@pytest.mark.parametrize("p", [48, 256])
-def test_step_p_sizes(p):
-    # p = 48 pads the p-space to 64; p = 256 is the largest supported
-    case = Case(2, 64, p, ell=0.2, steps=2)
+@pytest.mark.parametrize("dim,n,p", [(2, 64, 48), (2, 64, 256), (2, 64, 272), (2, 64, 400),
+                                      (2, 64, 512), (3, 16, 512)])
+def test_step_p_sizes(dim, n, p):
+    # p = 48 pads the p-space to 64; above 256 the row pass splits the columns
+    # in four (272: uneven parts; 400: odd number of 32-blocks); 512 is the
+    # largest supported
+    case = Case(dim, n, p, ell=0.2, steps=2, planes=8 if dim == 3 else 2)
     _, xs, vs, stats = case.gpu_run(n_c=4, precision="f64")
     xb, vb = case.tier_b(case.cq_bbfmm(4), steps=2)
     assert stats.last_status == 0
