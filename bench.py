@@ -16,6 +16,7 @@ same workload.
 
 import argparse
 import ctypes
+import hashlib
 import json
 import os
 import sys
@@ -53,6 +54,33 @@ def parse():
                     help="before the jobs, run one plain device copy of this many MiB "
                          "(reference kernel for hardware byte counters)")
     return ap.parse_args()
+
+
+def kernel_source_digest():
+    """SHA-256 over the sources the step kernels are built from."""
+    h = hashlib.sha256()
+    for f in ("step.hip", "hikf_internal.h"):
+        with open(os.path.join(ROOT, "paper_1404_3816_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads
+    for a plain copy of known size), or None when there is no summary for this
+    workload or the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    digest = kernel_source_digest()
+    for line in open(path):
+        if line.startswith("traffic-record: "):
+            rec = json.loads(line[len("traffic-record: "):])
+            if rec.get("kernel") == kernel and rec.get("source_sha256") == digest:
+                return int(rec["fetch_kib"] * 1024 * rec["fetch_scale"]
+                           + rec["write_kib"] * 1024 * rec["write_scale"])
+    return None
 
 
 def cpu_baseline(w, assim_steps, budget):
@@ -209,7 +237,8 @@ def main():
     row_tflops = 2.0 * m * p * p / row_s / 1e12
     roof = {"bound": "mfma", "achieved": round(row_tflops, 3), "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s", "frac": round(row_tflops / PEAK_FP64_TFLOPS, 4),
-            "traffic": None, "kernel": "k_rowpass (FP64 MFMA)",
+            "traffic": measured_traffic(a.workload, "k_rowpass"), "traffic_unit": "bytes/launch",
+            "algorithmic_bytes": (8 + 4 + 8) * m * p, "kernel": "k_rowpass (FP64 MFMA)",
             "avg_ms": round(avg["rowpass"], 4)}
     tq = 8 if a.precision == "f64" else 4
     peak_f = PEAK_FP64_TFLOPS if a.precision == "f64" else PEAK_FP32_TFLOPS
