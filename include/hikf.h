@@ -106,6 +106,11 @@ typedef struct hikf_options {
                                 for small grids and tests)                   */
     int32_t timing;          /* 1: bracket every phase with HIP events on the
                                 launch stream; hikf_query reports the sums    */
+    int32_t graph;           /* 1: capture the step's kernels once, at init,
+                                into a HIP graph and replay it per step (y is
+                                first copied into the resident region).
+                                Ignored when timing = 1.  Results are bitwise
+                                those of the launched kernels.                */
 } hikf_options;
 
 /* Phases timed when hikf_options.timing = 1 (indices of hikf_stats.time_ms). */
@@ -140,6 +145,8 @@ typedef struct hikf_stats {
     int32_t last_status;     /* hikf_status of the most recent step           */
     int32_t init_status;     /* hikf_status of the device-side init checks    */
     double min_pivot;        /* smallest Cholesky diagonal of the last step   */
+    int64_t negative_variances; /* variance entries that came out negative, summed
+                                over all steps since init (no clamping)       */
     double time_ms[HIKF_NUM_PHASES];     /* summed event time per phase       */
     int64_t time_count[HIKF_NUM_PHASES]; /* timed executions per phase        */
 } hikf_stats;
@@ -189,6 +196,20 @@ hikf_status hikf_init(const hikf_problem *prob, const hikf_options *opt,
  */
 hikf_status hikf_step(hikf_filter *f, const double *y_dev, double *x_out_dev,
                       double *var_out_dev, void *stream);
+
+/*
+ * Grouped step for a serving loop: hikf_step(filters[i], y_dev[i], x_out[i],
+ * var_out[i], stream) for i = 0 .. count-1, in order, all on `stream`.
+ * x_out_dev / var_out_dev may be NULL (no copies for any filter) or hold
+ * NULL entries.  Each filter's result is exactly its solo hikf_step result;
+ * the filters must be distinct.
+ * Errors: HIKF_E_INVALID (count < 0, NULL arrays, a NULL filter or y: then
+ * no filter is stepped), otherwise the first immediate error of a step
+ * (the filters before it have been stepped, the ones after it have not).
+ */
+hikf_status hikf_step_batch(hikf_filter *const *filters, const double *const *y_dev,
+                            double *const *x_out_dev, double *const *var_out_dev,
+                            int32_t count, void *stream);
 
 /*
  * Synchronise the filter's last stream and read its device status and, if

@@ -34,6 +34,8 @@ Layout make_layout(const Geometry &g) {
     L.status = take(kNumStatus * 4);
     L.minpiv = take(8);
     L.steps = take(8);
+    L.negvar = take(8);
+    L.ybuf = take(p * 8);
     L.psA = take(size_t(g.pp) * g.pp * 8);
     L.psL = take(size_t(g.pp) * g.pp * 8);
     L.psD = take(size_t(g.pp) * 32 * 8);
@@ -258,6 +260,7 @@ hikf_status hikf_init(const hikf_problem *prob, const hikf_options *opt, void *r
     if (opt->timing) HIKF_TRY(f->timing.create(), "event create");
     HIKF_TRY(hipMemsetAsync(res + lay.status, 0, hikf::kNumStatus * 4, s), "status clear");
     HIKF_TRY(hipMemsetAsync(res + lay.steps, 0, 8, s), "steps clear");
+    HIKF_TRY(hipMemsetAsync(res + lay.negvar, 0, 8, s), "counter clear");
     HIKF_TRY(hipMemcpyAsync(res + lay.rowptr, prob->h_rowptr_dev, size_t(g.p + 1) * 8,
                             hipMemcpyDeviceToDevice, s), "copy rowptr");
     if (g.nnz > 0) {
@@ -271,6 +274,27 @@ hikf_status hikf_init(const hikf_problem *prob, const hikf_options *opt, void *r
     HIKF_TRY(hikf::launch_validate(g, lay, res, prob->x0_dev, s), "validate");
     HIKF_TRY(hikf::launch_fmm(g, lay, res, scr, s, &f->timing), "fmm");
     HIKF_TRY(hikf::launch_init_state(g, lay, res, prob->x0_dev, s), "init state");
+    if (opt->graph && !opt->timing) {
+        // capture on a private stream (the caller's may be the null stream,
+        // which cannot be captured); the graph reads y from the resident copy
+        hipStream_t cs = nullptr;
+        HIKF_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
+        hipError_t ce = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (ce == hipSuccess) {
+            hipError_t le = hikf::launch_step(f->g, lay, res,
+                                              reinterpret_cast<const double *>(res + lay.ybuf), cs,
+                                              nullptr);
+            ce = hipStreamEndCapture(cs, &f->graph);
+            if (ce == hipSuccess) ce = le;
+        }
+        if (ce == hipSuccess) ce = hipGraphInstantiate(&f->gexec, f->graph, nullptr, nullptr, 0);
+        (void)hipStreamDestroy(cs);
+        if (ce != hipSuccess) {
+            if (f->graph) (void)hipGraphDestroy(f->graph);
+            f->graph = nullptr;
+        }
+        HIKF_TRY(ce, "step graph");
+    }
 #undef HIKF_TRY
     *out = f;
     return HIKF_OK;
@@ -281,7 +305,14 @@ hikf_status hikf_step(hikf_filter *f, const double *y_dev, double *x_out_dev, do
     if (!f || !y_dev) return HIKF_E_INVALID;
     hipStream_t s = static_cast<hipStream_t>(stream);
     f->last_stream = s;
-    hipError_t e = hikf::launch_step(f->g, f->lay, f->res, y_dev, s, &f->timing);
+    hipError_t e;
+    if (f->gexec) {
+        e = hipMemcpyAsync(f->res + f->lay.ybuf, y_dev, size_t(f->g.p) * 8,
+                           hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipGraphLaunch(f->gexec, s);
+    } else {
+        e = hikf::launch_step(f->g, f->lay, f->res, y_dev, s, &f->timing);
+    }
     if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "step", e);
     const size_t mb = size_t(f->g.m) * 8;
     if (x_out_dev || var_out_dev) hikf::tbegin(&f->timing, HIKF_PHASE_OUTPUT, s);
@@ -297,6 +328,20 @@ hikf_status hikf_step(hikf_filter *f, const double *y_dev, double *x_out_dev, do
     return HIKF_OK;
 }
 
+hikf_status hikf_step_batch(hikf_filter *const *filters, const double *const *y_dev,
+                            double *const *x_out_dev, double *const *var_out_dev, int32_t count,
+                            void *stream) {
+    if (count < 0 || (count > 0 && (!filters || !y_dev))) return HIKF_E_INVALID;
+    for (int32_t i = 0; i < count; ++i)
+        if (!filters[i] || !y_dev[i]) return HIKF_E_INVALID;
+    for (int32_t i = 0; i < count; ++i) {
+        hikf_status st = hikf_step(filters[i], y_dev[i], x_out_dev ? x_out_dev[i] : nullptr,
+                                   var_out_dev ? var_out_dev[i] : nullptr, stream);
+        if (st != HIKF_OK) return st;
+    }
+    return HIKF_OK;
+}
+
 hikf_status hikf_query(hikf_filter *f, hikf_stats *out) {
     if (!f || !out) return HIKF_E_INVALID;
     hipError_t e = hipStreamSynchronize(f->last_stream);
@@ -307,8 +352,11 @@ hikf_status hikf_query(hikf_filter *f, hikf_stats *out) {
     e = hipMemcpy(st, f->res + f->lay.status, sizeof(st), hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(&mp, f->res + f->lay.minpiv, 8, hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(&steps, f->res + f->lay.steps, 8, hipMemcpyDeviceToHost);
+    unsigned long long neg = 0;
+    if (e == hipSuccess) e = hipMemcpy(&neg, f->res + f->lay.negvar, 8, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "read status", e);
     out->steps_applied = steps;
+    out->negative_variances = int64_t(neg);
     out->last_status = st[hikf::kStStep];
     out->init_status = st[hikf::kStInit];
     out->min_pivot = mp;
@@ -366,6 +414,8 @@ hikf_status hikf_export_cq(hikf_filter *f, double *cq_dev, void *stream) {
 
 void hikf_destroy(hikf_filter *f) {
     if (!f) return;
+    if (f->gexec) (void)hipGraphExecDestroy(f->gexec);
+    if (f->graph) (void)hipGraphDestroy(f->graph);
     f->timing.destroy();
     delete f;
 }

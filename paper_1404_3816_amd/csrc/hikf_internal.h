@@ -81,7 +81,7 @@ struct Geometry {
 struct Layout {
     // resident
     size_t C, CQ, xhat, var, sinv, xbuf, G, hvec, nu, partial;
-    size_t rowptr, col, val, rdiag, status, minpiv, steps;
+    size_t rowptr, col, val, rdiag, status, minpiv, steps, negvar, ybuf;
     size_t psA, psL, psD, pivs;               // blocked p-space work arrays
     size_t resident_bytes;
     // scratch
@@ -142,5 +142,7 @@ struct hikf_filter {
     hipStream_t last_stream = nullptr;
     int device = 0;
     hikf::Timing timing;
+    hipGraph_t graph = nullptr;      // step captured at init (hikf_options.graph)
+    hipGraphExec_t gexec = nullptr;
     char err[256] = {0};
 };

@@ -296,7 +296,8 @@ __device__ __forceinline__ void rowpass_part(double *sB, double *red, int64_t m,
 template <typename TQ, int NT, int CS>
 __global__ void __launch_bounds__(512)
 k_rowpass(int64_t m, double *C, const TQ *CQ, const double *Sinv, const double *nu,
-          const double *rdiag, double *xhat, double *var, double kdiag, const int *status) {
+          const double *rdiag, double *xhat, double *var, double kdiag, const int *status,
+          unsigned long long *negvar) {
     using RS = RowSplit<NT, CS>;
     constexpr int RG = RS::RG;
     __shared__ double sB[2 * RS::SLAB];
@@ -322,8 +323,10 @@ k_rowpass(int64_t m, double *C, const TQ *CQ, const double *Sinv, const double *
                 dv += red[(c * 16 * RG + tid) * 2];
                 dx += red[(c * 16 * RG + tid) * 2 + 1];
             }
-            var[row] = var[row] + kdiag - dv;
+            const double v = var[row] + kdiag - dv;
+            var[row] = v;
             xhat[row] += dx;
+            if (v < 0.0) atomicAdd(negvar, 1ull);
         }
     }
 }
@@ -341,7 +344,8 @@ void launch_rowpass_nt(const Geometry &g, const Layout &lay, char *res, hipStrea
                        reinterpret_cast<const double *>(res + lay.rdiag),
                        reinterpret_cast<double *>(res + lay.xhat),
                        reinterpret_cast<double *>(res + lay.var), g.kp.family == HIKF_KERNEL_TEST_R2 ? 0.0 : g.kp.theta,
-                       reinterpret_cast<const int *>(res + lay.status));
+                       reinterpret_cast<const int *>(res + lay.status),
+                       reinterpret_cast<unsigned long long *>(res + lay.negvar));
 }
 
 template <typename TQ>

@@ -50,12 +50,13 @@ def problem_from_csr(dim, n, rowptr, col, val, r_diag, family="powexp", theta=1.
     return pr, (t_rowptr, t_col, t_val, t_r, t_x0)
 
 
-def make_options(n_c=4, precision="f32", direct=False, timing=False):
+def make_options(n_c=4, precision="f32", direct=False, timing=False, graph=False):
     op = H.hikf_options()
     op.n_c = int(n_c)
     op.fmm_precision = PRECISIONS[precision]
     op.direct = 1 if direct else 0
     op.timing = 1 if timing else 0
+    op.graph = 1 if graph else 0
     return op
 
 
@@ -136,3 +137,22 @@ class HikfFilter:
             self.close()
         except Exception:
             pass
+
+
+def step_batch(filters, ys, x_outs=None, var_outs=None, stream=None):
+    """One hikf_step_batch call: step filters[i] with ys[i] (p_i doubles on the
+    device each), writing x_outs[i] / var_outs[i] when given."""
+    n = len(filters)
+    assert len(ys) == n
+    for f, y in zip(filters, ys):
+        assert y.dtype == torch.float64 and y.is_cuda and y.is_contiguous() and y.numel() == f.p
+    arr = ctypes.c_void_p * n
+
+    def ptrs(ts):
+        return arr(*[t.data_ptr() if t is not None else None for t in ts])
+
+    fh = arr(*[f.handle.value for f in filters])
+    st = H.hikf_step_batch(fh, ptrs(ys), ptrs(x_outs) if x_outs is not None else None,
+                           ptrs(var_outs) if var_outs is not None else None, n,
+                           _stream_handle(stream))
+    H.check(st, "hikf_step_batch")

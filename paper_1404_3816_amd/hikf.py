@@ -53,7 +53,7 @@ class hikf_problem(ctypes.Structure):
 
 class hikf_options(ctypes.Structure):
     _fields_ = [("n_c", c_i32), ("fmm_precision", c_i32), ("direct", c_i32),
-                ("timing", c_i32)]
+                ("timing", c_i32), ("graph", c_i32)]
 
 
 class hikf_plan_info(ctypes.Structure):
@@ -68,7 +68,8 @@ PHASES = ("operators", "p2m", "m2m", "m2l", "l2l", "p2p", "init", "gather", "red
 
 class hikf_stats(ctypes.Structure):
     _fields_ = [("steps_applied", c_i64), ("last_status", c_i32), ("init_status", c_i32),
-                ("min_pivot", c_dbl), ("time_ms", c_dbl * HIKF_NUM_PHASES),
+                ("min_pivot", c_dbl), ("negative_variances", c_i64),
+                ("time_ms", c_dbl * HIKF_NUM_PHASES),
                 ("time_count", c_i64 * HIKF_NUM_PHASES)]
 
 
@@ -79,6 +80,7 @@ _SIGS = {
     "hikf_init": (c_i32, [_P(hikf_problem), _P(hikf_options), c_vp, c_sz, c_vp, c_sz, c_vp,
                           _P(c_vp)]),
     "hikf_step": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "hikf_step_batch": (c_i32, [_P(c_vp), _P(c_vp), _P(c_vp), _P(c_vp), c_i32, c_vp]),
     "hikf_query": (c_i32, [c_vp, _P(hikf_stats)]),
     "hikf_export_state": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     "hikf_import_state": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
@@ -98,6 +100,7 @@ for _name, (_res, _args) in _SIGS.items():
 hikf_plan = _lib.hikf_plan
 hikf_init = _lib.hikf_init
 hikf_step = _lib.hikf_step
+hikf_step_batch = _lib.hikf_step_batch
 hikf_query = _lib.hikf_query
 hikf_export_state = _lib.hikf_export_state
 hikf_import_state = _lib.hikf_import_state

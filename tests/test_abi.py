@@ -114,3 +114,13 @@ def test_status_strings():
 def test_ray_operator_fits_abi_layout():
     rp, col, val = synth.crosswell_h(2, 32, 16)
     assert rp.dtype.name == "int64" and col.dtype.name == "int32" and val.dtype.name == "float64"
+
+
+def test_step_batch_rejects_bad_arguments_without_a_device():
+    # argument checks happen before any device call
+    from paper_1404_3816_amd import hikf as H
+    assert H.hikf_step_batch(None, None, None, None, -1, None) == H.HIKF_E_INVALID
+    assert H.hikf_step_batch(None, None, None, None, 0, None) == H.HIKF_OK
+    arr = ctypes.c_void_p * 2
+    assert H.hikf_step_batch(arr(None, None), arr(None, None), None, None, 2,
+                             None) == H.HIKF_E_INVALID

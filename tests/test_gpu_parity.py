@@ -23,7 +23,7 @@ def _gpu():
     torch = pytest.importorskip("torch")
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    import paper_1404_3816_amd  # noqa: F401  (fails loudly without libhikf.so)
+    from paper_1404_3816_amd import hikf  # noqa: F401  (fails loudly without libhikf.so)
 
 
 def _elementwise_ok(gpu, ref, rtol, atol_rel):
