@@ -152,22 +152,24 @@ k_reduce_g(int p, int cpr, const double *partial, double *G, double *hvec, const
 // ends up holding, so the epilogue needs no second read of C or C_Q.  S^{-1}
 // is streamed through a double-buffered LDS slab of 16 rows, prefetched into
 // registers one block ahead; LDS operands are read two MFMAs ahead.
-template <int NT, int CS>
+template <int NT, int CS, int RG_>
 struct RowSplit {
-    static constexpr int RG = 8 / CS;
+    static constexpr int RG = RG_;
+    static constexpr int NTH = 64 * CS * RG_;  // threads of the workgroup
     static constexpr int P = NT * 16;
     static constexpr int LDB = P + 16;          // row pitch of the LDS slab (doubles)
     static constexpr int SLAB = 16 * LDB;
-    static constexpr int PER = (16 * P + 511) / 512;  // slab doubles per thread
+    static constexpr int PER = (16 * P + NTH - 1) / NTH;  // slab doubles per thread
     static constexpr int t0(int c) { return (c * NT + CS - 1) / CS; }
 };
 
-template <typename TQ, int NT, int CS, int PART>
+template <typename TQ, int NT, int CS, int RG_, int PART>
 __device__ __forceinline__ void rowpass_part(double *sB, double *red, int64_t m, double *C,
                                              const TQ *CQ, const double *Sinv, const double *nu,
                                              const double *rdiag) {
-    using RS = RowSplit<NT, CS>;
+    using RS = RowSplit<NT, CS, RG_>;
     constexpr int RG = RS::RG, P = RS::P, LDB = RS::LDB, SLAB = RS::SLAB, PER = RS::PER;
+    constexpr int NTH = RS::NTH;
     constexpr int T0 = RS::t0(PART);
     constexpr int T1 = RS::t0(PART + 1);
     constexpr int NH = T1 - T0;
@@ -190,7 +192,7 @@ __device__ __forceinline__ void rowpass_part(double *sB, double *red, int64_t m,
 
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-        const int idx = tid + 512 * u, rr = idx / P, c = idx % P;
+        const int idx = tid + NTH * u, rr = idx / P, c = idx % P;
         if (idx < 16 * P) sB[rr * LDB + c] = Sinv[int64_t(rr) * P + c];
     }
 #pragma unroll
@@ -207,7 +209,7 @@ __device__ __forceinline__ void rowpass_part(double *sB, double *red, int64_t m,
             // slab first: it is needed first (end of this block), C_prior next
 #pragma unroll
             for (int u = 0; u < PH; ++u) {
-                const int idx = tid + 512 * u, rr = idx / P, c = idx % P;
+                const int idx = tid + NTH * u, rr = idx / P, c = idx % P;
                 if (idx < 16 * P) bpre[u] = Sinv[int64_t(16 * (kb + 1) + rr) * P + c];
             }
 #pragma unroll
@@ -239,12 +241,12 @@ __device__ __forceinline__ void rowpass_part(double *sB, double *red, int64_t m,
                     // the target buffer was last read before the previous barrier
 #pragma unroll
                     for (int u = 0; u < PH; ++u) {
-                        const int idx = tid + 512 * u, rr = idx / P, c = idx % P;
+                        const int idx = tid + NTH * u, rr = idx / P, c = idx % P;
                         if (idx < 16 * P) sB[((kb + 1) & 1) * SLAB + rr * LDB + c] = bpre[u];
                     }
 #pragma unroll
                     for (int u = PH; u < PER; ++u) {
-                        const int idx = tid + 512 * u, rr = idx / P, c = idx % P;
+                        const int idx = tid + NTH * u, rr = idx / P, c = idx % P;
                         if (idx < 16 * P) bpre[u - PH] = Sinv[int64_t(16 * (kb + 1) + rr) * P + c];
                     }
                 }
@@ -254,7 +256,7 @@ __device__ __forceinline__ void rowpass_part(double *sB, double *red, int64_t m,
             constexpr int U0 = PH < PER ? PH : 0;
 #pragma unroll
             for (int u = U0; u < PER; ++u) {
-                const int idx = tid + 512 * u, rr = idx / P, c = idx % P;
+                const int idx = tid + NTH * u, rr = idx / P, c = idx % P;
                 if (idx < 16 * P) sB[((kb + 1) & 1) * SLAB + rr * LDB + c] = bpre[u - U0];
             }
         }
@@ -293,25 +295,24 @@ __device__ __forceinline__ void rowpass_part(double *sB, double *red, int64_t m,
     }
 }
 
-template <typename TQ, int NT, int CS>
-__global__ void __launch_bounds__(512)
+template <typename TQ, int NT, int CS, int RG>
+__global__ void __launch_bounds__(64 * CS * RG)
 k_rowpass(int64_t m, double *C, const TQ *CQ, const double *Sinv, const double *nu,
           const double *rdiag, double *xhat, double *var, double kdiag, const int *status,
           unsigned long long *negvar) {
-    using RS = RowSplit<NT, CS>;
-    constexpr int RG = RS::RG;
+    using RS = RowSplit<NT, CS, RG>;
     __shared__ double sB[2 * RS::SLAB];
-    __shared__ double red[8 * 16 * 2];
+    __shared__ double red[CS * RG * 16 * 2];
     if (status[kStStep] != HIKF_OK) return;
     const int part = (threadIdx.x >> 6) / RG;
     if (part == 0)
-        rowpass_part<TQ, NT, CS, 0>(sB, red, m, C, CQ, Sinv, nu, rdiag);
+        rowpass_part<TQ, NT, CS, RG, 0>(sB, red, m, C, CQ, Sinv, nu, rdiag);
     else if (part == 1)
-        rowpass_part<TQ, NT, CS, 1>(sB, red, m, C, CQ, Sinv, nu, rdiag);
+        rowpass_part<TQ, NT, CS, RG, 1>(sB, red, m, C, CQ, Sinv, nu, rdiag);
     else if (CS > 2 && part == 2)
-        rowpass_part<TQ, NT, CS, (CS > 2 ? 2 : 0)>(sB, red, m, C, CQ, Sinv, nu, rdiag);
+        rowpass_part<TQ, NT, CS, RG, (CS > 2 ? 2 : 0)>(sB, red, m, C, CQ, Sinv, nu, rdiag);
     else if (CS > 3)
-        rowpass_part<TQ, NT, CS, (CS > 3 ? 3 : 0)>(sB, red, m, C, CQ, Sinv, nu, rdiag);
+        rowpass_part<TQ, NT, CS, RG, (CS > 3 ? 3 : 0)>(sB, red, m, C, CQ, Sinv, nu, rdiag);
     __syncthreads();
     const int tid = threadIdx.x;
     if (tid < 16 * RG) {
@@ -334,9 +335,10 @@ k_rowpass(int64_t m, double *C, const TQ *CQ, const double *Sinv, const double *
 template <typename TQ, int NT>
 void launch_rowpass_nt(const Geometry &g, const Layout &lay, char *res, hipStream_t s) {
     constexpr int CS = NT <= 16 ? 2 : 4;
-    constexpr int rows = 16 * (8 / CS);
+    constexpr int RG = NT <= 16 ? 4 : 2;     // 8 waves; 4-wave workgroups of 32 rows measured slower
+    constexpr int rows = 16 * RG;
     const unsigned blocks = unsigned((g.m + rows - 1) / rows);
-    hipLaunchKernelGGL((k_rowpass<TQ, NT, CS>), dim3(blocks), dim3(512), 0, s, g.m,
+    hipLaunchKernelGGL((k_rowpass<TQ, NT, CS, RG>), dim3(blocks), dim3(64 * CS * RG), 0, s, g.m,
                        reinterpret_cast<double *>(res + lay.C),
                        reinterpret_cast<const TQ *>(res + lay.CQ),
                        reinterpret_cast<const double *>(res + lay.sinv),
