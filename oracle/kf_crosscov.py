@@ -27,19 +27,23 @@ def _as_operator(H):
     return H.tocsr() if sp.issparse(H) else np.asarray(H, np.float64)
 
 
-def crosscov_kf(CQ, H, R, x0, C0, var0, qdiag, ys, return_C=False):
+def crosscov_kf(CQ, H, R, x0, C0, var0, qdiag, ys, return_C=False, return_Z=False):
     """Run tier B over the rows of ``ys``.
 
     CQ (m,p) = Q H^T; H (p,m) dense or scipy-sparse; R (p,p); x0 (m,);
     C0 (m,p) = P0 H^T; var0 (m,) = diag P0; qdiag = K(0) (scalar or (m,)).
-    Returns (xs, variances) of shape (steps, m) [and the final C].
+    Returns (xs, variances) of shape (steps, m) [and the final C] [and the
+    list of Z_s = C_{s|s-1} L_s^{-T}, S_s = L_s L_s^T].  The covariance update
+    P_{s|s} = P_{s|s-1} - K_s H P_{s|s-1} equals P_{s|s-1} - Z_s Z_s^T, so
+    P_t = P_0 + t Q - sum_s Z_s Z_s^T can be rebuilt from the Z history
+    without ever holding an m x m matrix during the filter.
     """
     H = _as_operator(H)
     R = np.asarray(R, np.float64)
     C = np.array(C0, np.float64, copy=True)
     x = np.array(x0, np.float64, copy=True)
     var = np.array(var0, np.float64, copy=True)
-    xs, vs = [], []
+    xs, vs, zs = [], [], []
     for y in np.atleast_2d(ys):
         C = C + CQ                                   # predict
         var = var + qdiag
@@ -47,14 +51,20 @@ def crosscov_kf(CQ, H, R, x0, C0, var0, qdiag, ys, return_C=False):
         S = 0.5 * (G + G.T) + R
         cf = sla.cho_factor(S, lower=True)
         K = sla.cho_solve(cf, C.T).T                 # C S^{-1}
+        if return_Z:
+            L = np.tril(cf[0])
+            zs.append(sla.solve_triangular(L, C.T, lower=True).T)
         x = x + K @ (y - H @ x)
         var = var - np.einsum("ij,ij->i", K, C)
         C = C - K @ G
         xs.append(x.copy())
         vs.append(var.copy())
+    out = (np.array(xs), np.array(vs))
     if return_C:
-        return np.array(xs), np.array(vs), C
-    return np.array(xs), np.array(vs)
+        out = out + (C,)
+    if return_Z:
+        out = out + (zs,)
+    return out
 
 
 def crosscov_gain_identity(C_prior, G, R):

@@ -144,6 +144,18 @@ def test_tier_b_equals_tier_a_crosswell():
         assert _rel(vb[k], va[k]) < 1e-11
 
 
+def test_tier_b_z_history_rebuilds_tier_a_covariance():
+    # P_t = P_0 + t Q - sum_s Z_s Z_s^T with Z_s = C_{s|s-1} L_s^{-T}: the
+    # cross-covariance filter carries enough to rebuild tier A's full P_t
+    Q, H, R, P0, mu0, ys = _small_problem()
+    _, _, Ps = kf_dense.dense_kf(Q, H, R, mu0, P0, ys)
+    _, _, zs = kf_crosscov.crosscov_kf(Q @ H.T, H, R, mu0, P0 @ H.T, np.diag(P0),
+                                       np.diag(Q), ys, return_Z=True)
+    for t in range(1, len(ys) + 1):
+        P = P0 + t * Q - sum(z @ z.T for z in zs[:t])
+        assert _rel(P, Ps[t - 1]) < 1e-12, t
+
+
 def test_tier_b_row_subset_is_exact():
     # rows outside the ray cells do not influence the update (Sec. 3.1)
     w = synth.workload("crosswell-32x32-p16")
