@@ -144,79 +144,106 @@ k_reduce_g(int p, int cpr, const double *partial, double *G, double *hvec, const
 // v_mfma_f64_16x16x4 computes D += A B with lane l supplying A[l%16][l/16] and
 // B[l/16][l%16] and holding D[l/16 + 4 r][l%16] (the FP64 variant interleaves
 // the rows).  The kernel computes tiles of K^T = S^{-1} C_prior^T: A is a
-// 16 x 4 slab of S^{-1} (symmetric) read from LDS and B is 4 values of the
-// lane's own row of C_prior, so the result K[row][16 t + l/16 + 4 r] stays in
-// the lane that owns the row.  Within the 16-wide k block kb, MFMA step s
-// pairs lane group q = l/16 with k = 16 kb + q + 4 s; the C_prior values a
-// lane loads in its own column part are then exactly the columns of K it
-// ends up holding, so the epilogue needs no second read of C or C_Q.  S^{-1}
-// is streamed through a double-buffered LDS slab of 16 rows, prefetched into
-// registers one block ahead; LDS operands are read two MFMAs ahead.
+// 16 x 4 piece of a slab of S^{-1} (symmetric) read from LDS and B is 4
+// values of the lane's own row of C_prior, so the result stays in the lane
+// that owns the row.  Columns are assigned so that every lane handles pairs
+// of adjacent columns: with q = l/16, lane l holds, for tile t and r = 0..3,
+//     K[row][16 t + col(q, r)],   col(q, r) = 8 (r/2) + 2 q + r % 2,
+// (output row i = q + 4 r of the MFMA tile is column col(i%4, i/4)), and the
+// MFMA step s of k block kb pairs lane group q with k = 16 kb + col(q, s).
+// The C_prior values a lane loads in its own column part are then exactly
+// the columns of K it ends up holding (no second read of C or C_Q), and every
+// global access of C, C_Q and the stores of C are 16-byte (two-column)
+// vector accesses.  S^{-1} is streamed through a double-buffered LDS slab of
+// 16 rows (row pitch P + 8 doubles: lane groups q and q + 1 read rows two
+// apart, which then fall on disjoint banks), prefetched into registers one
+// block ahead as 16-byte loads; LDS operands are read two MFMAs ahead.
 template <int NT, int CS, int RG_>
 struct RowSplit {
     static constexpr int RG = RG_;
     static constexpr int NTH = 64 * CS * RG_;  // threads of the workgroup
     static constexpr int P = NT * 16;
-    static constexpr int LDB = P + 16;          // row pitch of the LDS slab (doubles)
+    static constexpr int LDB = P + 8;           // row pitch of the LDS slab (doubles)
     static constexpr int SLAB = 16 * LDB;
-    static constexpr int PER = (16 * P + NTH - 1) / NTH;  // slab doubles per thread
+    static constexpr int PER2 = (8 * P + NTH - 1) / NTH;  // slab column pairs per thread
     static constexpr int t0(int c) { return (c * NT + CS - 1) / CS; }
 };
+
+// column offset inside a 16-column tile of MFMA output row i (see above)
+__device__ __forceinline__ constexpr int rp_col(int q, int r) { return 8 * (r >> 1) + 2 * q + (r & 1); }
+
+template <typename TQ> struct Pair;
+template <> struct Pair<float> { typedef float v2 __attribute__((ext_vector_type(2))); };
+template <> struct Pair<double> { typedef double v2 __attribute__((ext_vector_type(2))); };
+typedef double dv2 __attribute__((ext_vector_type(2)));
 
 template <typename TQ, int NT, int CS, int RG_, int PART>
 __device__ __forceinline__ void rowpass_part(double *sB, double *red, int64_t m, double *C,
                                              const TQ *CQ, const double *Sinv, const double *nu,
                                              const double *rdiag) {
     using RS = RowSplit<NT, CS, RG_>;
-    constexpr int RG = RS::RG, P = RS::P, LDB = RS::LDB, SLAB = RS::SLAB, PER = RS::PER;
+    typedef typename Pair<TQ>::v2 qv2;
+    constexpr int RG = RS::RG, P = RS::P, LDB = RS::LDB, SLAB = RS::SLAB, PER2 = RS::PER2;
     constexpr int NTH = RS::NTH;
     constexpr int T0 = RS::t0(PART);
     constexpr int T1 = RS::t0(PART + 1);
     constexpr int NH = T1 - T0;
     constexpr int NQ = 4 * NH;                  // (s, t) pairs per k block
-    constexpr int PH = PER > 8 && NQ >= 4 ? (PER + 1) / 2 : PER;  // slab doubles in flight
+    constexpr int PH = PER2 > 4 && NQ >= 4 ? (PER2 + 1) / 2 : PER2;  // slab pairs in flight
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, q = lane >> 4, grp = wave % RG;
     const int64_t row = int64_t(blockIdx.x) * (16 * RG) + grp * 16 + lr;
     const bool ok = row < m;
-    const int64_t rbase = (ok ? row : 0) * P;
+    const int64_t rbase = (ok ? row : 0) * P + 2 * q;
+    // A operand column of this lane inside a tile, and its slab row for step s
+    const int acol = rp_col(lr & 3, lr >> 2);
 
-    double keep[NH > 0 ? NH : 1][4];            // C_prior[row][16 t + q + 4 s], t in [T0, T1)
+    double keep[NH > 0 ? NH : 1][4];            // C_prior[row][16 t + col(q, s)], t in [T0, T1)
     double cur[4];
-    double nc[4];                               // next block's C and C_Q, kept apart so the
-    TQ nq[4];                                   // loads are waited for only where they are used
-    double bpre[PH];
+    dv2 nc[2];                                  // next block's C and C_Q, kept apart so the
+    qv2 nq[2];                                  // loads are waited for only where they are used
+    dv2 bpre[PH];
     d4 acc[NH > 0 ? NH : 1];
 #pragma unroll
     for (int t = 0; t < NH; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
 
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        const int idx = tid + NTH * u, rr = idx / P, c = idx % P;
-        if (idx < 16 * P) sB[rr * LDB + c] = Sinv[int64_t(rr) * P + c];
+    for (int u = 0; u < PER2; ++u) {
+        const int idx = tid + NTH * u, rr = idx / (P / 2), c = 2 * (idx % (P / 2));
+        if (idx < 8 * P)
+            *reinterpret_cast<dv2 *>(sB + rr * LDB + c) =
+                *reinterpret_cast<const dv2 *>(Sinv + int64_t(rr) * P + c);
     }
 #pragma unroll
-    for (int s = 0; s < 4; ++s) cur[s] = ok ? C[rbase + q + 4 * s] + (double)CQ[rbase + q + 4 * s] : 0.0;
+    for (int h = 0; h < 2; ++h) {
+        const dv2 cv = *reinterpret_cast<const dv2 *>(C + rbase + 8 * h);
+        const qv2 qv = *reinterpret_cast<const qv2 *>(CQ + rbase + 8 * h);
+        cur[2 * h] = ok ? cv[0] + (double)qv[0] : 0.0;
+        cur[2 * h + 1] = ok ? cv[1] + (double)qv[1] : 0.0;
+    }
     __syncthreads();
 
 #pragma unroll
     for (int kb = 0; kb < NT; ++kb) {
         if (kb > 0) {
 #pragma unroll
-            for (int s = 0; s < 4; ++s) cur[s] = ok ? nc[s] + (double)nq[s] : 0.0;
+            for (int h = 0; h < 2; ++h) {
+                cur[2 * h] = ok ? nc[h][0] + (double)nq[h][0] : 0.0;
+                cur[2 * h + 1] = ok ? nc[h][1] + (double)nq[h][1] : 0.0;
+            }
         }
         if (kb + 1 < NT) {
             // slab first: it is needed first (end of this block), C_prior next
 #pragma unroll
             for (int u = 0; u < PH; ++u) {
-                const int idx = tid + NTH * u, rr = idx / P, c = idx % P;
-                if (idx < 16 * P) bpre[u] = Sinv[int64_t(16 * (kb + 1) + rr) * P + c];
+                const int idx = tid + NTH * u, rr = idx / (P / 2), c = 2 * (idx % (P / 2));
+                if (idx < 8 * P)
+                    bpre[u] = *reinterpret_cast<const dv2 *>(Sinv + int64_t(16 * (kb + 1) + rr) * P + c);
             }
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int64_t o = rbase + 16 * (kb + 1) + q + 4 * s;
-                nc[s] = C[o];
-                nq[s] = CQ[o];
+            for (int h = 0; h < 2; ++h) {
+                nc[h] = *reinterpret_cast<const dv2 *>(C + rbase + 16 * (kb + 1) + 8 * h);
+                nq[h] = *reinterpret_cast<const qv2 *>(CQ + rbase + 16 * (kb + 1) + 8 * h);
             }
         }
         if (kb >= T0 && kb < T1) {
@@ -224,71 +251,70 @@ __device__ __forceinline__ void rowpass_part(double *sB, double *red, int64_t m,
             for (int s = 0; s < 4; ++s) keep[kb - T0][s] = cur[s];
         }
         if (NH > 0) {
-            const double *B = sB + (kb & 1) * SLAB + q * LDB + lr + 16 * T0;
+            const double *B = sB + (kb & 1) * SLAB + 2 * q * LDB + acol + 16 * T0;
+            // step s reads slab row col(q, s) = 8 (s/2) + 2 q + s % 2
+            auto aop = [&](int i) {
+                constexpr int NHp = NH > 0 ? NH : 1;
+                const int si = i / NHp, ti = i % NHp;
+                return B[(8 * (si >> 1) + (si & 1)) * LDB + 16 * ti];
+            };
             double ring[3];
-            ring[0] = B[0];
-            if (NQ > 1) ring[1] = B[(1 / NH) * 4 * LDB + 16 * (1 % NH)];
+            ring[0] = aop(0);
+            if (NQ > 1) ring[1] = aop(1);
 #pragma unroll
             for (int i = 0; i < NQ; ++i) {
-                if (i + 2 < NQ) {
-                    const int s2 = (i + 2) / NH, t2 = (i + 2) % NH;
-                    ring[(i + 2) % 3] = B[4 * s2 * LDB + 16 * t2];
-                }
+                if (i + 2 < NQ) ring[(i + 2) % 3] = aop(i + 2);
                 const int si = i / NH, ti = i % NH;
                 acc[ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(ring[i % 3], cur[si], acc[ti], 0, 0, 0);
-                if (PH < PER && i == NQ / 2 - 1 && kb + 1 < NT) {
+                if (PH < PER2 && i == NQ / 2 - 1 && kb + 1 < NT) {
                     // wide slabs go in two halves to bound the registers they hold;
                     // the target buffer was last read before the previous barrier
 #pragma unroll
                     for (int u = 0; u < PH; ++u) {
-                        const int idx = tid + NTH * u, rr = idx / P, c = idx % P;
-                        if (idx < 16 * P) sB[((kb + 1) & 1) * SLAB + rr * LDB + c] = bpre[u];
+                        const int idx = tid + NTH * u, rr = idx / (P / 2), c = 2 * (idx % (P / 2));
+                        if (idx < 8 * P)
+                            *reinterpret_cast<dv2 *>(sB + ((kb + 1) & 1) * SLAB + rr * LDB + c) = bpre[u];
                     }
 #pragma unroll
-                    for (int u = PH; u < PER; ++u) {
-                        const int idx = tid + NTH * u, rr = idx / P, c = idx % P;
-                        if (idx < 16 * P) bpre[u - PH] = Sinv[int64_t(16 * (kb + 1) + rr) * P + c];
+                    for (int u = PH; u < PER2; ++u) {
+                        const int idx = tid + NTH * u, rr = idx / (P / 2), c = 2 * (idx % (P / 2));
+                        if (idx < 8 * P)
+                            bpre[u - PH] = *reinterpret_cast<const dv2 *>(Sinv + int64_t(16 * (kb + 1) + rr) * P + c);
                     }
                 }
             }
         }
         if (kb + 1 < NT) {
-            constexpr int U0 = PH < PER ? PH : 0;
+            constexpr int U0 = PH < PER2 ? PH : 0;
 #pragma unroll
-            for (int u = U0; u < PER; ++u) {
-                const int idx = tid + NTH * u, rr = idx / P, c = idx % P;
-                if (idx < 16 * P) sB[((kb + 1) & 1) * SLAB + rr * LDB + c] = bpre[u - U0];
+            for (int u = U0; u < PER2; ++u) {
+                const int idx = tid + NTH * u, rr = idx / (P / 2), c = 2 * (idx % (P / 2));
+                if (idx < 8 * P)
+                    *reinterpret_cast<dv2 *>(sB + ((kb + 1) & 1) * SLAB + rr * LDB + c) = bpre[u - U0];
             }
         }
         __syncthreads();
     }
 
-    // epilogue: lane holds K[row][16 t + q + 4 r] = acc[t - T0][r] and
-    // C_prior[row][16 t + q + 4 r] = keep[t - T0][r]
+    // epilogue: lane holds K[row][16 t + col(q, r)] = acc[t - T0][r] and
+    // C_prior[row][16 t + col(q, r)] = keep[t - T0][r]
     double dv = 0.0, dx = 0.0;
 #pragma unroll
     for (int t = 0; t < NH; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int c = 16 * (T0 + t) + q + 4 * r;
-            const double kv = acc[t][r];
-            dv += kv * keep[t][r];
-            dx += kv * nu[c];
+        for (int h = 0; h < 2; ++h) {
+            const int c = 16 * (T0 + t) + 8 * h + 2 * q;
+            const dv2 nv = *reinterpret_cast<const dv2 *>(nu + c);
+            const dv2 rv = *reinterpret_cast<const dv2 *>(rdiag + c);
+            const double k0 = acc[t][2 * h], k1 = acc[t][2 * h + 1];
+            dv += k0 * keep[t][2 * h] + k1 * keep[t][2 * h + 1];
+            dx += k0 * nv[0] + k1 * nv[1];
+            if (ok) *reinterpret_cast<dv2 *>(C + rbase - 2 * q + c) = dv2{k0 * rv[0], k1 * rv[1]};
         }
     dv += __shfl_xor(dv, 16, 64);
     dx += __shfl_xor(dx, 16, 64);
     dv += __shfl_xor(dv, 32, 64);
     dx += __shfl_xor(dx, 32, 64);
-    if (ok) {
-        double *cout = C + row * P;
-#pragma unroll
-        for (int t = 0; t < NH; ++t)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int c = 16 * (T0 + t) + q + 4 * r;
-                cout[c] = acc[t][r] * rdiag[c];
-            }
-    }
     if (q == 0) {
         red[((PART * RG + grp) * 16 + lr) * 2 + 0] = dv;
         red[((PART * RG + grp) * 16 + lr) * 2 + 1] = dx;
@@ -301,7 +327,7 @@ k_rowpass(int64_t m, double *C, const TQ *CQ, const double *Sinv, const double *
           const double *rdiag, double *xhat, double *var, double kdiag, const int *status,
           unsigned long long *negvar) {
     using RS = RowSplit<NT, CS, RG>;
-    __shared__ double sB[2 * RS::SLAB];
+    __shared__ __align__(16) double sB[2 * RS::SLAB];
     __shared__ double red[CS * RG * 16 * 2];
     if (status[kStStep] != HIKF_OK) return;
     const int part = (threadIdx.x >> 6) / RG;
