@@ -305,12 +305,38 @@ __device__ __forceinline__ void rowpass_part(double *sB, double *red, int64_t m,
         for (int h = 0; h < 2; ++h) {
             const int c = 16 * (T0 + t) + 8 * h + 2 * q;
             const dv2 nv = *reinterpret_cast<const dv2 *>(nu + c);
-            const dv2 rv = *reinterpret_cast<const dv2 *>(rdiag + c);
             const double k0 = acc[t][2 * h], k1 = acc[t][2 * h + 1];
             dv += k0 * keep[t][2 * h] + k1 * keep[t][2 * h + 1];
             dx += k0 * nv[0] + k1 * nv[1];
-            if (ok) *reinterpret_cast<dv2 *>(C + rbase - 2 * q + c) = dv2{k0 * rv[0], k1 * rv[1]};
         }
+    // C <- K R.  A row's 16 columns of tile t sit in its 4 lanes as two
+    // 64-byte halves (h = 0: columns 0..7, h = 1: 8..15).  Lanes of rows 2j
+    // and 2j + 1 (adjacent lanes) swap one half each (DPP quad permutation
+    // [1,0,3,2]), so that every store instruction writes whole 128-byte rows:
+    // first rows 2j (the even lane's h = 0 and, from the odd lane, the even
+    // row's h = 1), then rows 2j + 1.
+    {
+        const bool odd = lr & 1;
+        const int64_t r0 = row - odd;
+        auto swap_pair = [](double x) {
+            int2 v = __builtin_bit_cast(int2, x);
+            v.x = __builtin_amdgcn_mov_dpp(v.x, 0xB1, 0xF, 0xF, false);
+            v.y = __builtin_amdgcn_mov_dpp(v.y, 0xB1, 0xF, 0xF, false);
+            return __builtin_bit_cast(double, v);
+        };
+#pragma unroll
+        for (int t = 0; t < NH; ++t) {
+            const int c0 = 16 * (T0 + t) + 2 * q;
+            const dv2 ra = *reinterpret_cast<const dv2 *>(rdiag + c0);
+            const dv2 rb = *reinterpret_cast<const dv2 *>(rdiag + c0 + 8);
+            const dv2 a = dv2{acc[t][0] * ra[0], acc[t][1] * ra[1]};   // h = 0 of own row
+            const dv2 b = dv2{acc[t][2] * rb[0], acc[t][3] * rb[1]};   // h = 1 of own row
+            const dv2 g = dv2{swap_pair(odd ? a[0] : b[0]), swap_pair(odd ? a[1] : b[1])};
+            const int cc = c0 + (odd ? 8 : 0);
+            if (r0 < m) *reinterpret_cast<dv2 *>(C + r0 * P + cc) = odd ? g : a;
+            if (r0 + 1 < m) *reinterpret_cast<dv2 *>(C + (r0 + 1) * P + cc) = odd ? b : g;
+        }
+    }
     dv += __shfl_xor(dv, 16, 64);
     dx += __shfl_xor(dx, 16, 64);
     dv += __shfl_xor(dv, 32, 64);
