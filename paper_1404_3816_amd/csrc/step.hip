@@ -91,11 +91,18 @@ __global__ void k_widen(int64_t n, const TQ *src, double *dst) {
 }
 
 // ---------------------------------------------------------------- 1. gather
+// One workgroup per (ray a, chunk ch of its nonzeros); thread t < p/2 sums
+// columns 2t and 2t + 1 of sum_e H_ae C_prior[col_e][.] with 16-byte loads,
+// thread p/2 sums H_ae x_hat[col_e].  Eight nonzeros are loaded before any is
+// accumulated, so the row loads of a chunk are in flight together.
 template <typename TQ>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 k_gather(int p, int cpr, int64_t m, int64_t nnz, const int64_t *rowptr, const int32_t *col,
          const double *val, const double *C, const TQ *CQ, const double *xhat,
          double *partial, const int *status) {
+    typedef double dv2 __attribute__((ext_vector_type(2)));
+    typedef TQ qv2 __attribute__((ext_vector_type(2)));
+    constexpr int U = 8;
     if (status[kStInit] != 0) return;
     const int a = blockIdx.x, ch = blockIdx.y;
     int64_t r0 = rowptr[a], r1 = rowptr[a + 1];
@@ -104,16 +111,45 @@ k_gather(int p, int cpr, int64_t m, int64_t nnz, const int64_t *rowptr, const in
     const int64_t len = r1 - r0;
     const int64_t e0 = r0 + len * ch / cpr, e1 = r0 + len * (ch + 1) / cpr;
     double *out = partial + (int64_t(a) * cpr + ch) * (p + 1);
-    for (int b = threadIdx.x; b <= p; b += blockDim.x) {
-        double acc = 0.0;
-        for (int64_t e = e0; e < e1; ++e) {
-            int64_t c = col[e];
-            if (c < 0 || c >= m) continue;
-            double v = val[e];
-            double x = b < p ? C[c * p + b] + (double)CQ[c * p + b] : xhat[c];
-            acc += v * x;
+    const int half = p / 2;
+    for (int t = threadIdx.x; t <= half; t += blockDim.x) {
+        if (t == half) {
+            double acc = 0.0;
+            for (int64_t e = e0; e < e1; ++e) {
+                const int64_t c = col[e];
+                if (c >= 0 && c < m) acc += val[e] * xhat[c];
+            }
+            out[p] = acc;
+            continue;
         }
-        out[b] = acc;
+        dv2 acc = dv2{0.0, 0.0};
+        int64_t e = e0;
+        for (; e + U <= e1; e += U) {
+            dv2 x[U];
+            double w[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t c = col[e + u];
+                const bool ok = c >= 0 && c < m;
+                const int64_t o = (ok ? c : 0) * p + 2 * t;
+                const dv2 cv = *reinterpret_cast<const dv2 *>(C + o);
+                const qv2 qv = *reinterpret_cast<const qv2 *>(CQ + o);
+                x[u] = dv2{cv[0] + (double)qv[0], cv[1] + (double)qv[1]};
+                w[u] = ok ? val[e + u] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc += w[u] * x[u];
+        }
+        for (; e < e1; ++e) {
+            const int64_t c = col[e];
+            if (c < 0 || c >= m) continue;
+            const int64_t o = c * p + 2 * t;
+            const dv2 cv = *reinterpret_cast<const dv2 *>(C + o);
+            const qv2 qv = *reinterpret_cast<const qv2 *>(CQ + o);
+            acc += val[e] * dv2{cv[0] + (double)qv[0], cv[1] + (double)qv[1]};
+        }
+        out[2 * t] = acc[0];
+        out[2 * t + 1] = acc[1];
     }
 }
 
@@ -421,7 +457,8 @@ hipError_t run_step(const Geometry &g, const Layout &lay, char *res, const doubl
                     hipStream_t s, Timing *tm) {
     const int p = g.p;
     tbegin(tm, HIKF_PHASE_GATHER, s);
-    hipLaunchKernelGGL(k_gather<TQ>, dim3(p, g.cpr), dim3(256), 0, s, p, g.cpr, g.m, g.nnz,
+    const unsigned gthreads = unsigned(((p / 2 + 1) + 63) / 64 * 64);
+    hipLaunchKernelGGL(k_gather<TQ>, dim3(p, g.cpr), dim3(gthreads), 0, s, p, g.cpr, g.m, g.nnz,
                        reinterpret_cast<const int64_t *>(res + lay.rowptr),
                        reinterpret_cast<const int32_t *>(res + lay.col),
                        reinterpret_cast<const double *>(res + lay.val),
