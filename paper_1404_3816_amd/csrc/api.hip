@@ -37,8 +37,6 @@ Layout make_layout(const Geometry &g) {
     L.negvar = take(8);
     L.ybuf = take(p * 8);
     L.psA = take(size_t(g.pp) * g.pp * 8);
-    L.psL = take(size_t(g.pp) * g.pp * 8);
-    L.psD = take(size_t(g.pp) * 32 * 8);
     L.pivs = take(size_t(g.pp / 32) * 8);
     L.resident_bytes = off;
 

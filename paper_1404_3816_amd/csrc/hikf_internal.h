@@ -82,7 +82,7 @@ struct Layout {
     // resident
     size_t C, CQ, xhat, var, sinv, xbuf, G, hvec, nu, partial;
     size_t rowptr, col, val, rdiag, status, minpiv, steps, negvar, ybuf;
-    size_t psA, psL, psD, pivs;               // blocked p-space work arrays
+    size_t psA, pivs;                         // p-space ping-pong buffer (with xbuf), pivots
     size_t resident_bytes;
     // scratch
     size_t W, sleaf, schild, m2l, lev_off;   // lev_off: start of M/L storage

@@ -1,21 +1,25 @@
 // p x p part of one assimilation step (Algorithm Algorithm_HiKF, gain row):
-// S = (G + G^T)/2 + R with G = H C_prior, its Cholesky factor S = L L^T,
-// X = L^{-1} and S^{-1} = X^T X, plus the innovation nu = y - h.
+// S = (G + G^T)/2 + R with G = H C_prior, S^{-1}, and the innovation
+// nu = y - h.
 //
-// Blocked with 32 x 32 FP64 blocks (the matrix is padded to PP = 32 NBk with
-// an identity block), every block product on v_mfma_f64_16x16x4 with one
-// 256-thread workgroup per block (each wave owns one 16 x 16 tile):
-//   k_ps_factor   (1 WG)     : checks y, forms nu, factors block (0,0):
-//                              L00 and D0 = L00^{-1}.
-//   k_ps_update(kb)          : one WG per block (i, j), kb < j <= i: panel
-//                              blocks L_ik = A_ik D_kb^T, L_jk = A_jk D_kb^T,
-//                              A_ij -= L_ik L_jk^T; the WG of block
-//                              (kb+1, kb+1) then factors it (L, D for kb+1).
-//   k_ps_trtri    (NBk WGs)  : column j of X: X_jj = D_j,
-//                              X_ij = -D_i sum_{k=j}^{i-1} L_ik X_kj.
-//   k_ps_lauum    (one WG per lower block): S^{-1}_ij = sum_{k>=i} X_ki^T X_kj.
-// A failed pivot (not > 0 or not finite) sets HIKF_E_NOT_SPD; every later
-// kernel, and the row pass, then does nothing, so the state is untouched.
+// S^{-1} comes from the symmetric sweep operator (block Gauss-Jordan
+// elimination without pivoting, valid for SPD matrices) over 32 x 32 FP64
+// blocks; the matrix is padded to PP = 32 NBk with an identity block.
+// Sweeping pivot block k maps
+//     A_kk -> -A_kk^{-1},        A_ik -> A_ik A_kk^{-1},   A_kj -> A_kk^{-1} A_kj,
+//     A_ij -> A_ij - A_ik A_kk^{-1} A_kj                       (i, j != k),
+// and after all blocks the matrix is -S^{-1}.  The pivots are those of the
+// Cholesky factorisation (LDL^T), so S is SPD exactly when every pivot is
+// positive, and sqrt(pivot) is the Cholesky diagonal.
+//   k_ps_sweep(k), one launch per pivot block, one 256-thread workgroup per
+//   block (i, j) of the matrix (ping-pong between two PP x PP buffers):
+//   wave 0 sweeps the 32 scalar pivots of block (k, k) in registers (no
+//   barriers: column and row j pass through wave-private LDS), then the four
+//   waves form the block's new value on v_mfma_f64_16x16x4 (each wave owns
+//   one 16 x 16 tile).  Launch 0 also checks y and forms nu; the last launch
+//   writes S^{-1}.
+// A non-positive or non-finite pivot sets HIKF_E_NOT_SPD; every later
+// launch, and the row pass, then does nothing, so the state is untouched.
 #include "hikf_internal.h"
 
 namespace hikf {
@@ -26,7 +30,6 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int BS = 32;            // block size
 constexpr int BP = 36;            // LDS pitch of a block (doubles)
 constexpr int NT = 256;           // threads per workgroup
-constexpr int kMaxNbk = kMaxP / BS;
 
 // element (r, c) of block (bi, bj) of S = (G + G^T)/2 + R, identity beyond p
 __device__ __forceinline__ double s_elem(const double *G, const double *rdiag, int p, int i, int j) {
@@ -92,213 +95,142 @@ __device__ __forceinline__ void tile_write(double *s, d4 v) {
     for (int r = 0; r < 4; ++r) s[(16 * wi + q + 4 * r) * BP + 16 * wj + lr] = v[r];
 }
 
-// Factor the 32 x 32 SPD block in sA (in place) into L (lower, zero above)
-// and write D = L^{-1} into sD.  Returns false on a failed pivot; *piv gets
-// the smallest diagonal of L (or the failing pivot).  Uniform across the WG.
-__device__ bool blk_factor(double *sA, double *sD, double *piv) {
-    const int t = threadIdx.x, c = t % BS, r0 = t / BS;      // 4 rows per thread: r0 + 8 u
+// Sweep the 32 x 32 block in sP (pitch BP) over its 32 pivots, in place:
+// on return it holds -A^{-1}.  Run by one wave: lane l keeps column l % 32,
+// rows 16 (l / 32) .. +15, in registers; cbuf / rbuf (32 doubles each,
+// private to the wave) carry pivot column and row j to every lane.  Returns
+// false on a non-positive or non-finite pivot; *pmin gets the smallest pivot.
+__device__ bool blk_sweep_wave(double *sP, double *cbuf, double *rbuf, double *pmin) {
+    const int lane = threadIdx.x & 63, c = lane & 31, h = lane >> 5;
+    double a[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) a[e] = sP[(16 * h + e) * BP + c];
     double mp = 1.0e300;
+    bool ok = true;
+#pragma unroll
     for (int j = 0; j < BS; ++j) {
-        const double d2 = sA[j * BP + j];
-        if (!(d2 > 0.0) || !isfinite(d2)) { *piv = d2; return false; }
-        mp = fmin(mp, d2);
-        const double inv = 1.0 / d2;
-        const double acj = sA[c * BP + j];
+        if (c == j) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = r0 + 8 * u;
-            if (c > j && c <= i) sA[i * BP + c] -= sA[i * BP + j] * acj * inv;
+            for (int e = 0; e < 16; ++e) cbuf[16 * h + e] = a[e];
         }
-        __syncthreads();
-    }
-    // scale the columns: L_ij = A_ij / sqrt(A_jj); zero the upper part
-    double vals[4];
+        if (h == (j >> 4)) rbuf[c] = a[j & 15];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const double piv = cbuf[j];
+        ok = ok && piv > 0.0 && isfinite(piv);
+        mp = fmin(mp, piv);
+        const double inv = 1.0 / piv;
+        const double rj = rbuf[c] * inv;                 // A_jc / A_jj
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int i = r0 + 8 * u;
-        vals[u] = i >= c ? sA[i * BP + c] / sqrt(sA[c * BP + c]) : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int i = r0 + 8 * u;
-        sA[i * BP + c] = vals[u];
-        sD[i * BP + c] = i == c ? 1.0 : 0.0;
-    }
-    *piv = sqrt(mp);
-    __syncthreads();
-    // D = L^{-1}: row k of D is final once divided by L_kk; then rows i > k
-    // subtract L_ik D_k.
-    for (int k = 0; k < BS; ++k) {
-        if (k % 8 == r0) sD[k * BP + c] /= sA[k * BP + k];
-        __syncthreads();
-        const double dk = sD[k * BP + c];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = r0 + 8 * u;
-            if (i > k) sD[i * BP + c] -= sA[i * BP + k] * dk;
+        for (int e = 0; e < 16; ++e) {
+            const int i = 16 * h + e;
+            const double aij = cbuf[i];
+            if (i == j) a[e] = c == j ? -inv : rj;
+            else a[e] = c == j ? aij * inv : a[e] - aij * rj;
         }
-        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
-    return true;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) sP[(16 * h + e) * BP + c] = a[e];
+    *pmin = mp;
+    return ok;
 }
 
 struct PsArgs {
     int p, PP, nbk;
     const double *G, *rdiag, *y, *hvec;
-    double *A, *L, *D, *X, *Sinv, *nu, *pivs, *minpiv;
+    double *A, *X, *Sinv, *nu, *pivs, *minpiv;
     int *status;
     long long *steps;
 };
 
-__global__ void __launch_bounds__(NT) k_ps_factor(PsArgs a) {
-    __shared__ double sA[BS * BP];
-    __shared__ double sD[BS * BP];
+__global__ void __launch_bounds__(NT) k_ps_sweep(PsArgs a, int k) {
+    __shared__ double sP[BS * BP];                // -A_kk^{-1} after the sweep
+    __shared__ double sI[BS * BP];                // A_ik (or A_kk)
+    __shared__ double sJ[BS * BP];                // A_kj
+    __shared__ double sT[BS * BP];
+    __shared__ double bufs[2 * BS];
+    __shared__ int okflag;
     const int t = threadIdx.x;
-    int bad = a.status[kStInit] != 0;
-    for (int i = t; i < a.p; i += NT)
-        if (!isfinite(a.y[i])) bad = 1;
-    bad = __syncthreads_or(bad);
-    if (bad) {
-        if (t == 0) a.status[kStStep] = HIKF_E_INVALID;
+    if (k == 0) {
+        // a new step: clear the status (the previous step's may be a failure)
+        if (a.status[kStInit] != 0) {
+            if (blockIdx.x == 0 && t == 0) a.status[kStStep] = HIKF_E_INVALID;
+            return;
+        }
+        if (blockIdx.x == 0) {
+            int bad = 0;
+            for (int i = t; i < a.p; i += NT) {
+                if (!isfinite(a.y[i])) bad = 1;
+                a.nu[i] = a.y[i] - a.hvec[i];
+            }
+            bad = __syncthreads_or(bad);
+            if (t == 0) a.status[kStStep] = bad ? HIKF_E_INVALID : HIKF_OK;
+            if (bad) return;
+        }
+    } else if (a.status[kStStep] != HIKF_OK) {
         return;
     }
-    for (int i = t; i < a.p; i += NT) a.nu[i] = a.y[i] - a.hvec[i];
-    blk_load(sA, a.A, a.PP, a.G, a.rdiag, a.p, true, 0, 0);
+    const int bi = blockIdx.x / a.nbk, bj = blockIdx.x % a.nbk;
+    const double *src = (k & 1) ? a.X : a.A;
+    double *dst = (k & 1) ? a.A : a.X;
+    const bool first = k == 0;
+    blk_load(sP, src, a.PP, a.G, a.rdiag, a.p, first, k, k);
+    if (bi != k) blk_load(sI, src, a.PP, a.G, a.rdiag, a.p, first, bi, k);
+    if (bj != k) blk_load(sJ, src, a.PP, a.G, a.rdiag, a.p, first, k, bj);
+    if (bi != k && bj != k) blk_load(sT, src, a.PP, a.G, a.rdiag, a.p, first, bi, bj);
     __syncthreads();
-    double piv;
-    const bool ok = blk_factor(sA, sD, &piv);
-    if (t == 0) {
-        a.status[kStStep] = ok ? HIKF_OK : HIKF_E_NOT_SPD;
-        a.pivs[0] = piv;
-        if (!ok) a.minpiv[0] = piv;
-    }
-    if (!ok) return;
-    blk_store(sA, a.L, a.PP, 0, 0);
-    blk_store(sD, a.D, BS, 0, 0);
-}
-
-// block (i, j) with kb < j <= i < nbk, enumerated row by row
-__device__ __forceinline__ void pair_of(int w, int kb, int *bi, int *bj) {
-    int i = kb + 1, base = 0;
-    while (base + (i - kb) <= w) { base += i - kb; ++i; }
-    *bi = i;
-    *bj = kb + 1 + (w - base);
-}
-
-__global__ void __launch_bounds__(NT) k_ps_update(PsArgs a, int kb) {
-    __shared__ double sD[BS * BP];
-    __shared__ double sPi[BS * BP];
-    __shared__ double sPj[BS * BP];
-    __shared__ double sT[BS * BP];
-    if (a.status[kStStep] != HIKF_OK) return;
-    int bi, bj;
-    pair_of(blockIdx.x, kb, &bi, &bj);
-    const bool first = kb == 0;
-    blk_load_plain(sD, a.D + int64_t(kb) * BS * BS, BS, 0, 0);
-    blk_load(sPi, a.A, a.PP, a.G, a.rdiag, a.p, first, bi, kb);
-    blk_load(sPj, a.A, a.PP, a.G, a.rdiag, a.p, first, bj, kb);
-    blk_load(sT, a.A, a.PP, a.G, a.rdiag, a.p, first, bi, bj);
-    __syncthreads();
-    // panel blocks: L_ik = A_ik D^T, L_jk = A_jk D^T
-    d4 pi = tile_mma<false, true>(d4{0, 0, 0, 0}, sPi, sD, 1.0);
-    d4 pj = tile_mma<false, true>(d4{0, 0, 0, 0}, sPj, sD, 1.0);
-    d4 acc = tile_read(sT);
-    __syncthreads();
-    tile_write(sPi, pi);
-    tile_write(sPj, pj);
-    __syncthreads();
-    if (bj == kb + 1) blk_store(sPi, a.L, a.PP, bi, kb);
-    // A_ij -= L_ik L_jk^T
-    acc = tile_mma<false, true>(acc, sPi, sPj, -1.0);
-    if (bi == bj && bi == kb + 1) {
-        // the next diagonal block is final: factor it here
-        tile_write(sT, acc);
-        __syncthreads();
-        double piv;
-        const bool ok = blk_factor(sT, sD, &piv);
-        if (threadIdx.x == 0) {
-            a.pivs[bi] = piv;
-            if (!ok) {
-                a.status[kStStep] = HIKF_E_NOT_SPD;
-                a.minpiv[0] = piv;
+    if (t < 64) {
+        double pmin;
+        const bool ok = blk_sweep_wave(sP, bufs, bufs + BS, &pmin);
+        if (t == 0) {
+            okflag = ok;
+            if (bi == k && bj == k) {
+                a.pivs[k] = ok ? sqrt(pmin) : pmin;
+                if (!ok) {
+                    a.status[kStStep] = HIKF_E_NOT_SPD;
+                    a.minpiv[0] = pmin;
+                }
             }
         }
-        if (!ok) return;
-        blk_store(sT, a.L, a.PP, bi, bi);
-        blk_store(sD, a.D + int64_t(bi) * BS * BS, BS, 0, 0);
+    }
+    __syncthreads();
+    if (!okflag) return;
+    d4 acc;
+    if (bi == k && bj == k) {
+        acc = tile_read(sP);                                    // -A_kk^{-1}
+    } else if (bi == k) {
+        acc = tile_mma<false, false>(d4{0, 0, 0, 0}, sP, sJ, -1.0);   // A_kk^{-1} A_kj
+    } else if (bj == k) {
+        acc = tile_mma<false, false>(d4{0, 0, 0, 0}, sI, sP, -1.0);   // A_ik A_kk^{-1}
     } else {
+        // A_ij + A_ik (-A_kk^{-1}) A_kj
+        d4 tik = tile_mma<false, false>(d4{0, 0, 0, 0}, sI, sP, 1.0);
+        acc = tile_read(sT);
+        __syncthreads();
+        tile_write(sI, tik);
+        __syncthreads();
+        acc = tile_mma<false, false>(acc, sI, sJ, 1.0);
+    }
+    if (k + 1 < a.nbk) {
         __syncthreads();
         tile_write(sT, acc);
         __syncthreads();
-        blk_store(sT, a.A, a.PP, bi, bj);
+        blk_store(sT, dst, a.PP, bi, bj);
+        return;
     }
-}
-
-__global__ void __launch_bounds__(NT) k_ps_trtri(PsArgs a) {
-    // The blocks X_kj of column j are written to X as soon as they are final
-    // and read back from there (they are needed by every later block of the
-    // column; at PP = 512 they would not fit in LDS together).  The barrier
-    // that follows each store makes them visible to the whole workgroup.
-    __shared__ double sL[BS * BP];                // staged L_ik block
-    __shared__ double sX[BS * BP];                // staged X_kj block
-    __shared__ double sD[BS * BP];
-    if (a.status[kStStep] != HIKF_OK) return;
-    const int j = blockIdx.x;
-    blk_load_plain(sD, a.D + int64_t(j) * BS * BS, BS, 0, 0);
-    __syncthreads();
-    blk_store(sD, a.X, a.PP, j, j);
-    for (int i = j + 1; i < a.nbk; ++i) {
-        d4 acc = d4{0, 0, 0, 0};
-        for (int k = j; k < i; ++k) {
-            __syncthreads();
-            blk_load_plain(sL, a.L, a.PP, i, k);
-            blk_load_plain(sX, a.X, a.PP, k, j);
-            __syncthreads();
-            acc = tile_mma<false, false>(acc, sL, sX, 1.0);
-        }
-        __syncthreads();
-        tile_write(sL, acc);                       // T = sum_k L_ik X_kj
-        blk_load_plain(sD, a.D + int64_t(i) * BS * BS, BS, 0, 0);
-        __syncthreads();
-        d4 x = tile_mma<false, false>(d4{0, 0, 0, 0}, sD, sL, -1.0);
-        tile_write(sX, x);
-        __syncthreads();
-        blk_store(sX, a.X, a.PP, i, j);
-    }
-}
-
-__global__ void __launch_bounds__(NT) k_ps_lauum(PsArgs a) {
-    __shared__ double sXi[BS * BP];
-    __shared__ double sXj[BS * BP];
-    __shared__ double sT[BS * BP];
-    if (a.status[kStStep] != HIKF_OK) return;
-    int bi = 0, base = 0;
-    while (base + bi + 1 <= (int)blockIdx.x) { base += bi + 1; ++bi; }
-    const int bj = blockIdx.x - base;              // 0 <= bj <= bi
-    d4 acc = d4{0, 0, 0, 0};
-    for (int k = bi; k < a.nbk; ++k) {
-        __syncthreads();
-        blk_load_plain(sXi, a.X, a.PP, k, bi);
-        blk_load_plain(sXj, a.X, a.PP, k, bj);
-        __syncthreads();
-        acc = tile_mma<true, false>(acc, sXi, sXj, 1.0);   // X_ki^T X_kj
-    }
+    // last pivot: the matrix is now -S^{-1}
     __syncthreads();
     tile_write(sT, acc);
     __syncthreads();
-    for (int idx = threadIdx.x; idx < BS * BS; idx += NT) {
-        const int r = idx / BS, c = idx % BS, i = bi * BS + r, jj = bj * BS + c;
-        // a diagonal block is written from its lower half only, so that both
-        // triangles of S^{-1} receive the same value
-        if (i < a.p && jj < a.p && (bi != bj || r >= c)) {
-            a.Sinv[int64_t(i) * a.p + jj] = sT[r * BP + c];
-            a.Sinv[int64_t(jj) * a.p + i] = sT[r * BP + c];
-        }
+    for (int idx = t; idx < BS * BS; idx += NT) {
+        const int r = idx / BS, c = idx % BS, i = bi * BS + r, j = bj * BS + c;
+        if (i < a.p && j < a.p) a.Sinv[int64_t(i) * a.p + j] = -sT[r * BP + c];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bi == k && bj == k && t == 0) {
         double mp = a.pivs[0];
-        for (int k = 1; k < a.nbk; ++k) mp = fmin(mp, a.pivs[k]);
+        for (int q = 1; q < a.nbk; ++q) mp = fmin(mp, a.pivs[q]);
         a.minpiv[0] = mp;
         a.steps[0] += 1;
     }
@@ -317,8 +249,6 @@ hipError_t launch_pspace(const Geometry &g, const Layout &lay, char *res, const 
     a.y = y;
     a.hvec = reinterpret_cast<const double *>(res + lay.hvec);
     a.A = reinterpret_cast<double *>(res + lay.psA);
-    a.L = reinterpret_cast<double *>(res + lay.psL);
-    a.D = reinterpret_cast<double *>(res + lay.psD);
     a.X = reinterpret_cast<double *>(res + lay.xbuf);
     a.Sinv = reinterpret_cast<double *>(res + lay.sinv);
     a.nu = reinterpret_cast<double *>(res + lay.nu);
@@ -326,14 +256,8 @@ hipError_t launch_pspace(const Geometry &g, const Layout &lay, char *res, const 
     a.minpiv = reinterpret_cast<double *>(res + lay.minpiv);
     a.status = reinterpret_cast<int *>(res + lay.status);
     a.steps = reinterpret_cast<long long *>(res + lay.steps);
-    hipLaunchKernelGGL(k_ps_factor, dim3(1), dim3(NT), 0, s, a);
-    for (int kb = 0; kb + 1 < a.nbk; ++kb) {
-        const int n = a.nbk - 1 - kb;
-        hipLaunchKernelGGL(k_ps_update, dim3(n * (n + 1) / 2), dim3(NT), 0, s, a, kb);
-    }
-    if (a.nbk > kMaxNbk) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_ps_trtri, dim3(a.nbk), dim3(NT), 0, s, a);
-    hipLaunchKernelGGL(k_ps_lauum, dim3(a.nbk * (a.nbk + 1) / 2), dim3(NT), 0, s, a);
+    for (int k = 0; k < a.nbk; ++k)
+        hipLaunchKernelGGL(k_ps_sweep, dim3(a.nbk * a.nbk), dim3(NT), 0, s, a, k);
     return hipGetLastError();
 }
 

@@ -5,10 +5,10 @@
 //                   chunks of each ray's nonzeros (the prediction
 //                   C_{t+1|t} = C_{t|t} + C_Q is formed on the fly).
 //   2. k_reduce_g : chunk partials -> G (p x p), h (p), in a fixed order.
-//   3. p-space    : S = (G + G^T)/2 + R, its Cholesky factor L,
-//                   X = L^{-1}, S^{-1} = X^T X and the innovation nu = y - h
-//                   as blocked FP64 MFMA kernels (pspace.hip); writes the
-//                   step status.
+//   3. p-space    : S = (G + G^T)/2 + R, S^{-1} by a blocked symmetric
+//                   sweep (Gauss-Jordan; its pivots are those of the
+//                   Cholesky factorisation) on FP64 MFMA, and the innovation
+//                   nu = y - h (pspace.hip); writes the step status.
 //   4. k_rowpass  : K = C_prior S^{-1} on FP64 MFMA, fused with the state,
 //                   variance and cross-covariance updates:
 //                   x_hat += K nu, var += K(0) - sum_j K_ij C_prior,ij,
