@@ -31,6 +31,7 @@ import numpy as np  # noqa: E402
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0   # dense BF16 MFMA
 
 
 def log(msg):
@@ -43,7 +44,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3, help="timed jobs")
     ap.add_argument("--warmup", type=int, default=1, help="untimed jobs")
     ap.add_argument("--workload", default="crosswell-1024x1024-p256")
-    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64", "bf16x3", "bf16"])
     ap.add_argument("--n-c", type=int, default=None)
     ap.add_argument("--assim-steps", type=int, default=None,
                     help="assimilation steps per job (default: the workload's)")
@@ -251,7 +252,10 @@ def main():
             "algorithmic_bytes": (8 + 4 + 8) * m * p, "kernel": "k_rowpass (FP64 MFMA)",
             "avg_ms": round(avg["rowpass"], 4)}
     tq = 8 if a.precision == "f64" else 4
-    peak_f = PEAK_FP64_TFLOPS if a.precision == "f64" else PEAK_FP32_TFLOPS
+    # M2L and P2P run on FP64 / FP32 MFMA, or on BF16 MFMA (three products per
+    # FP32 product with the refinement terms): frac is issued work over peak
+    issue = {"f64": 1, "f32": 1, "bf16x3": 3, "bf16": 1}[a.precision]
+    peak_f = {"f64": PEAK_FP64_TFLOPS, "f32": PEAK_FP32_TFLOPS}.get(a.precision, PEAK_BF16_TFLOPS)
     leaves = m // 64
     fmm = {}
     if avg["p2p"]:
@@ -259,12 +263,12 @@ def main():
         by = 2.0 * m * p * tq
         fmm["p2p_l2p"] = {"ms": round(avg["p2p"], 4),
                           "tflops": round(fl / avg["p2p"] / 1e9, 3),
-                          "frac_fp_peak": round(fl / avg["p2p"] / 1e9 / peak_f, 4),
+                          "frac_fp_peak": round(issue * fl / avg["p2p"] / 1e9 / peak_f, 4),
                           "GBps": round(by / avg["p2p"] / 1e6, 1)}
     if avg["m2l"]:
         fl = 2.0 * info.far_pairs * info.r * info.r * p
         fmm["m2l"] = {"ms": round(avg["m2l"], 4), "tflops": round(fl / avg["m2l"] / 1e9, 3),
-                      "frac_fp_peak": round(fl / avg["m2l"] / 1e9 / peak_f, 4)}
+                      "frac_fp_peak": round(issue * fl / avg["m2l"] / 1e9 / peak_f, 4)}
     if avg["p2m"]:
         by = (m * p + leaves * info.r * p) * tq
         fmm["p2m"] = {"ms": round(avg["p2m"], 4), "GBps": round(by / avg["p2m"] / 1e6, 1),

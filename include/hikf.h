@@ -69,7 +69,15 @@ enum {
 /* Arithmetic of the H^2 product (the per-step update is always FP64). */
 enum {
     HIKF_FMM_F32 = 0,        /* FP32 operands and accumulation, C_Q kept in FP32 */
-    HIKF_FMM_F64 = 1         /* FP64 throughout, C_Q kept in FP64                */
+    HIKF_FMM_F64 = 1,        /* FP64 throughout, C_Q kept in FP64                */
+    HIKF_FMM_BF16X3 = 2,     /* as F32, but the M2L and P2P products run on BF16
+                                MFMA with every FP32 operand split into
+                                a = hi + lo (hi = bf16(a), lo = bf16(a - hi)) and
+                                A B ~ A_hi B_hi + A_hi B_lo + A_lo B_hi with FP32
+                                accumulation (relative error ~1e-5)          */
+    HIKF_FMM_BF16 = 3        /* the same products from A_hi B_hi alone (no
+                                refinement; relative error ~1e-3), kept to
+                                show what the refinement terms contribute    */
 };
 
 /*
@@ -100,7 +108,7 @@ typedef struct hikf_problem {
 
 typedef struct hikf_options {
     int32_t n_c;             /* Chebyshev nodes per axis, 1..8 (r = n_c^dim) */
-    int32_t fmm_precision;   /* HIKF_FMM_F32 or HIKF_FMM_F64                 */
+    int32_t fmm_precision;   /* HIKF_FMM_*                                   */
     int32_t direct;          /* 1: exact near-field sum over all leaves, no
                                 far field (C_Q exact up to rounding; O(m^2),
                                 for small grids and tests)                   */

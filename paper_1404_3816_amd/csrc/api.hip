@@ -54,6 +54,19 @@ Layout make_layout(const Geometry &g) {
         ml_bytes = off - L.ML_level[2];
         L.L_base = take(ml_bytes);
     }
+    if (g.fmm_prec == HIKF_FMM_BF16X3 || g.fmm_prec == HIKF_FMM_BF16) {
+        // BF16 hi / lo operands: W per leaf as [column][point], multipoles per
+        // box as [column][node], M2L tables as [target node][source node],
+        // node counts padded to kr32 = 32 ceil(r / 32)
+        const size_t leaves = size_t(g.boxes(g.depth));
+        L.Wsplit = take(2 * leaves * p * kLeafPts * 2);
+        if (g.far) {
+            const size_t kr = size_t(g.kr32()), rt = size_t(g.r + 15) / 16 * 16;
+            L.Tsplit = take(2 * size_t(g.depth - 1) * g.noff() * rt * kr * 2);
+            for (int lev = 2; lev <= g.depth; ++lev)
+                L.MS_level[lev] = take(2 * size_t(g.boxes(lev)) * p * kr * 2);
+        }
+    }
     L.scratch_bytes = off > 0 ? off : 256;
     return L;
 }
@@ -127,7 +140,7 @@ hikf_status build_geometry(const hikf_problem *pr, const hikf_options *op, Geome
     if (pr->dim != 2 && pr->dim != 3) return HIKF_E_INVALID;
     if (pr->n < 1 || pr->p < 1 || pr->nnz < 0) return HIKF_E_INVALID;
     if (op->n_c < 1 || op->n_c > 8) return HIKF_E_INVALID;
-    if (op->fmm_precision != HIKF_FMM_F32 && op->fmm_precision != HIKF_FMM_F64) return HIKF_E_INVALID;
+    if (op->fmm_precision < HIKF_FMM_F32 || op->fmm_precision > HIKF_FMM_BF16) return HIKF_E_INVALID;
     if (pr->kernel_family != HIKF_KERNEL_POWEXP && pr->kernel_family != HIKF_KERNEL_TEST_R2)
         return HIKF_E_INVALID;
     if (!(pr->theta > 0.0) || !std::isfinite(pr->theta)) return HIKF_E_INVALID;

@@ -22,7 +22,6 @@ namespace hikf {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kMaxU = 16;         // outputs per thread in the tile kernels
 
 __device__ __forceinline__ double cheb_node(int nc, int k) {
     return cos((2 * k + 1) * M_PI / (2.0 * nc));
@@ -231,55 +230,6 @@ __device__ __forceinline__ bool il_member(const int *b, const int *o, int nb, in
     return omax >= 2;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
-k_m2l(int dim, int r, int p, int lev, int PT, const T *M, const T *Tlev, T *L) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *sM = reinterpret_cast<T *>(smem_raw);           // [r][PT]
-    const int64_t B = blockIdx.x;
-    const int c0 = blockIdx.y * PT;
-    const int ncols = min(PT, p - c0);
-    const int nb = 1 << lev;
-    const int noff = dim == 2 ? 49 : 343;
-    int b[3];
-    box_coords(B, nb, dim, b);
-    T acc[kMaxU];
-#pragma unroll
-    for (int u = 0; u < kMaxU; ++u) acc[u] = (T)0;
-    for (int oi = 0; oi < noff; ++oi) {
-        int o[3] = {oi % 7 - 3, (oi / 7) % 7 - 3, oi / 49 - 3};
-        if (!il_member(b, o, nb, dim)) continue;
-        int a[3] = {b[0] + o[0], b[1] + o[1], dim == 3 ? b[2] + o[2] : 0};
-        int64_t A = box_index(a, nb, dim);
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < r * PT; idx += blockDim.x) {
-            int k = idx / PT, c = idx % PT;
-            sM[idx] = (c < ncols) ? M[(A * r + k) * p + c0 + c] : (T)0;
-        }
-        __syncthreads();
-        const T *Toff = Tlev + int64_t(oi) * r * r;
-#pragma unroll
-        for (int u = 0; u < kMaxU; ++u) {
-            int idx = threadIdx.x + u * blockDim.x;
-            if (idx < r * PT) {
-                int k = idx / PT, c = idx % PT;
-                const T *trow = Toff + k * r;
-                T s = (T)0;
-                for (int kq = 0; kq < r; ++kq) s += trow[kq] * sM[kq * PT + c];
-                acc[u] += s;
-            }
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < kMaxU; ++u) {
-        int idx = threadIdx.x + u * blockDim.x;
-        if (idx < r * PT) {
-            int k = idx / PT, c = idx % PT;
-            if (c < ncols) L[(B * r + k) * p + c0 + c] = acc[u];
-        }
-    }
-}
-
 // ---------------------------------------------------------------- L2L
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
@@ -307,87 +257,6 @@ k_l2l(int dim, int r, int p, int lev, int PT, const T *Lpar, const T *Schild, T 
         const T *S = Schild + int64_t(ch) * r * r + kq;
         for (int k = 0; k < r; ++k) acc += S[k * r] * sL[k * PT + c];
         Lchild[(Bc * r + kq) * p + c0 + c] += acc;
-    }
-}
-
-// ---------------------------------------------------------------- L2P + P2P
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
-k_l2p_p2p(int dim, int n, int ls, int depth, int r, int p, int PT, int rad, int far,
-          KernelParams kp, T h2, const T *W, const T *Sleaf, const T *Lleaf, T *CQ) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *sK = reinterpret_cast<T *>(smem_raw);           // [64][64]
-    T *sW = sK + kLeafPts * kLeafPts;                  // [max(64, r)][PT]
-    const int64_t B = blockIdx.x;
-    const int c0 = blockIdx.y * PT;
-    const int ncols = min(PT, p - c0);
-    const int nb = 1 << depth;
-    int b[3];
-    box_coords(B, nb, dim, b);
-    T acc[kMaxU];
-#pragma unroll
-    for (int u = 0; u < kMaxU; ++u) acc[u] = (T)0;
-    const int zlo = dim == 3 ? max(0, b[2] - rad) : 0;
-    const int zhi = dim == 3 ? min(nb - 1, b[2] + rad) : 0;
-    for (int az = zlo; az <= zhi; ++az)
-    for (int ay = max(0, b[1] - rad); ay <= min(nb - 1, b[1] + rad); ++ay)
-    for (int ax = max(0, b[0] - rad); ax <= min(nb - 1, b[0] + rad); ++ax) {
-        int a[3] = {ax, ay, az};
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < kLeafPts * PT; idx += blockDim.x) {
-            int j = idx / PT, c = idx % PT;
-            sW[idx] = (c < ncols) ? W[leaf_point(a, j, dim, n, ls) * p + c0 + c] : (T)0;
-        }
-        for (int idx = threadIdx.x; idx < kLeafPts * kLeafPts; idx += blockDim.x) {
-            int i = idx / kLeafPts, j = idx % kLeafPts;
-            int li[3], lj[3];
-            leaf_local(i, dim, li);
-            leaf_local(j, dim, lj);
-            int dsq = 0;
-            for (int q = 0; q < dim; ++q) {
-                int d = (a[q] - b[q]) * ls + lj[q] - li[q];
-                dsq += d * d;
-            }
-            sK[idx] = kernel_from_r2<T>((T)dsq * h2, kp);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < kMaxU; ++u) {
-            int idx = threadIdx.x + u * blockDim.x;
-            if (idx < kLeafPts * PT) {
-                int i = idx / PT, c = idx % PT;
-                const T *krow = sK + i * kLeafPts;
-                T s = (T)0;
-                for (int j = 0; j < kLeafPts; ++j) s += krow[j] * sW[j * PT + c];
-                acc[u] += s;
-            }
-        }
-    }
-    if (far) {
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < r * PT; idx += blockDim.x) {
-            int k = idx / PT, c = idx % PT;
-            sW[idx] = (c < ncols) ? Lleaf[(B * r + k) * p + c0 + c] : (T)0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < kMaxU; ++u) {
-            int idx = threadIdx.x + u * blockDim.x;
-            if (idx < kLeafPts * PT) {
-                int i = idx / PT, c = idx % PT;
-                T s = (T)0;
-                for (int k = 0; k < r; ++k) s += Sleaf[k * kLeafPts + i] * sW[k * PT + c];
-                acc[u] += s;
-            }
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < kMaxU; ++u) {
-        int idx = threadIdx.x + u * blockDim.x;
-        if (idx < kLeafPts * PT) {
-            int i = idx / PT, c = idx % PT;
-            if (c < ncols) CQ[leaf_point(b, i, dim, n, ls) * p + c0 + c] = acc[u];
-        }
     }
 }
 
@@ -579,6 +448,291 @@ k_m2l_mma(int dim, int r, int p, int lev, const T *M, const T *Tlev, T *L) {
     }
 }
 
+// ---------------------------------------------------------------- BF16 split (MFMA)
+// v_mfma_f32_16x16x32_bf16: D += A B with lane l supplying the 8 values
+// A[l%16][8 (l/16) + i] and B[8 (l/16) + i][l%16], i = 0..7, and holding
+// D[4 (l/16) + r][l%16] (the FP32 16x16x4 layout).  Every FP32 operand a is
+// split as hi = bf16(a), lo = bf16(a - hi); a product is accumulated in FP32
+// as A_hi B_hi + A_hi B_lo + A_lo B_hi (SPLIT) or A_hi B_hi alone.  Operands
+// are stored k-contiguous ([row][k] for A, [column][k] for B) so that a
+// lane's 8 values are one 16-byte LDS read; LDS rows are padded by 8 values.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void split_bf16(float a, __bf16 *hi, __bf16 *lo) {
+    const __bf16 h = (__bf16)a;
+    *hi = h;
+    *lo = (__bf16)(a - (float)h);
+}
+
+template <bool SPLIT>
+__device__ __forceinline__ f4v mma_bf16(const bf8 &ah, const bf8 &al, const bf8 &bh, const bf8 &bl,
+                                        f4v acc) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+    if (SPLIT) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// W = H^T split per leaf as [leaf][column][point] (hi block, then lo block);
+// the region is zeroed first.  Each nonzero of H is one entry.
+__global__ void k_split_w(int64_t nnz, int p, int64_t m, int dim, int n, int ls,
+                          const int64_t *rowptr, const int32_t *col, const double *val,
+                          __bf16 *Wh, __bf16 *Wl) {
+    int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    int lo = 0, hi = p - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (rowptr[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    if (rowptr[lo] > e || rowptr[lo + 1] <= e) return;
+    const int64_t c = col[e];
+    if (c < 0 || c >= m) return;
+    int g[3] = {int(c % n), int((c / n) % n), dim == 3 ? int(c / (int64_t(n) * n)) : 0};
+    int bc[3] = {g[0] / ls, g[1] / ls, g[2] / ls};
+    const int j = dim == 2 ? (g[0] % ls) + 8 * (g[1] % ls)
+                           : (g[0] % ls) + 4 * (g[1] % ls) + 16 * (g[2] % ls);
+    const int64_t leaf = box_index(bc, n / ls, dim);
+    const int64_t o = (leaf * p + lo) * kLeafPts + j;
+    split_bf16((float)val[e], Wh + o, Wl + o);
+}
+
+// Multipoles [box][node][p] (FP32) -> [box][column][kr] hi / lo, nodes >= r
+// zero.  One workgroup per (box, 64 columns), transposed through LDS.
+__global__ void __launch_bounds__(kBlock)
+k_split_m(int r, int kr, int p, const float *M, __bf16 *Mh, __bf16 *Ml) {
+    __shared__ float s[64 * 65];
+    const int64_t B = blockIdx.x;
+    const int c0 = blockIdx.y * 64;
+    const int nc = min(64, p - c0);
+    for (int k0 = 0; k0 < kr; k0 += 64) {
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < 64 * 64; idx += kBlock) {
+            const int kk = idx / 64, c = idx % 64, k = k0 + kk;
+            s[kk * 65 + c] = (k < r && c < nc) ? M[(B * r + k) * p + c0 + c] : 0.f;
+        }
+        __syncthreads();
+        const int kw = min(64, kr - k0);
+        for (int idx = threadIdx.x; idx < 64 * kw; idx += kBlock) {
+            const int c = idx / kw, kk = idx % kw;
+            if (c >= nc) continue;
+            const int64_t o = (B * p + c0 + c) * kr + k0 + kk;
+            split_bf16(s[kk * 65 + c], Mh + o, Ml + o);
+        }
+    }
+}
+
+// M2L tables [level][slot][r][r] -> [level][slot][rt][kr] hi / lo (zero padded)
+__global__ void k_split_t(int64_t nslots, int r, int rt, int kr, const float *T, __bf16 *Th,
+                          __bf16 *Tl) {
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= nslots * rt * kr) return;
+    const int64_t sl = idx / (int64_t(rt) * kr);
+    const int i = int((idx / kr) % rt), k = int(idx % kr);
+    const float v = (i < r && k < r) ? T[(sl * r + i) * r + k] : 0.f;
+    split_bf16(v, Th + idx, Tl + idx);
+}
+
+// M2L on BF16 MFMA: as k_m2l_mma, with the translation tile (A, [target
+// node][source node]) and M_A (B, [column][source node]) staged as hi / lo.
+template <bool SPLIT, int PT>
+__global__ void __launch_bounds__(kBlock)
+k_m2l_bf16(int dim, int r, int kr, int p, int lev, const __bf16 *Mh, const __bf16 *Ml,
+           const __bf16 *Th, const __bf16 *Tl, float *L) {
+    constexpr int NCT = PT / 16;
+    constexpr int MAXT = 8;                            // tiles per wave (r <= 128)
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int RT = (r + 15) / 16, rt16 = 16 * RT, KP = kr + 8;
+    __bf16 *sTh = reinterpret_cast<__bf16 *>(smem_raw);
+    __bf16 *sTl = sTh + rt16 * KP;
+    __bf16 *sMh = sTl + rt16 * KP;
+    __bf16 *sMl = sMh + PT * KP;
+    const int64_t B = blockIdx.x;
+    const int c0 = blockIdx.y * PT;
+    const int ncols = min(PT, p - c0);
+    const int nb = 1 << lev;
+    const int noff = dim == 2 ? 49 : 343;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, q = lane >> 4;
+    const int ntiles = RT * NCT, kch = kr / 8;        // 16-byte chunks per row
+    int b[3];
+    box_coords(B, nb, dim, b);
+    f4v acc[MAXT];
+#pragma unroll
+    for (int u = 0; u < MAXT; ++u) acc[u] = f4v{0, 0, 0, 0};
+    for (int oi = 0; oi < noff; ++oi) {
+        int o[3] = {oi % 7 - 3, (oi / 7) % 7 - 3, oi / 49 - 3};
+        if (!il_member(b, o, nb, dim)) continue;       // uniform
+        int a[3] = {b[0] + o[0], b[1] + o[1], dim == 3 ? b[2] + o[2] : 0};
+        const int64_t A = box_index(a, nb, dim);
+        const int64_t tbase = int64_t(oi) * rt16 * kr;
+        __syncthreads();
+        for (int idx = tid; idx < rt16 * kch; idx += kBlock) {
+            const int i = idx / kch, ch = idx % kch;
+            *reinterpret_cast<bf8 *>(sTh + i * KP + 8 * ch) =
+                *reinterpret_cast<const bf8 *>(Th + tbase + int64_t(i) * kr + 8 * ch);
+            *reinterpret_cast<bf8 *>(sTl + i * KP + 8 * ch) =
+                *reinterpret_cast<const bf8 *>(Tl + tbase + int64_t(i) * kr + 8 * ch);
+        }
+        for (int idx = tid; idx < PT * kch; idx += kBlock) {
+            const int c = idx / kch, ch = idx % kch;
+            bf8 vh, vl;
+            if (c < ncols) {
+                const int64_t g = (A * p + c0 + c) * kr + 8 * ch;
+                vh = *reinterpret_cast<const bf8 *>(Mh + g);
+                vl = *reinterpret_cast<const bf8 *>(Ml + g);
+            } else {
+                for (int e = 0; e < 8; ++e) vh[e] = vl[e] = (__bf16)0.f;
+            }
+            *reinterpret_cast<bf8 *>(sMh + c * KP + 8 * ch) = vh;
+            *reinterpret_cast<bf8 *>(sMl + c * KP + 8 * ch) = vl;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < MAXT; ++u) {
+            const int tile = wave + 4 * u;
+            if (tile >= ntiles) break;                 // uniform per wave
+            const int rt = tile / NCT, ct = tile % NCT;
+            const __bf16 *ah = sTh + (16 * rt + lr) * KP + 8 * q;
+            const __bf16 *al = sTl + (16 * rt + lr) * KP + 8 * q;
+            const __bf16 *bh = sMh + (16 * ct + lr) * KP + 8 * q;
+            const __bf16 *bl = sMl + (16 * ct + lr) * KP + 8 * q;
+            for (int k0 = 0; k0 < kr; k0 += 32)
+                acc[u] = mma_bf16<SPLIT>(*reinterpret_cast<const bf8 *>(ah + k0),
+                                         *reinterpret_cast<const bf8 *>(al + k0),
+                                         *reinterpret_cast<const bf8 *>(bh + k0),
+                                         *reinterpret_cast<const bf8 *>(bl + k0), acc[u]);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < MAXT; ++u) {
+        const int tile = wave + 4 * u;
+        if (tile >= ntiles) break;
+        const int rt = tile / NCT, ct = tile % NCT;
+        const int c = 16 * ct + lr;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int k = 16 * rt + 4 * q + rr;
+            if (k < r && c < ncols) L[(B * r + k) * p + c0 + c] = acc[u][rr];
+        }
+    }
+}
+
+// L2P + P2P with the near field on BF16 MFMA: the 64 x 64 kernel tile is
+// generated in FP32 and split into LDS ([target][source] hi / lo), W_A comes
+// pre-split ([column][source]); the far field S_leaf^T L_B stays on FP32 MFMA.
+template <bool SPLIT, int PT>
+__global__ void __launch_bounds__(kBlock)
+k_l2p_p2p_bf16(int dim, int n, int ls, int depth, int r, int rpad, int p, int rad, int far,
+               KernelParams kp, float h2, const __bf16 *Wh, const __bf16 *Wl,
+               const float *Sleaf, const float *Lleaf, float *CQ) {
+    constexpr int NTI = PT / 16;
+    constexpr int KPB = kLeafPts + 8;                  // bf16 row pitch
+    constexpr int WP = PT + Mma<float>::pad;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __bf16 *sKh = reinterpret_cast<__bf16 *>(smem_raw);
+    __bf16 *sKl = sKh + kLeafPts * KPB;
+    __bf16 *sWh = sKl + kLeafPts * KPB;
+    __bf16 *sWl = sWh + PT * KPB;
+    const int64_t B = blockIdx.x;
+    const int c0 = blockIdx.y * PT;
+    const int ncols = min(PT, p - c0);
+    const int nb = 1 << depth;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, q = lane >> 4;
+    int b[3];
+    box_coords(B, nb, dim, b);
+    f4v acc[NTI];
+#pragma unroll
+    for (int t = 0; t < NTI; ++t) acc[t] = f4v{0, 0, 0, 0};
+    const int zlo = dim == 3 ? max(0, b[2] - rad) : 0;
+    const int zhi = dim == 3 ? min(nb - 1, b[2] + rad) : 0;
+    for (int az = zlo; az <= zhi; ++az)
+    for (int ay = max(0, b[1] - rad); ay <= min(nb - 1, b[1] + rad); ++ay)
+    for (int ax = max(0, b[0] - rad); ax <= min(nb - 1, b[0] + rad); ++ax) {
+        int a[3] = {ax, ay, az};
+        const int64_t A = box_index(a, nb, dim);
+        __syncthreads();
+        for (int idx = tid; idx < PT * 8; idx += kBlock) {
+            const int c = idx / 8, ch = idx % 8;
+            bf8 vh, vl;
+            if (c < ncols) {
+                const int64_t g = (A * p + c0 + c) * kLeafPts + 8 * ch;
+                vh = *reinterpret_cast<const bf8 *>(Wh + g);
+                vl = *reinterpret_cast<const bf8 *>(Wl + g);
+            } else {
+                for (int e = 0; e < 8; ++e) vh[e] = vl[e] = (__bf16)0.f;
+            }
+            *reinterpret_cast<bf8 *>(sWh + c * KPB + 8 * ch) = vh;
+            *reinterpret_cast<bf8 *>(sWl + c * KPB + 8 * ch) = vl;
+        }
+        for (int idx = tid; idx < kLeafPts * kLeafPts; idx += kBlock) {
+            const int i = idx / kLeafPts, j = idx % kLeafPts;
+            int li[3], lj[3];
+            leaf_local(i, dim, li);
+            leaf_local(j, dim, lj);
+            int dsq = 0;
+            for (int qq = 0; qq < dim; ++qq) {
+                const int d = (a[qq] - b[qq]) * ls + lj[qq] - li[qq];
+                dsq += d * d;
+            }
+            split_bf16(kernel_from_r2<float>((float)dsq * h2, kp), sKh + i * KPB + j,
+                       sKl + i * KPB + j);
+        }
+        __syncthreads();
+        const __bf16 *ah = sKh + (16 * wave + lr) * KPB + 8 * q;
+        const __bf16 *al = sKl + (16 * wave + lr) * KPB + 8 * q;
+#pragma unroll
+        for (int k0 = 0; k0 < kLeafPts; k0 += 32) {
+            const bf8 avh = *reinterpret_cast<const bf8 *>(ah + k0);
+            const bf8 avl = *reinterpret_cast<const bf8 *>(al + k0);
+#pragma unroll
+            for (int t = 0; t < NTI; ++t) {
+                const __bf16 *bh = sWh + (16 * t + lr) * KPB + 8 * q + k0;
+                const __bf16 *bl = sWl + (16 * t + lr) * KPB + 8 * q + k0;
+                acc[t] = mma_bf16<SPLIT>(avh, avl, *reinterpret_cast<const bf8 *>(bh),
+                                         *reinterpret_cast<const bf8 *>(bl), acc[t]);
+            }
+        }
+    }
+    if (far) {
+        // S_leaf^T (64 x r) L_B (r x PT) on FP32 MFMA, staged in the same LDS
+        const int KP = max(kLeafPts, rpad) + 4;
+        float *sK = reinterpret_cast<float *>(smem_raw);
+        float *sW = sK + kLeafPts * KP;
+        __syncthreads();
+        for (int idx = tid; idx < kLeafPts * rpad; idx += kBlock) {
+            const int i = idx / rpad, k = idx % rpad;
+            sK[i * KP + k] = k < r ? Sleaf[k * kLeafPts + i] : 0.f;
+        }
+        for (int idx = tid; idx < rpad * PT; idx += kBlock) {
+            const int k = idx / PT, c = idx % PT;
+            sW[k * WP + c] = (k < r && c < ncols) ? Lleaf[(B * r + k) * p + c0 + c] : 0.f;
+        }
+        __syncthreads();
+        const float *arow = sK + (16 * wave + lr) * KP + q;
+        const float *bcol = sW + q * WP + lr;
+        for (int k0 = 0; k0 < rpad; k0 += 4) {
+            const float av = arow[k0];
+#pragma unroll
+            for (int t = 0; t < NTI; ++t) acc[t] = Mma<float>::op(av, bcol[k0 * WP + 16 * t], acc[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NTI; ++t) {
+        const int c = 16 * t + lr;
+        if (c >= ncols) continue;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int i = 16 * wave + 4 * q + rr;
+            CQ[leaf_point(b, i, dim, n, ls) * p + c0 + c] = acc[t][rr];
+        }
+    }
+}
+
 // Allow a kernel more than the default 64 KiB of dynamic LDS (gfx950 has
 // 160 KiB per workgroup).
 template <typename K>
@@ -600,6 +754,9 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
                    Timing *tm) {
     const int p = g.p, r = g.r, dim = g.dim, D = g.depth;
     const int64_t m = g.m;
+    const bool bf16 = g.fmm_prec == HIKF_FMM_BF16X3 || g.fmm_prec == HIKF_FMM_BF16;
+    const bool split = g.fmm_prec == HIKF_FMM_BF16X3;
+    (void)split;
     T *W = reinterpret_cast<T *>(scr + lay.W);
     T *CQ = reinterpret_cast<T *>(res + lay.CQ);
     const int64_t *rowptr = reinterpret_cast<const int64_t *>(res + lay.rowptr);
@@ -651,7 +808,38 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
         tend(tm, HIKF_PHASE_M2M, s);
         // M2L
         tbegin(tm, HIKF_PHASE_M2L, s);
-        {
+        if constexpr (sizeof(T) == 4) {
+            if (bf16) {
+                const int kr = g.kr32(), rt16 = (r + 15) / 16 * 16;
+                const int64_t nslots = int64_t(D - 1) * g.noff();
+                __bf16 *Th = reinterpret_cast<__bf16 *>(scr + lay.Tsplit);
+                __bf16 *Tl = Th + nslots * rt16 * kr;
+                hipLaunchKernelGGL(k_split_t, dim3(unsigned((nslots * rt16 * kr + 255) / 256)),
+                                   dim3(256), 0, s, nslots, r, rt16, kr, Tm2l, Th, Tl);
+                const size_t lds = size_t(rt16 + 128) * (kr + 8) * 2 * sizeof(__bf16);
+                e = allow_lds(k_m2l_bf16<true, 128>, lds);
+                if (e == hipSuccess) e = allow_lds(k_m2l_bf16<false, 128>, lds);
+                if (e != hipSuccess) return e;
+                for (int lev = 2; lev <= D; ++lev) {
+                    const int64_t nbx = g.boxes(lev);
+                    __bf16 *Mh = reinterpret_cast<__bf16 *>(scr + lay.MS_level[lev]);
+                    __bf16 *Ml = Mh + nbx * p * kr;
+                    hipLaunchKernelGGL(k_split_m, dim3(unsigned(nbx), (p + 63) / 64), dim3(kBlock), 0,
+                                       s, r, kr, p, Mlev(lev), Mh, Ml);
+                    const __bf16 *Thl = Th + int64_t(lev - 2) * g.noff() * rt16 * kr;
+                    const __bf16 *Tll = Tl + int64_t(lev - 2) * g.noff() * rt16 * kr;
+                    if (split)
+                        hipLaunchKernelGGL((k_m2l_bf16<true, 128>), dim3(unsigned(nbx), (p + 127) / 128),
+                                           dim3(kBlock), lds, s, dim, r, kr, p, lev, Mh, Ml, Thl, Tll,
+                                           Llev(lev));
+                    else
+                        hipLaunchKernelGGL((k_m2l_bf16<false, 128>), dim3(unsigned(nbx), (p + 127) / 128),
+                                           dim3(kBlock), lds, s, dim, r, kr, p, lev, Mh, Ml, Thl, Tll,
+                                           Llev(lev));
+                }
+            }
+        }
+        if (!bf16) {
             constexpr int MPT = sizeof(T) == 4 ? 128 : 64;
             const int RT = (r + 15) / 16, KR = (r + 3) / 4 * 4;
             const size_t lds = (size_t(KR) * (MPT + Mma<T>::pad) + size_t(16 * RT) * 68) * sizeof(T);
@@ -671,6 +859,42 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
                                dim3(kBlock), size_t(r) * PT * sizeof(T), s, dim, r, p, lev, PT,
                                Llev(lev), Schild, Llev(lev + 1));
         tend(tm, HIKF_PHASE_L2L, s);
+    }
+    if constexpr (sizeof(T) == 4) {
+        if (bf16) {
+            const int rpad = (r + 3) / 4 * 4;
+            const int rad = g.direct ? (1 << D) : 1;
+            const double h = 1.0 / g.n;
+            const int64_t leaves = g.boxes(D);
+            __bf16 *Wh = reinterpret_cast<__bf16 *>(scr + lay.Wsplit);
+            __bf16 *Wl = Wh + leaves * p * kLeafPts;
+            tbegin(tm, HIKF_PHASE_P2P, s);
+            e = hipMemsetAsync(Wh, 0, size_t(2 * leaves * p * kLeafPts) * sizeof(__bf16), s);
+            if (e != hipSuccess) return e;
+            if (g.nnz > 0)
+                hipLaunchKernelGGL(k_split_w, dim3(unsigned((g.nnz + kBlock - 1) / kBlock)),
+                                   dim3(kBlock), 0, s, g.nnz, p, m, dim, g.n, g.ls, rowptr, col, val,
+                                   Wh, Wl);
+            const size_t near_lds = size_t(kLeafPts + 128) * (kLeafPts + 8) * 2 * sizeof(__bf16);
+            const size_t far_lds = (size_t(kLeafPts) * (max(kLeafPts, rpad) + 4) +
+                                    size_t(max(kLeafPts, rpad)) * (128 + Mma<float>::pad)) * sizeof(float);
+            const size_t lds = max(near_lds, far_lds);
+            e = allow_lds(k_l2p_p2p_bf16<true, 128>, lds);
+            if (e == hipSuccess) e = allow_lds(k_l2p_p2p_bf16<false, 128>, lds);
+            if (e != hipSuccess) return e;
+            if (split)
+                hipLaunchKernelGGL((k_l2p_p2p_bf16<true, 128>), dim3(unsigned(leaves), (p + 127) / 128),
+                                   dim3(kBlock), lds, s, dim, g.n, g.ls, D, r, rpad, p, rad,
+                                   g.far ? 1 : 0, g.kp, (float)(h * h), Wh, Wl, Sleaf,
+                                   g.far ? Llev(D) : W, CQ);
+            else
+                hipLaunchKernelGGL((k_l2p_p2p_bf16<false, 128>), dim3(unsigned(leaves), (p + 127) / 128),
+                                   dim3(kBlock), lds, s, dim, g.n, g.ls, D, r, rpad, p, rad,
+                                   g.far ? 1 : 0, g.kp, (float)(h * h), Wh, Wl, Sleaf,
+                                   g.far ? Llev(D) : W, CQ);
+            tend(tm, HIKF_PHASE_P2P, s);
+            return hipGetLastError();
+        }
     }
     {
         constexpr int PPT = sizeof(T) == 4 ? 128 : 64;

@@ -75,6 +75,7 @@ struct Geometry {
         return dim == 2 ? nb * nb : nb * nb * nb;
     }
     int noff() const { return dim == 2 ? 49 : 343; }   // 7^dim offset slots
+    int kr32() const { return (r + 31) / 32 * 32; }    // nodes padded for BF16 MFMA
 };
 
 // Byte offsets of every array inside the two caller-owned regions.
@@ -88,6 +89,7 @@ struct Layout {
     size_t W, sleaf, schild, m2l, lev_off;   // lev_off: start of M/L storage
     size_t ML_level[24];                      // per-level offset of M (L follows after all M)
     size_t L_base;
+    size_t Wsplit, Tsplit, MS_level[24];      // BF16 hi/lo operands (BF16 modes only)
     size_t scratch_bytes;
 };
 

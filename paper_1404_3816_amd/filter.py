@@ -11,7 +11,8 @@ import torch
 
 from . import hikf as H
 
-PRECISIONS = {"f32": H.HIKF_FMM_F32, "f64": H.HIKF_FMM_F64}
+PRECISIONS = {"f32": H.HIKF_FMM_F32, "f64": H.HIKF_FMM_F64, "bf16x3": H.HIKF_FMM_BF16X3,
+              "bf16": H.HIKF_FMM_BF16}
 PRIORS = {"zero": H.HIKF_PRIOR_ZERO, "scaled_i": H.HIKF_PRIOR_SCALED_I,
           "kernel": H.HIKF_PRIOR_KERNEL}
 FAMILIES = {"powexp": H.HIKF_KERNEL_POWEXP, "r2": H.HIKF_KERNEL_TEST_R2}

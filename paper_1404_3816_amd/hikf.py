@@ -36,6 +36,8 @@ HIKF_PRIOR_KERNEL = 2
 # FMM precision
 HIKF_FMM_F32 = 0
 HIKF_FMM_F64 = 1
+HIKF_FMM_BF16X3 = 2
+HIKF_FMM_BF16 = 3
 
 c_i32, c_i64, c_dbl, c_vp, c_sz = (ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
                                    ctypes.c_void_p, ctypes.c_size_t)

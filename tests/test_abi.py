@@ -124,3 +124,16 @@ def test_step_batch_rejects_bad_arguments_without_a_device():
     arr = ctypes.c_void_p * 2
     assert H.hikf_step_batch(arr(None, None), arr(None, None), None, None, 2,
                              None) == H.HIKF_E_INVALID
+
+
+def test_plan_bf16_modes_add_split_operands():
+    # BF16 modes keep FP32 storage and add hi/lo copies of W, M and the M2L tables
+    from paper_1404_3816_amd import hikf as H
+    st32, i32 = _plan(_problem(dim=3, n=32, p=64), precision=H.HIKF_FMM_F32)
+    st3, i3 = _plan(_problem(dim=3, n=32, p=64), precision=H.HIKF_FMM_BF16X3)
+    st1, i1 = _plan(_problem(dim=3, n=32, p=64), precision=H.HIKF_FMM_BF16)
+    assert st32 == st3 == st1 == H.HIKF_OK
+    assert i3.resident_bytes == i32.resident_bytes == i1.resident_bytes
+    assert i3.scratch_bytes == i1.scratch_bytes > i32.scratch_bytes
+    # W split: 2 copies x 2 bytes per entry of the m x p matrix
+    assert i3.scratch_bytes - i32.scratch_bytes >= 2 * 2 * 32 ** 3 * 64

@@ -61,6 +61,29 @@ def test_cq_fmm_matches_oracle_bbfmm(dim, n, p, n_c, ell, gamma, precision):
         assert _elementwise_ok(cq, ref, 1e-5, 2e-6)
 
 
+@pytest.mark.parametrize("dim,n,p,n_c,ell,gamma", [
+    (2, 64, 32, 4, 0.1, 1.0),
+    (2, 128, 48, 5, 0.05, 2.0),    # r = 25: BF16 k padded to 32, p tile ragged
+    (3, 16, 64, 4, 0.2, 1.0),
+    (3, 32, 32, 4, 0.2, 1.0),      # r = 64, octree depth 3
+])
+def test_cq_bf16_split_matches_oracle_bbfmm(dim, n, p, n_c, ell, gamma):
+    # BF16 split products (hi/lo with the two refinement terms) carry a
+    # relative operand error of ~2^-16; dropping the refinement leaves the
+    # ~2^-9 rounding of bf16 and must be clearly worse (the terms are live)
+    case = Case(dim, n, p, ell=ell, gamma=gamma, steps=1)
+    ref = case.cq_bbfmm(n_c)
+    errs = {}
+    for prec in ("bf16x3", "bf16"):
+        f = case.gpu_filter(n_c=n_c, precision=prec)
+        errs[prec] = rel(f.export_cq().cpu().numpy(), ref)
+        f.close()
+    print(f"C_Q vs oracle bbFMM: bf16x3 {errs['bf16x3']:.3e}, bf16 {errs['bf16']:.3e}")
+    assert errs["bf16x3"] < 1e-4
+    assert 3e-4 < errs["bf16"] < 3e-2
+    assert errs["bf16"] > 20 * errs["bf16x3"]
+
+
 @pytest.mark.parametrize("dim,n,n_c", [(2, 64, 3), (2, 64, 4), (3, 16, 3)])
 def test_cq_polynomial_kernel_exact(dim, n, n_c):
     # Chebyshev interpolation reproduces K = r^2 exactly for n_c >= 3, so the
@@ -113,7 +136,7 @@ def test_steps_direct_f32_match_dense_kf():
     assert ex < tx and ev < tv
 
 
-@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("precision", ["f64", "f32", "bf16x3"])
 @pytest.mark.parametrize("n,p,n_c,ell,gamma", [(32, 16, 4, 0.3, 1.0), (64, 32, 5, 0.1, 2.0)])
 def test_steps_fmm_match_oracle(precision, n, p, n_c, ell, gamma):
     case = Case(2, n, p, ell=ell, gamma=gamma, steps=4)
