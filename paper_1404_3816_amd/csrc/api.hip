@@ -42,6 +42,7 @@ Layout make_layout(const Geometry &g) {
 
     off = 0;
     L.W = take(m * p * tq);
+    L.knear = take(size_t(g.dim == 2 ? 9 : 27) * kLeafPts * kLeafPts * tq);
     if (g.far) {
         const size_t r = size_t(g.r);
         L.sleaf = take(r * kLeafPts * tq);

@@ -135,6 +135,28 @@ __global__ void k_ops_m2l(int dim, int nc, int r, int lev0, int nlev, KernelPara
     out[idx] = (T)kernel_from_r2<double>(r2, kp);
 }
 
+// Near-field kernel blocks: on a uniform grid the 64 x 64 block between a
+// target leaf b and a source leaf b + o depends on o only.  For the 3^dim
+// offsets o in [-1, 1]^dim (slot (ox+1) + 3 (oy+1) (+ 9 (oz+1))):
+// out[slot][i][j] = K(h |o ls + l_j - l_i|).
+template <typename T>
+__global__ void k_ops_near(int dim, int ls, KernelParams kp, double h, T *out) {
+    const int nslot = dim == 2 ? 9 : 27;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nslot * kLeafPts * kLeafPts) return;
+    const int sl = idx / (kLeafPts * kLeafPts), i = (idx / kLeafPts) % kLeafPts, j = idx % kLeafPts;
+    const int o[3] = {sl % 3 - 1, (sl / 3) % 3 - 1, sl / 9 - 1};
+    int li[3], lj[3];
+    leaf_local(i, dim, li);
+    leaf_local(j, dim, lj);
+    int dsq = 0;
+    for (int q = 0; q < dim; ++q) {
+        const int d = o[q] * ls + lj[q] - li[q];
+        dsq += d * d;
+    }
+    out[idx] = kernel_from_r2<T>((T)dsq * (T)(h * h), kp);
+}
+
 // ---------------------------------------------------------------- W = H^T
 template <typename T>
 __global__ void k_scatter_w(int64_t nnz, int p, int64_t m, const int64_t *rowptr,
@@ -292,7 +314,8 @@ template <> struct Mma<double> {
 template <typename T, int PT>
 __global__ void __launch_bounds__(kBlock)
 k_l2p_p2p_mma(int dim, int n, int ls, int depth, int r, int rpad, int p, int rad, int far,
-              KernelParams kp, T h2, const T *W, const T *Sleaf, const T *Lleaf, T *CQ) {
+              KernelParams kp, T h2, const T *W, const T *Sleaf, const T *Lleaf, const T *Knear,
+              T *CQ) {
     typedef typename Mma<T>::v4 v4;
     constexpr int NTI = PT / 16;
     constexpr int WP = PT + Mma<T>::pad;
@@ -318,21 +341,43 @@ k_l2p_p2p_mma(int dim, int n, int ls, int depth, int r, int rpad, int p, int rad
     for (int ax = max(0, b[0] - rad); ax <= min(nb - 1, b[0] + rad); ++ax) {
         int a[3] = {ax, ay, az};
         __syncthreads();
-        for (int idx = tid; idx < kLeafPts * PT; idx += kBlock) {
-            const int j = idx / PT, c = idx % PT;
-            sW[j * WP + c] = (c < ncols) ? W[leaf_point(a, j, dim, n, ls) * p + c0 + c] : (T)0;
-        }
-        for (int idx = tid; idx < kLeafPts * kLeafPts; idx += kBlock) {
-            const int i = idx / kLeafPts, j = idx % kLeafPts;
-            int li[3], lj[3];
-            leaf_local(i, dim, li);
-            leaf_local(j, dim, lj);
-            int dsq = 0;
-            for (int qq = 0; qq < dim; ++qq) {
-                const int d = (a[qq] - b[qq]) * ls + lj[qq] - li[qq];
-                dsq += d * d;
+        // W_A: 64 rows of PT values as 16-byte pieces
+        constexpr int VW = 16 / sizeof(T), CH = PT / VW;
+        typedef T tv __attribute__((ext_vector_type(VW)));
+        for (int idx = tid; idx < kLeafPts * CH; idx += kBlock) {
+            const int j = idx / CH, ch = idx % CH;
+            tv v;
+            if (VW * ch < ncols) {
+                v = *reinterpret_cast<const tv *>(W + leaf_point(a, j, dim, n, ls) * p + c0 + VW * ch);
+            } else {
+#pragma unroll
+                for (int e = 0; e < VW; ++e) v[e] = (T)0;
             }
-            sK[i * KP + j] = kernel_from_r2<T>((T)dsq * h2, kp);
+            *reinterpret_cast<tv *>(sW + j * WP + VW * ch) = v;
+        }
+        if (Knear) {
+            // the kernel block of offset a - b from the table
+            const int sl = (a[0] - b[0] + 1) + 3 * (a[1] - b[1] + 1) + (dim == 3 ? 9 * (a[2] - b[2] + 1) : 0);
+            const T *kt = Knear + int64_t(sl) * kLeafPts * kLeafPts;
+            constexpr int KC = kLeafPts / VW;
+            for (int idx = tid; idx < kLeafPts * KC; idx += kBlock) {
+                const int i = idx / KC, ch = idx % KC;
+                *reinterpret_cast<tv *>(sK + i * KP + VW * ch) =
+                    *reinterpret_cast<const tv *>(kt + i * kLeafPts + VW * ch);
+            }
+        } else {
+            for (int idx = tid; idx < kLeafPts * kLeafPts; idx += kBlock) {
+                const int i = idx / kLeafPts, j = idx % kLeafPts;
+                int li[3], lj[3];
+                leaf_local(i, dim, li);
+                leaf_local(j, dim, lj);
+                int dsq = 0;
+                for (int qq = 0; qq < dim; ++qq) {
+                    const int d = (a[qq] - b[qq]) * ls + lj[qq] - li[qq];
+                    dsq += d * d;
+                }
+                sK[i * KP + j] = kernel_from_r2<T>((T)dsq * h2, kp);
+            }
         }
         __syncthreads();
         const T *arow = sK + (16 * wave + lr) * KP + q;
@@ -628,7 +673,7 @@ template <bool SPLIT, int PT>
 __global__ void __launch_bounds__(kBlock)
 k_l2p_p2p_bf16(int dim, int n, int ls, int depth, int r, int rpad, int p, int rad, int far,
                KernelParams kp, float h2, const __bf16 *Wh, const __bf16 *Wl,
-               const float *Sleaf, const float *Lleaf, float *CQ) {
+               const float *Sleaf, const float *Lleaf, const float *Knear, float *CQ) {
     constexpr int NTI = PT / 16;
     constexpr int KPB = kLeafPts + 8;                  // bf16 row pitch
     constexpr int WP = PT + Mma<float>::pad;
@@ -669,18 +714,24 @@ k_l2p_p2p_bf16(int dim, int n, int ls, int depth, int r, int rpad, int p, int ra
             *reinterpret_cast<bf8 *>(sWh + c * KPB + 8 * ch) = vh;
             *reinterpret_cast<bf8 *>(sWl + c * KPB + 8 * ch) = vl;
         }
+        const int sl = (a[0] - b[0] + 1) + 3 * (a[1] - b[1] + 1) + (dim == 3 ? 9 * (a[2] - b[2] + 1) : 0);
         for (int idx = tid; idx < kLeafPts * kLeafPts; idx += kBlock) {
             const int i = idx / kLeafPts, j = idx % kLeafPts;
-            int li[3], lj[3];
-            leaf_local(i, dim, li);
-            leaf_local(j, dim, lj);
-            int dsq = 0;
-            for (int qq = 0; qq < dim; ++qq) {
-                const int d = (a[qq] - b[qq]) * ls + lj[qq] - li[qq];
-                dsq += d * d;
+            float kv;
+            if (Knear) {
+                kv = Knear[int64_t(sl) * kLeafPts * kLeafPts + idx];
+            } else {
+                int li[3], lj[3];
+                leaf_local(i, dim, li);
+                leaf_local(j, dim, lj);
+                int dsq = 0;
+                for (int qq = 0; qq < dim; ++qq) {
+                    const int d = (a[qq] - b[qq]) * ls + lj[qq] - li[qq];
+                    dsq += d * d;
+                }
+                kv = kernel_from_r2<float>((float)dsq * h2, kp);
             }
-            split_bf16(kernel_from_r2<float>((float)dsq * h2, kp), sKh + i * KPB + j,
-                       sKl + i * KPB + j);
+            split_bf16(kv, sKh + i * KPB + j, sKl + i * KPB + j);
         }
         __syncthreads();
         const __bf16 *ah = sKh + (16 * wave + lr) * KPB + 8 * q;
@@ -860,6 +911,15 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
                                Llev(lev), Schild, Llev(lev + 1));
         tend(tm, HIKF_PHASE_L2L, s);
     }
+    // near-field kernel blocks by leaf offset (all neighbours are within one
+    // leaf unless the exact all-pairs sum is requested)
+    T *Knear = nullptr;
+    if (!g.direct) {
+        Knear = reinterpret_cast<T *>(scr + lay.knear);
+        const int tot = (dim == 2 ? 9 : 27) * kLeafPts * kLeafPts;
+        hipLaunchKernelGGL(k_ops_near<T>, dim3((tot + 255) / 256), dim3(256), 0, s, dim, g.ls, g.kp,
+                           1.0 / g.n, Knear);
+    }
     if constexpr (sizeof(T) == 4) {
         if (bf16) {
             const int rpad = (r + 3) / 4 * 4;
@@ -886,12 +946,12 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
                 hipLaunchKernelGGL((k_l2p_p2p_bf16<true, 128>), dim3(unsigned(leaves), (p + 127) / 128),
                                    dim3(kBlock), lds, s, dim, g.n, g.ls, D, r, rpad, p, rad,
                                    g.far ? 1 : 0, g.kp, (float)(h * h), Wh, Wl, Sleaf,
-                                   g.far ? Llev(D) : W, CQ);
+                                   g.far ? Llev(D) : W, Knear, CQ);
             else
                 hipLaunchKernelGGL((k_l2p_p2p_bf16<false, 128>), dim3(unsigned(leaves), (p + 127) / 128),
                                    dim3(kBlock), lds, s, dim, g.n, g.ls, D, r, rpad, p, rad,
                                    g.far ? 1 : 0, g.kp, (float)(h * h), Wh, Wl, Sleaf,
-                                   g.far ? Llev(D) : W, CQ);
+                                   g.far ? Llev(D) : W, Knear, CQ);
             tend(tm, HIKF_PHASE_P2P, s);
             return hipGetLastError();
         }
@@ -908,7 +968,7 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
         tbegin(tm, HIKF_PHASE_P2P, s);
         hipLaunchKernelGGL((k_l2p_p2p_mma<T, PPT>), dim3(unsigned(g.boxes(D)), (p + PPT - 1) / PPT),
                            dim3(kBlock), lds, s, dim, g.n, g.ls, D, r, rpad, p, rad, g.far ? 1 : 0,
-                           g.kp, (T)(h * h), W, Sleaf, g.far ? Llev(D) : W, CQ);
+                           g.kp, (T)(h * h), W, Sleaf, g.far ? Llev(D) : W, Knear, CQ);
         tend(tm, HIKF_PHASE_P2P, s);
     }
     return hipGetLastError();

@@ -86,7 +86,7 @@ struct Layout {
     size_t psA, pivs;                         // p-space ping-pong buffer (with xbuf), pivots
     size_t resident_bytes;
     // scratch
-    size_t W, sleaf, schild, m2l, lev_off;   // lev_off: start of M/L storage
+    size_t W, knear, sleaf, schild, m2l, lev_off;   // lev_off: start of M/L storage
     size_t ML_level[24];                      // per-level offset of M (L follows after all M)
     size_t L_base;
     size_t Wsplit, Tsplit, MS_level[24];      // BF16 hi/lo operands (BF16 modes only)
