@@ -64,6 +64,15 @@ def tree_depth(n, leaf):
     return int(round(np.log2(nl)))
 
 
+def padded_size(n, leaf):
+    """Cells per axis of the tree for an N-cell axis: the smallest
+    leaf * 2^D >= N (reading for grids that are not leaf * 2^D)."""
+    npad = leaf
+    while npad < n:
+        npad *= 2
+    return npad
+
+
 def _to_leaves(W, dim, n, leaf):
     """Grid-order (m, p) -> (nl,)*dim + (leaf^dim, p), coordinate-major."""
     p = W.shape[1]
@@ -105,8 +114,8 @@ def il_offsets(dim):
 
 
 def interaction_counts(dim, n, leaf):
-    """(near pairs, interaction-list pairs) of the uniform tree."""
-    D = tree_depth(n, leaf)
+    """(near pairs, interaction-list pairs) of the uniform (padded) tree."""
+    D = tree_depth(padded_size(n, leaf), leaf)
     nl = 2 ** D
     near = 0
     for o in itertools.product((-1, 0, 1), repeat=dim):
@@ -121,15 +130,33 @@ def interaction_counts(dim, n, leaf):
 
 def bbfmm_apply(dim, n, W, nc, leaf=None, family="powexp", theta=1.0,
                 ell=1.0, gamma=1.0):
-    """Approximate Q @ W (W is (m, p) in grid order) by the black-box FMM."""
+    """Approximate Q @ W (W is (m, p) in grid order) by the black-box FMM.
+
+    An N that is not leaf * 2^D is handled by the padded-tree reading: the
+    tree covers Npad = padded_size(N, leaf) cells per axis of the same size
+    h = 1/N (root box [0, Npad h]^dim), the cells beyond N carry zero weight,
+    and only the N^dim real rows are returned."""
     if leaf is None:
         leaf = 8 if dim == 2 else 4
     W = np.asarray(W, np.float64)
     if W.ndim == 1:
         W = W[:, None]
+    npad = padded_size(n, leaf)
+    if npad != n:
+        p = W.shape[1]
+        Wp = np.zeros((npad,) * dim + (p,))
+        Wp[(slice(0, n),) * dim] = W.reshape((n,) * dim + (p,))
+        out = _bbfmm_tree(dim, npad, 1.0 / n, Wp.reshape(npad ** dim, p), nc, leaf,
+                          family, theta, ell, gamma)
+        return out.reshape((npad,) * dim + (p,))[(slice(0, n),) * dim].reshape(n ** dim, p)
+    return _bbfmm_tree(dim, n, 1.0 / n, W, nc, leaf, family, theta, ell, gamma)
+
+
+def _bbfmm_tree(dim, n, h, W, nc, leaf, family, theta, ell, gamma):
+    """The FMM passes on a tree of n = leaf * 2^D cells per axis of side h
+    (grid-order layout of ``W`` and of the result, the first axis fastest)."""
     K = kernel(family, theta, ell, gamma)
     D = tree_depth(n, leaf)
-    h = 1.0 / n
     xi = cheb_nodes(nc)
     kidx = _multi(nc, dim)
     lidx = _multi(leaf, dim)
@@ -170,7 +197,7 @@ def bbfmm_apply(dim, n, W, nc, leaf=None, family="powexp", theta=1.0,
         L = {}
         for lev in range(2, D + 1):
             nb = 2 ** lev
-            s = 1.0 / nb
+            s = n * h / nb                                # box side
             acc = np.zeros_like(M[lev])
             for o in il_offsets(dim):
                 diff = s * (np.asarray(o)[None, None, :]

@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import bbfmm, cq_exact
+from oracle import bbfmm, cq_exact, kernels
 
 
 def _rel(a, b):
@@ -91,3 +91,27 @@ def test_interior_list_sizes():
                    (5 in bbfmm._il_axis_targets(16, v)) for v in o):
                 counts += 1
         assert counts == (27 if dim == 2 else 189)
+
+
+@pytest.mark.parametrize("dim,n,nc", [(2, 40, 3), (2, 20, 4), (3, 12, 3), (3, 6, 3)])
+def test_padded_tree_polynomial_kernel_exact(dim, n, nc):
+    # N not of the form leaf * 2^D: the tree is padded with zero-weight cells
+    # (root box Npad / N); Chebyshev interpolation is still exact for K = r^2,
+    # so the product must equal the dense one (catches padding, scaling and
+    # index mistakes)
+    rng = np.random.default_rng(5)
+    m = n ** dim
+    W = rng.standard_normal((m, 3))
+    Q = kernels.dense_q(synth.cell_centres(dim, n), "r2", 1.0, 1.0, 1.0)
+    got = bbfmm.bbfmm_apply(dim, n, W, nc, None, "r2", 1.0, 1.0, 1.0)
+    np.testing.assert_allclose(got, Q @ W, rtol=1e-12, atol=1e-12 * np.abs(Q @ W).max())
+
+
+def test_padded_tree_converges_for_smooth_kernel():
+    n = 40
+    pts = synth.cell_centres(2, n)
+    W = np.random.default_rng(6).standard_normal((n * n, 2))
+    ref = kernels.dense_q(pts, "powexp", 1.0, 0.3, 1.0) @ W
+    errs = [np.linalg.norm(bbfmm.bbfmm_apply(2, n, W, nc, None, "powexp", 1.0, 0.3, 1.0) - ref)
+            / np.linalg.norm(ref) for nc in (3, 4, 5, 6)]
+    assert all(errs[i + 1] < 0.5 * errs[i] for i in range(3)), errs
