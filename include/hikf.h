@@ -166,8 +166,10 @@ typedef struct hikf_filter hikf_filter;
  * no device memory and allocates nothing.
  * Errors: HIKF_E_INVALID (dim not 2/3, N < 1, p < 1, nnz < 0, theta/ell not
  * positive, gamma outside (0, 2], n_c outside 1..8, NULL arrays),
- * HIKF_E_UNSUPPORTED (N not leaf * 2^k with leaf 8 (2-D) / 4 (3-D), p not a
- * multiple of 16 or above 512, n_c^dim above 64).
+ * HIKF_E_UNSUPPORTED (p not a multiple of 16 or above 512, n_c^dim above
+ * 64, a tree of 2^31 cells or more).  Any N >= 1 is accepted: the tree
+ * covers Npad = leaf * 2^D >= N cells per axis (leaf 8 in 2-D, 4 in 3-D) of
+ * the same size 1/N, the cells beyond N carry no weight, and out.depth is D.
  */
 hikf_status hikf_plan(const hikf_problem *prob, const hikf_options *opt,
                       hikf_plan_info *out);

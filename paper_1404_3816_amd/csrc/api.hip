@@ -41,7 +41,7 @@ Layout make_layout(const Geometry &g) {
     L.resident_bytes = off;
 
     off = 0;
-    L.W = take(m * p * tq);
+    L.W = take(size_t(g.mpad) * p * tq);
     L.knear = take(size_t(g.dim == 2 ? 9 : 27) * kLeafPts * kLeafPts * tq);
     if (g.far) {
         const size_t r = size_t(g.r);
@@ -134,8 +134,6 @@ namespace {
 
 using hikf::Geometry;
 
-bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
-
 hikf_status build_geometry(const hikf_problem *pr, const hikf_options *op, Geometry *g) {
     if (!pr || !op || !g) return HIKF_E_INVALID;
     if (pr->dim != 2 && pr->dim != 3) return HIKF_E_INVALID;
@@ -159,14 +157,16 @@ hikf_status build_geometry(const hikf_problem *pr, const hikf_options *op, Geome
     g->dim = pr->dim;
     g->n = pr->n;
     g->ls = pr->dim == 2 ? 8 : 4;
-    if (pr->n % g->ls) return HIKF_E_UNSUPPORTED;
-    const int nl = pr->n / g->ls;
-    if (!is_pow2(nl)) return HIKF_E_UNSUPPORTED;
+    // the tree covers npad = ls * 2^D >= n cells per axis; cells beyond n
+    // are padding with zero weight (their rows are never produced)
+    if (pr->n > (1 << 20)) return HIKF_E_UNSUPPORTED;
     int D = 0;
-    while ((1 << D) < nl) ++D;
+    while ((g->ls << D) < pr->n) ++D;
     g->depth = D;
+    g->npad = g->ls << D;
     g->m = int64_t(pr->n) * pr->n * (pr->dim == 3 ? pr->n : 1);
-    if (g->m >= (int64_t(1) << 31)) return HIKF_E_UNSUPPORTED;
+    g->mpad = int64_t(g->npad) * g->npad * (pr->dim == 3 ? g->npad : 1);
+    if (g->mpad >= (int64_t(1) << 31)) return HIKF_E_UNSUPPORTED;
     if (pr->p % 16 != 0 || pr->p > hikf::kMaxP) return HIKF_E_UNSUPPORTED;
     g->p = pr->p;
     g->pp = (pr->p + 31) / 32 * 32;

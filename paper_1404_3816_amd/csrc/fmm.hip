@@ -73,6 +73,16 @@ __device__ __forceinline__ int64_t leaf_point(const int *bc, int j, int dim, int
     return g;
 }
 
+// grid-order index of local point j of leaf bc among the N^dim real cells,
+// or -1 for a padding cell of the tree (grids that are not leaf * 2^D)
+__device__ __forceinline__ int64_t leaf_point_real(const int *bc, int j, int dim, int n, int ls) {
+    int l[3];
+    leaf_local(j, dim, l);
+    const int x = bc[0] * ls + l[0], y = bc[1] * ls + l[1], z = dim == 3 ? bc[2] * ls + l[2] : 0;
+    if (x >= n || y >= n || z >= n) return -1;
+    return x + int64_t(n) * (y + int64_t(n) * z);
+}
+
 // ---------------------------------------------------------------- operators
 template <typename T>
 __global__ void k_ops_sleaf(int dim, int nc, int ls, int r, T *out) {
@@ -109,7 +119,7 @@ __global__ void k_ops_schild(int dim, int nc, int r, T *out) {
 // T_{l,o}[k][k'] = K(s_l * |o + (xi_k' - xi_k)/2|), o in [-3,3]^dim, slot
 // oi = (ox+3) + 7 (oy+3) (+ 49 (oz+3)); slots with max|o| < 2 are zero.
 template <typename T>
-__global__ void k_ops_m2l(int dim, int nc, int r, int lev0, int nlev, KernelParams kp,
+__global__ void k_ops_m2l(int dim, int nc, int r, int lev0, int nlev, double root, KernelParams kp,
                           T *out) {
     int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     int noff = dim == 2 ? 49 : 343;
@@ -127,7 +137,7 @@ __global__ void k_ops_m2l(int dim, int nc, int r, int lev0, int nlev, KernelPara
     int kk[3], kq3[3];
     node_idx(k, nc, kk);
     node_idx(kq, nc, kq3);
-    double s = 1.0 / double(int64_t(1) << lev), r2 = 0.0;
+    double s = root / double(int64_t(1) << lev), r2 = 0.0;      // box side
     for (int ax = 0; ax < dim; ++ax) {
         double d = s * (o[ax] + 0.5 * (cheb_node(nc, kq3[ax]) - cheb_node(nc, kk[ax])));
         r2 += d * d;
@@ -159,8 +169,8 @@ __global__ void k_ops_near(int dim, int ls, KernelParams kp, double h, T *out) {
 
 // ---------------------------------------------------------------- W = H^T
 template <typename T>
-__global__ void k_scatter_w(int64_t nnz, int p, int64_t m, const int64_t *rowptr,
-                            const int32_t *col, const double *val, T *W) {
+__global__ void k_scatter_w(int64_t nnz, int p, int64_t m, int dim, int n, int npad,
+                            const int64_t *rowptr, const int32_t *col, const double *val, T *W) {
     int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= nnz) return;
     int lo = 0, hi = p - 1;
@@ -171,7 +181,9 @@ __global__ void k_scatter_w(int64_t nnz, int p, int64_t m, const int64_t *rowptr
     if (rowptr[lo] > e || rowptr[lo + 1] <= e) return;
     int64_t c = col[e];
     if (c < 0 || c >= m) return;
-    W[c * p + lo] = (T)val[e];
+    // W is laid out over the tree's Npad^dim cells
+    const int64_t x = c % n, y = (c / n) % n, z = dim == 3 ? c / (int64_t(n) * n) : 0;
+    W[(x + int64_t(npad) * (y + int64_t(npad) * z)) * p + lo] = (T)val[e];
 }
 
 // ---------------------------------------------------------------- P2M
@@ -313,7 +325,7 @@ template <> struct Mma<double> {
 // S_leaf^T (64 x r) L_B (r x PT) the same way.
 template <typename T, int PT>
 __global__ void __launch_bounds__(kBlock)
-k_l2p_p2p_mma(int dim, int n, int ls, int depth, int r, int rpad, int p, int rad, int far,
+k_l2p_p2p_mma(int dim, int n, int npad, int ls, int depth, int r, int rpad, int p, int rad, int far,
               KernelParams kp, T h2, const T *W, const T *Sleaf, const T *Lleaf, const T *Knear,
               T *CQ) {
     typedef typename Mma<T>::v4 v4;
@@ -348,7 +360,7 @@ k_l2p_p2p_mma(int dim, int n, int ls, int depth, int r, int rpad, int p, int rad
             const int j = idx / CH, ch = idx % CH;
             tv v;
             if (VW * ch < ncols) {
-                v = *reinterpret_cast<const tv *>(W + leaf_point(a, j, dim, n, ls) * p + c0 + VW * ch);
+                v = *reinterpret_cast<const tv *>(W + leaf_point(a, j, dim, npad, ls) * p + c0 + VW * ch);
             } else {
 #pragma unroll
                 for (int e = 0; e < VW; ++e) v[e] = (T)0;
@@ -415,7 +427,8 @@ k_l2p_p2p_mma(int dim, int n, int ls, int depth, int r, int rpad, int p, int rad
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
             const int i = 16 * wave + Mma<T>::row(q, rr);
-            CQ[leaf_point(b, i, dim, n, ls) * p + c0 + c] = acc[t][rr];
+            const int64_t g = leaf_point_real(b, i, dim, n, ls);
+            if (g >= 0) CQ[g * p + c0 + c] = acc[t][rr];
         }
     }
 }
@@ -523,7 +536,7 @@ __device__ __forceinline__ f4v mma_bf16(const bf8 &ah, const bf8 &al, const bf8 
 
 // W = H^T split per leaf as [leaf][column][point] (hi block, then lo block);
 // the region is zeroed first.  Each nonzero of H is one entry.
-__global__ void k_split_w(int64_t nnz, int p, int64_t m, int dim, int n, int ls,
+__global__ void k_split_w(int64_t nnz, int p, int64_t m, int dim, int n, int npad, int ls,
                           const int64_t *rowptr, const int32_t *col, const double *val,
                           __bf16 *Wh, __bf16 *Wl) {
     int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -540,7 +553,7 @@ __global__ void k_split_w(int64_t nnz, int p, int64_t m, int dim, int n, int ls,
     int bc[3] = {g[0] / ls, g[1] / ls, g[2] / ls};
     const int j = dim == 2 ? (g[0] % ls) + 8 * (g[1] % ls)
                            : (g[0] % ls) + 4 * (g[1] % ls) + 16 * (g[2] % ls);
-    const int64_t leaf = box_index(bc, n / ls, dim);
+    const int64_t leaf = box_index(bc, npad / ls, dim);
     const int64_t o = (leaf * p + lo) * kLeafPts + j;
     split_bf16((float)val[e], Wh + o, Wl + o);
 }
@@ -671,7 +684,7 @@ k_m2l_bf16(int dim, int r, int kr, int p, int lev, const __bf16 *Mh, const __bf1
 // pre-split ([column][source]); the far field S_leaf^T L_B stays on FP32 MFMA.
 template <bool SPLIT, int PT>
 __global__ void __launch_bounds__(kBlock)
-k_l2p_p2p_bf16(int dim, int n, int ls, int depth, int r, int rpad, int p, int rad, int far,
+k_l2p_p2p_bf16(int dim, int n, int npad, int ls, int depth, int r, int rpad, int p, int rad, int far,
                KernelParams kp, float h2, const __bf16 *Wh, const __bf16 *Wl,
                const float *Sleaf, const float *Lleaf, const float *Knear, float *CQ) {
     constexpr int NTI = PT / 16;
@@ -779,7 +792,8 @@ k_l2p_p2p_bf16(int dim, int n, int ls, int depth, int r, int rpad, int p, int ra
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
             const int i = 16 * wave + 4 * q + rr;
-            CQ[leaf_point(b, i, dim, n, ls) * p + c0 + c] = acc[t][rr];
+            const int64_t g = leaf_point_real(b, i, dim, n, ls);
+            if (g >= 0) CQ[g * p + c0 + c] = acc[t][rr];
         }
     }
 }
@@ -814,12 +828,12 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
     const int32_t *col = reinterpret_cast<const int32_t *>(res + lay.col);
     const double *val = reinterpret_cast<const double *>(res + lay.val);
     tbegin(tm, HIKF_PHASE_INIT, s);
-    hipError_t e = hipMemsetAsync(W, 0, size_t(m) * p * sizeof(T), s);
+    hipError_t e = hipMemsetAsync(W, 0, size_t(g.mpad) * p * sizeof(T), s);
     if (e != hipSuccess) return e;
     if (g.nnz > 0) {
         int64_t blocks = (g.nnz + kBlock - 1) / kBlock;
         hipLaunchKernelGGL(k_scatter_w<T>, dim3(unsigned(blocks)), dim3(kBlock), 0, s,
-                           g.nnz, p, m, rowptr, col, val, W);
+                           g.nnz, p, m, dim, g.n, g.npad, rowptr, col, val, W);
     }
     tend(tm, HIKF_PHASE_INIT, s);
     T *Sleaf = reinterpret_cast<T *>(scr + lay.sleaf);
@@ -840,13 +854,13 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
                            dim, g.nc, r, Schild);
         int64_t tot64 = int64_t(D - 1) * g.noff() * r * r;
         hipLaunchKernelGGL(k_ops_m2l<T>, dim3(unsigned((tot64 + 255) / 256)), dim3(256), 0, s,
-                           dim, g.nc, r, 2, D - 1, g.kp, Tm2l);
+                           dim, g.nc, r, 2, D - 1, double(g.npad) / g.n, g.kp, Tm2l);
         tend(tm, HIKF_PHASE_OPERATORS, s);
         // P2M
         tbegin(tm, HIKF_PHASE_P2M, s);
         int PT = min(64, p);
         hipLaunchKernelGGL(k_p2m<T>, dim3(unsigned(g.boxes(D)), (p + PT - 1) / PT), dim3(kBlock),
-                           kLeafPts * PT * sizeof(T), s, dim, g.n, g.ls, D, r, p, PT, W, Sleaf,
+                           kLeafPts * PT * sizeof(T), s, dim, g.npad, g.ls, D, r, p, PT, W, Sleaf,
                            Mlev(D));
         tend(tm, HIKF_PHASE_P2M, s);
         // M2M
@@ -933,7 +947,7 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
             if (e != hipSuccess) return e;
             if (g.nnz > 0)
                 hipLaunchKernelGGL(k_split_w, dim3(unsigned((g.nnz + kBlock - 1) / kBlock)),
-                                   dim3(kBlock), 0, s, g.nnz, p, m, dim, g.n, g.ls, rowptr, col, val,
+                                   dim3(kBlock), 0, s, g.nnz, p, m, dim, g.n, g.npad, g.ls, rowptr, col, val,
                                    Wh, Wl);
             const size_t near_lds = size_t(kLeafPts + 128) * (kLeafPts + 8) * 2 * sizeof(__bf16);
             const size_t far_lds = (size_t(kLeafPts) * (max(kLeafPts, rpad) + 4) +
@@ -944,12 +958,12 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
             if (e != hipSuccess) return e;
             if (split)
                 hipLaunchKernelGGL((k_l2p_p2p_bf16<true, 128>), dim3(unsigned(leaves), (p + 127) / 128),
-                                   dim3(kBlock), lds, s, dim, g.n, g.ls, D, r, rpad, p, rad,
+                                   dim3(kBlock), lds, s, dim, g.n, g.npad, g.ls, D, r, rpad, p, rad,
                                    g.far ? 1 : 0, g.kp, (float)(h * h), Wh, Wl, Sleaf,
                                    g.far ? Llev(D) : W, Knear, CQ);
             else
                 hipLaunchKernelGGL((k_l2p_p2p_bf16<false, 128>), dim3(unsigned(leaves), (p + 127) / 128),
-                                   dim3(kBlock), lds, s, dim, g.n, g.ls, D, r, rpad, p, rad,
+                                   dim3(kBlock), lds, s, dim, g.n, g.npad, g.ls, D, r, rpad, p, rad,
                                    g.far ? 1 : 0, g.kp, (float)(h * h), Wh, Wl, Sleaf,
                                    g.far ? Llev(D) : W, Knear, CQ);
             tend(tm, HIKF_PHASE_P2P, s);
@@ -967,7 +981,7 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
         if (e != hipSuccess) return e;
         tbegin(tm, HIKF_PHASE_P2P, s);
         hipLaunchKernelGGL((k_l2p_p2p_mma<T, PPT>), dim3(unsigned(g.boxes(D)), (p + PPT - 1) / PPT),
-                           dim3(kBlock), lds, s, dim, g.n, g.ls, D, r, rpad, p, rad, g.far ? 1 : 0,
+                           dim3(kBlock), lds, s, dim, g.n, g.npad, g.ls, D, r, rpad, p, rad, g.far ? 1 : 0,
                            g.kp, (T)(h * h), W, Sleaf, g.far ? Llev(D) : W, Knear, CQ);
         tend(tm, HIKF_PHASE_P2P, s);
     }

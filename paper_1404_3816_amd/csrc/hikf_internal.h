@@ -54,6 +54,7 @@ __device__ __forceinline__ float kernel_from_r2<float>(float r2, const KernelPar
 struct Geometry {
     int dim = 2;
     int n = 0;                    // cells per axis
+    int npad = 0;                 // cells per axis of the tree: ls * 2^depth >= n
     int ls = 8;                   // cells per leaf per axis
     int depth = 0;                // leaves per axis = 2^depth
     int nc = 4;                   // Chebyshev nodes per axis
@@ -62,7 +63,8 @@ struct Geometry {
     int pp = 32;                  // p rounded up to 32 (p-space layout)
     int cpr = 1;                  // gather chunks per ray
     int num_cu = 256;             // compute units of the device (persistent grids)
-    int64_t m = 0;
+    int64_t m = 0;                // n^dim cells (state size)
+    int64_t mpad = 0;             // npad^dim cells of the tree
     int64_t nnz = 0;
     bool direct = false;
     bool far = false;             // far field present (depth >= 2 and not direct)

@@ -55,7 +55,8 @@ def _plan(pr, n_c=4, precision=0, direct=0):
     return st, info
 
 
-@pytest.mark.parametrize("dim,n", [(2, 32), (2, 256), (2, 1024), (3, 128), (3, 16)])
+@pytest.mark.parametrize("dim,n", [(2, 32), (2, 256), (2, 1024), (3, 128), (3, 16),
+                                   (2, 33), (2, 59), (2, 1000), (3, 12), (3, 100)])
 def test_plan_tree_counts_match_oracle(dim, n):
     from paper_1404_3816_amd import hikf as H
     st, info = _plan(_problem(dim=dim, n=n, p=64))
@@ -65,6 +66,7 @@ def test_plan_tree_counts_match_oracle(dim, n):
     assert info.near_pairs == near
     assert info.far_pairs == far
     assert info.m == n ** dim
+    assert leaf << info.depth == bbfmm.padded_size(n, leaf)
     assert info.r == 4 ** dim
     # resident state holds at least C (FP64) and C_Q (FP32): 12 m p bytes
     assert info.resident_bytes >= 12 * info.m * 64
@@ -89,8 +91,7 @@ def test_plan_rejects_bad_input():
 
 def test_plan_reports_unsupported_shapes():
     from paper_1404_3816_amd import hikf as H
-    assert _plan(_problem(n=33))[0] == H.HIKF_E_UNSUPPORTED      # not 8 * 2^k
-    assert _plan(_problem(n=24))[0] == H.HIKF_E_UNSUPPORTED
+    assert _plan(_problem(dim=3, n=1300))[0] == H.HIKF_E_UNSUPPORTED   # 2048^3-cell tree
     assert _plan(_problem(p=20))[0] == H.HIKF_E_UNSUPPORTED      # not a multiple of 16
     assert _plan(_problem(p=528))[0] == H.HIKF_E_UNSUPPORTED     # above 512
     assert _plan(_problem(dim=3, n=16), n_c=6)[0] == H.HIKF_E_UNSUPPORTED  # r > 128

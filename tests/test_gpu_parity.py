@@ -84,6 +84,34 @@ def test_cq_bf16_split_matches_oracle_bbfmm(dim, n, p, n_c, ell, gamma):
     assert errs["bf16"] > 20 * errs["bf16x3"]
 
 
+@pytest.mark.parametrize("dim,n,p,n_c,ell,gamma", [
+    (2, 40, 16, 4, 0.3, 1.0),      # padded to 64: 24 empty cells per axis
+    (2, 100, 32, 5, 0.1, 2.0),     # padded to 128
+    (3, 12, 16, 4, 0.2, 1.0),      # padded to 16
+    (3, 20, 32, 4, 0.2, 1.0),      # padded to 32
+])
+@pytest.mark.parametrize("precision", ["f64", "f32", "bf16x3"])
+def test_cq_padded_tree_matches_oracle_bbfmm(dim, n, p, n_c, ell, gamma, precision):
+    # N not of the form leaf * 2^D: the tree covers Npad cells per axis with
+    # zero-weight padding; the oracle's bbFMM takes the same reading
+    case = Case(dim, n, p, ell=ell, gamma=gamma, steps=1, planes=2)
+    f = case.gpu_filter(n_c=n_c, precision=precision)
+    cq = f.export_cq().cpu().numpy()
+    f.close()
+    ref = case.cq_bbfmm(n_c)
+    tol = {"f64": 1e-12, "f32": 2e-6, "bf16x3": 1e-4}[precision]
+    assert rel(cq, ref) < tol
+
+
+@pytest.mark.parametrize("dim,n,n_c", [(2, 40, 3), (3, 12, 3)])
+def test_cq_padded_polynomial_kernel_exact(dim, n, n_c):
+    case = Case(dim, n, 16, family="r2", steps=1)
+    f = case.gpu_filter(n_c=n_c, precision="f64")
+    cq = f.export_cq().cpu().numpy()
+    f.close()
+    assert rel(cq, case.cq_exact()) < 1e-12
+
+
 @pytest.mark.parametrize("dim,n,n_c", [(2, 64, 3), (2, 64, 4), (3, 16, 3)])
 def test_cq_polynomial_kernel_exact(dim, n, n_c):
     # Chebyshev interpolation reproduces K = r^2 exactly for n_c >= 3, so the
@@ -115,6 +143,16 @@ def test_steps_direct_f64_match_dense_kf():
     assert max_step_rel(vs, va) < 1e-10
 
 
+def test_steps_padded_grid_direct_f64_match_dense_kf():
+    # 59 x 59 (the paper's coarsest grid is 59 x 55): tree padded to 64
+    case = Case(2, 59, 32, ell=0.2, gamma=1.0, steps=4)
+    _, xs, vs, stats = case.gpu_run(precision="f64", direct=True)
+    xa, va = case.tier_a()
+    assert stats.last_status == 0 and stats.steps_applied == 4
+    assert max_step_rel(xs, xa) < 1e-10
+    assert max_step_rel(vs, va) < 1e-10
+
+
 def _fp32_tolerances(case, cq_exact, cq_gpu):
     """Oracle sensitivity: rerun tier B with C_Q perturbed the way the GPU's
     C_Q differs from the exact one, and allow 4x that response."""
@@ -137,7 +175,8 @@ def test_steps_direct_f32_match_dense_kf():
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32", "bf16x3"])
-@pytest.mark.parametrize("n,p,n_c,ell,gamma", [(32, 16, 4, 0.3, 1.0), (64, 32, 5, 0.1, 2.0)])
+@pytest.mark.parametrize("n,p,n_c,ell,gamma", [(32, 16, 4, 0.3, 1.0), (64, 32, 5, 0.1, 2.0),
+                                               (59, 32, 4, 0.2, 1.0)])
 def test_steps_fmm_match_oracle(precision, n, p, n_c, ell, gamma):
     case = Case(2, n, p, ell=ell, gamma=gamma, steps=4)
     cq, xs, vs, stats = case.gpu_run(n_c=n_c, precision=precision)
