@@ -51,6 +51,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="approximate seconds of CPU work for the oracle sample")
+    ap.add_argument("--serving", action="store_true",
+                    help="instead of the job benchmark: a serving mix of filters stepped "
+                         "by hikf_step_batch under Poisson request arrivals")
+    ap.add_argument("--streams", type=int, default=16, help="serving: filters")
+    ap.add_argument("--requests", type=int, default=2000, help="serving: requests per run")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the jobs, run one plain device copy of this many MiB "
                          "(reference kernel for hardware byte counters)")
@@ -151,6 +156,99 @@ def cpu_baseline(w, assim_steps, budget):
     }
 
 
+def serving(a):
+    """Serving mix: `streams` filters of different sizes, requests arriving as a
+    Poisson process with uniform stream ids.  The dispatcher takes, per round,
+    the oldest pending request of every stream that has one (per-stream order
+    is kept), steps them with one hikf_step_batch call on one stream, and
+    waits for it; a request's latency runs from its arrival to the end of its
+    round.  First a closed loop (all requests at time zero) gives the
+    saturation rate, then Poisson runs at 0.5x and 0.9x of it."""
+    import collections
+
+    import torch
+
+    import synth
+    from paper_1404_3816_amd import filter as F
+
+    torch.cuda.set_device(0)
+    cfgs = synth.serving_streams(a.streams, seed=1)
+    filters, ys, xo, vo = [], [], [], []
+    t0 = time.perf_counter()
+    for c in cfgs:
+        rowptr, col, val = synth.crosswell_h(2, c["n"], c["p"])
+        pr, keep = F.problem_from_csr(2, c["n"], rowptr, col, val, np.full(c["p"], c["r_var"]),
+                                      theta=c["theta"], ell=c["ell"], gamma=c["gamma"],
+                                      prior=c["prior"])
+        filters.append(F.HikfFilter(pr, F.make_options(c["n_c"], "f32", False, graph=True), keep))
+        # measurement values do not change the work of a step
+        ys.append(torch.as_tensor(synth.normal_draws(c["seed"], a.requests, c["p"]) * 1e-2,
+                                  device="cuda"))
+        xo.append(torch.empty(c["m"], dtype=torch.float64, device="cuda"))
+        vo.append(torch.empty(c["m"], dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    log(f"[serving] {len(filters)} filters built in {time.perf_counter() - t0:.1f} s")
+    step_of = [0] * len(filters)
+
+    def run(rate, seed):
+        arr, sid = synth.poisson_requests(a.requests, len(filters), rate, seed)
+        queues = [collections.deque() for _ in filters]
+        lat, done, i = [], 0, 0
+        t_start = time.perf_counter()
+        while done < a.requests:
+            now = time.perf_counter() - t_start
+            while i < a.requests and arr[i] <= now:
+                queues[sid[i]].append(arr[i])
+                i += 1
+            batch = [s for s in range(len(filters)) if queues[s]]
+            if not batch:
+                time.sleep(max(0.0, min(1e-3, arr[i] - now)))
+                continue
+            yb = []
+            for s in batch:
+                yb.append(ys[s][step_of[s] % a.requests])
+                step_of[s] += 1
+            F.step_batch([filters[s] for s in batch], yb, [xo[s] for s in batch],
+                         [vo[s] for s in batch])
+            torch.cuda.synchronize()
+            t_done = time.perf_counter() - t_start
+            for s in batch:
+                lat.append(t_done - queues[s].popleft())
+            done += len(batch)
+        wall = time.perf_counter() - t_start
+        lat = np.array(lat) * 1e3
+        return {"offered_per_s": rate, "achieved_per_s": round(a.requests / wall, 1),
+                "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+
+    run(None, 99)                                       # warm-up
+    sat = run(None, 2)
+    log(f"[serving] closed loop: {sat}")
+    runs = [sat]
+    for frac, sd in ((0.5, 3), (0.9, 4)):
+        r = run(frac * sat["achieved_per_s"], sd)
+        log(f"[serving] {frac} x saturation: {r}")
+        runs.append(r)
+    stats = [f.query() for f in filters]
+    failed = [{"stream": i, "status": st.last_status, "steps": st.steps_applied,
+               "min_pivot": st.min_pivot, "n": cfgs[i]["n"], "p": cfgs[i]["p"]}
+              for i, st in enumerate(stats) if st.last_status != 0]
+    if failed:
+        log(f"[serving] filters whose last step failed: {failed}")
+    for f in filters:
+        f.close()
+    mean_flops = float(np.mean([2.0 * c["m"] * c["p"] ** 2 for c in cfgs]))
+    print(json.dumps({
+        "metric": "serving requests/s (assimilation steps over a mixed set of filters)",
+        "value": sat["achieved_per_s"], "unit": "requests/s", "n_gpus": 1,
+        "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"serving-{len(filters)}-streams", "requests": a.requests,
+                   "streams": [{k: c[k] for k in ("n", "p", "gamma", "ell", "n_c")} for c in cfgs],
+                   "mean_row_pass_flops": mean_flops},
+        "runs": runs, "failed_filters": failed,
+    }), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -158,6 +256,9 @@ def main():
               "single MI355X; the multi-GPU sharding is a design note, not code.",
               file=sys.stderr)
         sys.exit(2)
+    if a.serving:
+        serving(a)
+        return
     import torch
 
     import synth

@@ -12,10 +12,11 @@ produces.
 from .grid import grid_shape, cell_centres, grid_size
 from .rays import crosswell_geometry, crosswell_h, ray_lengths
 from .streams import (normal_draws, plume_truth, observations, plume_observations, WORKLOADS,
-                      workload)
+                      workload, serving_streams, poisson_requests)
 
 __all__ = [
     "grid_shape", "cell_centres", "grid_size",
     "crosswell_geometry", "crosswell_h", "ray_lengths",
     "normal_draws", "plume_truth", "observations", "plume_observations", "WORKLOADS", "workload",
+    "serving_streams", "poisson_requests",
 ]
