@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--n-c", type=int, default=None)
     ap.add_argument("--assim-steps", type=int, default=None,
                     help="assimilation steps per job (default: the workload's)")
+    ap.add_argument("--riccati", type=int, default=0,
+                    help="gather G = H C_prior only every N steps and carry it between "
+                         "(exact p-space recursion); 0 = every step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="approximate seconds of CPU work for the oracle sample")
@@ -277,7 +280,7 @@ def main():
     pr, keep = F.problem_from_csr(dim, n, rowptr, col, val, np.full(p, w["r_var"]),
                                   theta=w["theta"], ell=w["ell"], gamma=w["gamma"],
                                   prior=w["prior"])
-    op = F.make_options(n_c, a.precision, False, timing=True)
+    op = F.make_options(n_c, a.precision, False, timing=True, riccati=a.riccati)
     info = F.plan(pr, op)
     resident = torch.empty(int(info.resident_bytes), dtype=torch.uint8, device="cuda")
     scratch = torch.empty(int(info.scratch_bytes), dtype=torch.uint8, device="cuda")
@@ -388,7 +391,8 @@ def main():
         "config": {"workload": a.workload, "m": m, "p": p, "dim": dim, "n_c": n_c,
                    "kernel": f"theta*exp(-(r/{w['ell']})^{w['gamma']:g})",
                    "fmm_dtype": a.precision, "step_dtype": "f64",
-                   "assim_steps_per_job": K, "parallelism": "none (1 GPU)"},
+                   "assim_steps_per_job": K, "gather_every": a.riccati or 1,
+                   "parallelism": "none (1 GPU)"},
         "warm_steps_per_s": round(1e3 / float(np.mean(lat_ms)), 2),
         "step_latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
                             "p99": round(float(np.percentile(lat_ms, 99)), 4),

@@ -114,6 +114,15 @@ typedef struct hikf_options {
                                 for small grids and tests)                   */
     int32_t timing;          /* 1: bracket every phase with HIP events on the
                                 launch stream; hikf_query reports the sums    */
+    int32_t riccati;         /* 0: form G = H C_prior and h = H x_hat from the
+                                rows of C every step (a gather over the
+                                nonzeros of H).  N >= 1: do that every N-th
+                                step only and carry G, h in between with the
+                                exact p-space recursion
+                                  G <- G S^{-1} R + H C_Q,  h <- h + G S^{-1} nu
+                                (from C_post = K R; O(p^3) instead of a read
+                                of nnz(H) rows of C).  Import_state forces the
+                                next step to gather.                          */
     int32_t graph;           /* 1: capture the step's kernels once, at init,
                                 into a HIP graph and replay it per step (y is
                                 first copied into the resident region).

@@ -35,6 +35,9 @@ Layout make_layout(const Geometry &g) {
     L.minpiv = take(8);
     L.steps = take(8);
     L.negvar = take(8);
+    L.GQ = take(p * p * 8);
+    L.Gn = take(p * p * 8);
+    L.hpart = take(size_t(g.pp / 32) * p * 8);
     L.ybuf = take(p * 8);
     L.psA = take(size_t(g.pp) * g.pp * 8);
     L.pivs = take(size_t(g.pp / 32) * 8);
@@ -286,6 +289,8 @@ hikf_status hikf_init(const hikf_problem *prob, const hikf_options *opt, void *r
     HIKF_TRY(hikf::launch_validate(g, lay, res, prob->x0_dev, s), "validate");
     HIKF_TRY(hikf::launch_fmm(g, lay, res, scr, s, &f->timing), "fmm");
     HIKF_TRY(hikf::launch_init_state(g, lay, res, prob->x0_dev, s), "init state");
+    f->riccati = opt->riccati > 0 ? opt->riccati : 0;
+    if (f->riccati) HIKF_TRY(hikf::launch_gq(f->g, lay, res, s), "H C_Q");
     if (opt->graph && !opt->timing) {
         // capture on a private stream (the caller's may be the null stream,
         // which cannot be captured); the graph reads y from the resident copy
@@ -295,15 +300,30 @@ hikf_status hikf_init(const hikf_problem *prob, const hikf_options *opt, void *r
         if (ce == hipSuccess) {
             hipError_t le = hikf::launch_step(f->g, lay, res,
                                               reinterpret_cast<const double *>(res + lay.ybuf), cs,
-                                              nullptr);
+                                              nullptr, true, f->riccati > 0);
             ce = hipStreamEndCapture(cs, &f->graph);
             if (ce == hipSuccess) ce = le;
         }
         if (ce == hipSuccess) ce = hipGraphInstantiate(&f->gexec, f->graph, nullptr, nullptr, 0);
+        if (ce == hipSuccess && f->riccati) {
+            ce = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (ce == hipSuccess) {
+                hipError_t le = hikf::launch_step(f->g, lay, res,
+                                                  reinterpret_cast<const double *>(res + lay.ybuf),
+                                                  cs, nullptr, false, true);
+                ce = hipStreamEndCapture(cs, &f->graph_ng);
+                if (ce == hipSuccess) ce = le;
+            }
+            if (ce == hipSuccess)
+                ce = hipGraphInstantiate(&f->gexec_ng, f->graph_ng, nullptr, nullptr, 0);
+        }
         (void)hipStreamDestroy(cs);
         if (ce != hipSuccess) {
+            if (f->gexec) (void)hipGraphExecDestroy(f->gexec);
             if (f->graph) (void)hipGraphDestroy(f->graph);
-            f->graph = nullptr;
+            if (f->graph_ng) (void)hipGraphDestroy(f->graph_ng);
+            f->gexec = nullptr;
+            f->graph = f->graph_ng = nullptr;
         }
         HIKF_TRY(ce, "step graph");
     }
@@ -318,12 +338,15 @@ hikf_status hikf_step(hikf_filter *f, const double *y_dev, double *x_out_dev, do
     hipStream_t s = static_cast<hipStream_t>(stream);
     f->last_stream = s;
     hipError_t e;
+    const bool gather = !f->riccati || f->force_gather || f->issued % f->riccati == 0;
+    f->force_gather = false;
+    ++f->issued;
     if (f->gexec) {
         e = hipMemcpyAsync(f->res + f->lay.ybuf, y_dev, size_t(f->g.p) * 8,
                            hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess) e = hipGraphLaunch(f->gexec, s);
+        if (e == hipSuccess) e = hipGraphLaunch(gather ? f->gexec : f->gexec_ng, s);
     } else {
-        e = hikf::launch_step(f->g, f->lay, f->res, y_dev, s, &f->timing);
+        e = hikf::launch_step(f->g, f->lay, f->res, y_dev, s, &f->timing, gather, f->riccati > 0);
     }
     if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "step", e);
     const size_t mb = size_t(f->g.m) * 8;
@@ -412,6 +435,7 @@ hikf_status hikf_import_state(hikf_filter *f, const double *x_dev, const double 
     if (e == hipSuccess && c_dev)
         e = hipMemcpyAsync(f->res + f->lay.C, c_dev, mb * f->g.p, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "import", e);
+    f->force_gather = true;                      // the carried G, h no longer match
     return HIKF_OK;
 }
 
@@ -428,6 +452,8 @@ void hikf_destroy(hikf_filter *f) {
     if (!f) return;
     if (f->gexec) (void)hipGraphExecDestroy(f->gexec);
     if (f->graph) (void)hipGraphDestroy(f->graph);
+    if (f->gexec_ng) (void)hipGraphExecDestroy(f->gexec_ng);
+    if (f->graph_ng) (void)hipGraphDestroy(f->graph_ng);
     f->timing.destroy();
     delete f;
 }

@@ -85,6 +85,7 @@ struct Layout {
     // resident
     size_t C, CQ, xhat, var, sinv, xbuf, G, hvec, nu, partial;
     size_t rowptr, col, val, rdiag, status, minpiv, steps, negvar, ybuf;
+    size_t GQ, Gn, hpart;                     // H C_Q, the next G, shares of the next h
     size_t psA, pivs;                         // p-space ping-pong buffer (with xbuf), pivots
     size_t resident_bytes;
     // scratch
@@ -128,10 +129,15 @@ hipError_t launch_validate(const Geometry &g, const Layout &lay, char *res,
                            const double *x0, hipStream_t s);
 hipError_t launch_init_state(const Geometry &g, const Layout &lay, char *res,
                              const double *x0, hipStream_t s);
+// gather: form G, h from the rows of C (else use the carried ones);
+// advance: afterwards carry G, h to the next step by the p-space recursion
 hipError_t launch_step(const Geometry &g, const Layout &lay, char *res,
-                       const double *y, hipStream_t s, Timing *t);
+                       const double *y, hipStream_t s, Timing *t, bool gather = true,
+                       bool advance = false);
 hipError_t launch_pspace(const Geometry &g, const Layout &lay, char *res,
                          const double *y, hipStream_t s);
+hipError_t launch_advance(const Geometry &g, const Layout &lay, char *res, hipStream_t s);
+hipError_t launch_gq(const Geometry &g, const Layout &lay, char *res, hipStream_t s);
 hipError_t launch_widen_cq(const Geometry &g, const Layout &lay, char *res,
                            double *out, hipStream_t s);
 
@@ -148,5 +154,10 @@ struct hikf_filter {
     hikf::Timing timing;
     hipGraph_t graph = nullptr;      // step captured at init (hikf_options.graph)
     hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph_ng = nullptr;   // the same without the gather (riccati mode)
+    hipGraphExec_t gexec_ng = nullptr;
+    int riccati = 0;                 // gather period of the p-space recursion, 0 = off
+    int64_t issued = 0;              // steps issued since init or the last import
+    bool force_gather = true;
     char err[256] = {0};
 };

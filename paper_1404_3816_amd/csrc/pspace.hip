@@ -236,6 +236,66 @@ __global__ void __launch_bounds__(NT) k_ps_sweep(PsArgs a, int k) {
     }
 }
 
+// ---------------------------------------------------------------- recursion
+// Carry G = H C_prior and h = H x_hat to the next step without touching C:
+// C_post = K R = C_prior S^{-1} R gives H C_post = G S^{-1} R, so the next
+// prior G is G S^{-1} R + H C_Q, and H x_hat_post = h + G S^{-1} nu.
+// k_ps_advance: one workgroup per 32 x 32 block (i, j) of G S^{-1}; it writes
+// that block of Gn = G S^{-1} R + G_Q and the block's share of (G S^{-1} nu)_i
+// to hpart[j][i].  k_ps_finish then copies Gn to G and adds the shares to h
+// in a fixed order (no atomics: the result is deterministic).
+__device__ void blk_load_p(double *s, const double *A, int p, int bi, int bj) {
+    for (int idx = threadIdx.x; idx < BS * BS; idx += NT) {
+        const int r = idx / BS, c = idx % BS, i = bi * BS + r, j = bj * BS + c;
+        s[r * BP + c] = (i < p && j < p) ? A[int64_t(i) * p + j] : 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(NT)
+k_ps_advance(int p, int nbk, const double *G, const double *Sinv, const double *rdiag,
+             const double *GQ, const double *nu, double *Gn, double *hpart, const int *status) {
+    __shared__ double sG[BS * BP];
+    __shared__ double sS[BS * BP];
+    if (status[kStStep] != HIKF_OK) return;          // failed step: keep G, h
+    const int bi = blockIdx.x / nbk, bj = blockIdx.x % nbk, t = threadIdx.x;
+    d4 acc = d4{0, 0, 0, 0};
+    for (int kb = 0; kb < nbk; ++kb) {
+        __syncthreads();
+        blk_load_p(sG, G, p, bi, kb);
+        blk_load_p(sS, Sinv, p, kb, bj);
+        __syncthreads();
+        acc = tile_mma<false, false>(acc, sG, sS, 1.0);
+    }
+    __syncthreads();
+    tile_write(sG, acc);                              // (G S^{-1}) block
+    __syncthreads();
+    for (int idx = t; idx < BS * BS; idx += NT) {
+        const int r = idx / BS, c = idx % BS, i = bi * BS + r, j = bj * BS + c;
+        if (i < p && j < p)
+            Gn[int64_t(i) * p + j] = sG[r * BP + c] * rdiag[j] + GQ[int64_t(i) * p + j];
+    }
+    if (t < BS && bi * BS + t < p) {
+        double d = 0.0;
+        for (int c = 0; c < BS && bj * BS + c < p; ++c) d += sG[t * BP + c] * nu[bj * BS + c];
+        hpart[int64_t(bj) * p + bi * BS + t] = d;
+    }
+}
+
+__global__ void k_ps_finish(int p, int nbk, const double *Gn, const double *hpart, double *G,
+                            double *h, const int *status) {
+    if (status[kStStep] != HIKF_OK) return;
+    const int64_t n = int64_t(p) * p;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        G[i] = Gn[i];
+        if (i < p) {
+            double d = 0.0;
+            for (int j = 0; j < nbk; ++j) d += hpart[int64_t(j) * p + i];
+            h[i] += d;
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_pspace(const Geometry &g, const Layout &lay, char *res, const double *y,
@@ -258,6 +318,28 @@ hipError_t launch_pspace(const Geometry &g, const Layout &lay, char *res, const 
     a.steps = reinterpret_cast<long long *>(res + lay.steps);
     for (int k = 0; k < a.nbk; ++k)
         hipLaunchKernelGGL(k_ps_sweep, dim3(a.nbk * a.nbk), dim3(NT), 0, s, a, k);
+    return hipGetLastError();
+}
+
+}  // namespace hikf
+
+namespace hikf {
+
+hipError_t launch_advance(const Geometry &g, const Layout &lay, char *res, hipStream_t s) {
+    const int nbk = g.pp / BS;
+    const int *status = reinterpret_cast<const int *>(res + lay.status);
+    double *Gn = reinterpret_cast<double *>(res + lay.Gn);
+    double *hpart = reinterpret_cast<double *>(res + lay.hpart);
+    hipLaunchKernelGGL(k_ps_advance, dim3(nbk * nbk), dim3(NT), 0, s, g.p, nbk,
+                       reinterpret_cast<const double *>(res + lay.G),
+                       reinterpret_cast<const double *>(res + lay.sinv),
+                       reinterpret_cast<const double *>(res + lay.rdiag),
+                       reinterpret_cast<const double *>(res + lay.GQ),
+                       reinterpret_cast<const double *>(res + lay.nu), Gn, hpart, status);
+    const int64_t n = int64_t(g.p) * g.p;
+    hipLaunchKernelGGL(k_ps_finish, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, g.p, nbk,
+                       Gn, hpart, reinterpret_cast<double *>(res + lay.G),
+                       reinterpret_cast<double *>(res + lay.hvec), status);
     return hipGetLastError();
 }
 

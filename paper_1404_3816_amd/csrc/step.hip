@@ -100,6 +100,7 @@ __global__ void __launch_bounds__(512)
 k_gather(int p, int cpr, int64_t m, int64_t nnz, const int64_t *rowptr, const int32_t *col,
          const double *val, const double *C, const TQ *CQ, const double *xhat,
          double *partial, const int *status) {
+    // C == nullptr: sums over C_Q alone (H C_Q, once at init)
     typedef double dv2 __attribute__((ext_vector_type(2)));
     typedef TQ qv2 __attribute__((ext_vector_type(2)));
     constexpr int U = 8;
@@ -132,7 +133,7 @@ k_gather(int p, int cpr, int64_t m, int64_t nnz, const int64_t *rowptr, const in
                 const int64_t c = col[e + u];
                 const bool ok = c >= 0 && c < m;
                 const int64_t o = (ok ? c : 0) * p + 2 * t;
-                const dv2 cv = *reinterpret_cast<const dv2 *>(C + o);
+                const dv2 cv = C ? *reinterpret_cast<const dv2 *>(C + o) : dv2{0.0, 0.0};
                 const qv2 qv = *reinterpret_cast<const qv2 *>(CQ + o);
                 x[u] = dv2{cv[0] + (double)qv[0], cv[1] + (double)qv[1]};
                 w[u] = ok ? val[e + u] : 0.0;
@@ -144,7 +145,7 @@ k_gather(int p, int cpr, int64_t m, int64_t nnz, const int64_t *rowptr, const in
             const int64_t c = col[e];
             if (c < 0 || c >= m) continue;
             const int64_t o = c * p + 2 * t;
-            const dv2 cv = *reinterpret_cast<const dv2 *>(C + o);
+            const dv2 cv = C ? *reinterpret_cast<const dv2 *>(C + o) : dv2{0.0, 0.0};
             const qv2 qv = *reinterpret_cast<const qv2 *>(CQ + o);
             acc += val[e] * dv2{cv[0] + (double)qv[0], cv[1] + (double)qv[1]};
         }
@@ -453,8 +454,8 @@ void launch_rowpass(const Geometry &g, const Layout &lay, char *res, hipStream_t
 }
 
 template <typename TQ>
-hipError_t run_step(const Geometry &g, const Layout &lay, char *res, const double *y,
-                    hipStream_t s, Timing *tm) {
+void run_gather(const Geometry &g, const Layout &lay, char *res, bool with_c, double *G,
+                double *h, hipStream_t s, Timing *tm) {
     const int p = g.p;
     tbegin(tm, HIKF_PHASE_GATHER, s);
     const unsigned gthreads = unsigned(((p / 2 + 1) + 63) / 64 * 64);
@@ -462,7 +463,7 @@ hipError_t run_step(const Geometry &g, const Layout &lay, char *res, const doubl
                        reinterpret_cast<const int64_t *>(res + lay.rowptr),
                        reinterpret_cast<const int32_t *>(res + lay.col),
                        reinterpret_cast<const double *>(res + lay.val),
-                       reinterpret_cast<const double *>(res + lay.C),
+                       with_c ? reinterpret_cast<const double *>(res + lay.C) : nullptr,
                        reinterpret_cast<const TQ *>(res + lay.CQ),
                        reinterpret_cast<const double *>(res + lay.xhat),
                        reinterpret_cast<double *>(res + lay.partial),
@@ -470,14 +471,21 @@ hipError_t run_step(const Geometry &g, const Layout &lay, char *res, const doubl
     tend(tm, HIKF_PHASE_GATHER, s);
     tbegin(tm, HIKF_PHASE_REDUCE, s);
     hipLaunchKernelGGL(k_reduce_g, dim3(p), dim3(256), 0, s, p, g.cpr,
-                       reinterpret_cast<const double *>(res + lay.partial),
-                       reinterpret_cast<double *>(res + lay.G),
-                       reinterpret_cast<double *>(res + lay.hvec),
+                       reinterpret_cast<const double *>(res + lay.partial), G, h,
                        reinterpret_cast<const int *>(res + lay.status));
     tend(tm, HIKF_PHASE_REDUCE, s);
+}
+
+template <typename TQ>
+hipError_t run_step(const Geometry &g, const Layout &lay, char *res, const double *y,
+                    hipStream_t s, Timing *tm, bool gather, bool advance) {
+    if (gather)
+        run_gather<TQ>(g, lay, res, true, reinterpret_cast<double *>(res + lay.G),
+                       reinterpret_cast<double *>(res + lay.hvec), s, tm);
     tbegin(tm, HIKF_PHASE_PSPACE, s);
     {
         hipError_t e = launch_pspace(g, lay, res, y, s);
+        if (e == hipSuccess && advance) e = launch_advance(g, lay, res, s);
         if (e != hipSuccess) return e;
     }
     tend(tm, HIKF_PHASE_PSPACE, s);
@@ -536,9 +544,18 @@ hipError_t launch_init_state(const Geometry &g, const Layout &lay, char *res, co
 }
 
 hipError_t launch_step(const Geometry &g, const Layout &lay, char *res, const double *y,
-                       hipStream_t s, Timing *t) {
-    if (g.fmm_prec == HIKF_FMM_F64) return run_step<double>(g, lay, res, y, s, t);
-    return run_step<float>(g, lay, res, y, s, t);
+                       hipStream_t s, Timing *t, bool gather, bool advance) {
+    if (g.fmm_prec == HIKF_FMM_F64) return run_step<double>(g, lay, res, y, s, t, gather, advance);
+    return run_step<float>(g, lay, res, y, s, t, gather, advance);
+}
+
+// G_Q = H C_Q (p x p) for the p-space recursion; nu serves as a throw-away h
+hipError_t launch_gq(const Geometry &g, const Layout &lay, char *res, hipStream_t s) {
+    double *GQ = reinterpret_cast<double *>(res + lay.GQ);
+    double *dummy = reinterpret_cast<double *>(res + lay.nu);
+    if (g.fmm_prec == HIKF_FMM_F64) run_gather<double>(g, lay, res, false, GQ, dummy, s, nullptr);
+    else run_gather<float>(g, lay, res, false, GQ, dummy, s, nullptr);
+    return hipGetLastError();
 }
 
 hipError_t launch_widen_cq(const Geometry &g, const Layout &lay, char *res, double *out,

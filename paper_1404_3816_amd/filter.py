@@ -51,13 +51,14 @@ def problem_from_csr(dim, n, rowptr, col, val, r_diag, family="powexp", theta=1.
     return pr, (t_rowptr, t_col, t_val, t_r, t_x0)
 
 
-def make_options(n_c=4, precision="f32", direct=False, timing=False, graph=False):
+def make_options(n_c=4, precision="f32", direct=False, timing=False, graph=False, riccati=0):
     op = H.hikf_options()
     op.n_c = int(n_c)
     op.fmm_precision = PRECISIONS[precision]
     op.direct = 1 if direct else 0
     op.timing = 1 if timing else 0
     op.graph = 1 if graph else 0
+    op.riccati = int(riccati)
     return op
 
 

@@ -19,11 +19,12 @@ def _gpu():
     from paper_1404_3816_amd import hikf  # noqa: F401  (fails loudly without libhikf.so)
 
 
-def _filter(case, graph=False, n_c=4, precision="f32"):
+def _filter(case, graph=False, n_c=4, precision="f32", riccati=0):
     from paper_1404_3816_amd import filter as F
     pr, keep = F.problem_from_csr(case.dim, case.n, case.rowptr, case.col, case.val,
                                   case.r_diag, **case.kparams())
-    return F.HikfFilter(pr, F.make_options(n_c, precision, False, graph=graph), keep)
+    return F.HikfFilter(pr, F.make_options(n_c, precision, False, graph=graph, riccati=riccati),
+                        keep)
 
 
 @pytest.mark.parametrize("dim,n,p", [(2, 64, 32), (3, 16, 64)])
@@ -114,3 +115,57 @@ def test_negative_variance_counter():
     f.close()
     assert int((v2 < 0).sum()) == case.m
     assert st.negative_variances == case.m
+
+
+def _trajectory(f, y, m, steps):
+    import torch
+    x = torch.empty(m, dtype=torch.float64, device="cuda")
+    v = torch.empty_like(x)
+    xs, vs = [], []
+    for k in range(steps):
+        f.step(y[k], x, v)
+        xs.append(x.cpu().numpy().copy())
+        vs.append(v.cpu().numpy().copy())
+    return np.array(xs), np.array(vs)
+
+
+@pytest.mark.parametrize("riccati,graph", [(1, False), (4, False), (1000, False), (4, True)])
+def test_riccati_recursion_matches_gather(riccati, graph):
+    # G <- G S^-1 R + H C_Q and h <- h + G S^-1 nu are exact identities of the
+    # update; carried over many steps they drift only by rounding
+    import torch
+    from helpers import max_step_rel
+    case = Case(2, 64, 32, ell=0.2, steps=12)
+    y = torch.as_tensor(case.ys, device="cuda")
+    fa, fb = _filter(case, precision="f64"), _filter(case, precision="f64", riccati=riccati,
+                                                     graph=graph)
+    xa, va = _trajectory(fa, y, case.m, case.steps)
+    xb, vb = _trajectory(fb, y, case.m, case.steps)
+    sa, sb = fa.query(), fb.query()
+    fa.close()
+    fb.close()
+    assert sb.last_status == 0 and sb.steps_applied == case.steps
+    assert max_step_rel(xb, xa) < 1e-9
+    assert max_step_rel(vb, va) < 1e-10
+
+
+def test_riccati_import_forces_a_gather():
+    # after import_state the carried G, h would describe the old state: the
+    # next step must form them from C again
+    import torch
+    case = Case(2, 32, 16, ell=0.3, steps=4)
+    y = torch.as_tensor(case.ys, device="cuda")
+    fa, fb = _filter(case, precision="f64"), _filter(case, precision="f64", riccati=1000)
+    for k in range(2):
+        fa.step(y[k])
+    fb.step(y[0])
+    x, v, c = fa.export_state()
+    fb.import_state(x, v, c)                 # fb jumps to fa's state after 2 steps
+    fa.step(y[2])
+    fb.step(y[2])
+    xa, va, ca = fa.export_state()
+    xb, vb, cb = fb.export_state()
+    fa.close()
+    fb.close()
+    assert float(((xb - xa).norm() / xa.norm())) < 1e-12
+    assert float(((vb - va).norm() / va.norm())) < 1e-12
