@@ -1,0 +1,80 @@
+"""GPU parity at the benchmark's full size (1024 x 1024 cells, p = 256,
+Gaussian kernel ell = 0.05, n_c = 5, FP32 FMM, FP64 step), in the launch
+configuration bench.py times (phase timing on, eager launches).
+
+At this size the oracle cannot run the whole filter, so the checks use
+outputs it computes one by one:
+* C_Q on 48 seeded rows by the defining sums over the nonzeros of H (exact);
+* x_hat and the variance after the first step on the same rows, by the
+  cross-covariance filter run on the rows the rays cross plus the sampled
+  ones (rows are independent given G = H C_prior), with C_Q from the exact
+  FFT route.
+The GPU differs from these exact values by the H^2 error of n_c = 5: at
+256 x 256 with the same kernel and p the oracle's own bbFMM is 7e-5 off in
+C_Q, 8e-4 in x_hat and 4e-5 in the variance after one step; the tolerances
+below leave a margin of about 10x over that.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from helpers import rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fullsize():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1404_3816_amd import filter as F
+    w = synth.workload("crosswell-1024x1024-p256")
+    dim, n, p, m = w["dim"], w["n"], w["p"], w["m"]
+    rowptr, col, val = synth.crosswell_h(dim, n, p, planes=8)
+    ys = synth.plume_observations(dim, n, rowptr, col, val, 1, w["r_var"], w["seed"] + 1)
+    pr, keep = F.problem_from_csr(dim, n, rowptr, col, val, np.full(p, w["r_var"]),
+                                  theta=w["theta"], ell=w["ell"], gamma=w["gamma"],
+                                  prior=w["prior"])
+    f = F.HikfFilter(pr, F.make_options(w["n_c"], "f32", False, timing=True), keep)
+    rows = np.sort(np.random.default_rng(7).choice(m, 48, replace=False))
+    cq = f.export_cq()[torch.as_tensor(rows, device="cuda")].cpu().numpy()
+    x = torch.empty(m, dtype=torch.float64, device="cuda")
+    v = torch.empty_like(x)
+    f.step(torch.as_tensor(ys[0], device="cuda"), x, v)
+    st = f.query()
+    out = dict(w=w, rowptr=rowptr, col=col, val=val, ys=ys, rows=rows, cq=cq,
+               x=x.cpu().numpy()[rows], v=v.cpu().numpy()[rows], stats=st)
+    f.close()
+    return out
+
+
+def test_fullsize_cq_sampled_rows_match_direct_sums(fullsize):
+    from oracle import cq_exact
+    d, w = fullsize, fullsize["w"]
+    ref = cq_exact.cq_rows(w["dim"], w["n"], d["rowptr"], d["col"], d["val"], d["rows"],
+                           "powexp", w["theta"], w["ell"], w["gamma"])
+    err = rel(d["cq"], ref)
+    print(f"full-size C_Q on 48 rows vs direct sums: {err:.3e}")
+    assert err < 1e-3
+
+
+def test_fullsize_first_step_sampled_rows_match_oracle(fullsize):
+    import scipy.sparse as sp
+    from oracle import cq_exact, kf_crosscov
+    d, w = fullsize, fullsize["w"]
+    n, p, m = w["n"], w["p"], w["m"]
+    assert d["stats"].last_status == 0 and d["stats"].steps_applied == 1
+    H = sp.csr_matrix((d["val"], d["col"], d["rowptr"]), shape=(p, m))
+    cq = cq_exact.cq_fft(w["dim"], n, H.T.toarray(), "powexp", w["theta"], w["ell"], w["gamma"])
+    sub = np.union1d(np.unique(d["col"]), d["rows"])
+    CQs = cq[sub]
+    del cq
+    xs, vs = kf_crosscov.crosscov_kf(CQs, H[:, sub], w["r_var"] * np.eye(p), np.zeros(len(sub)),
+                                     CQs, np.full(len(sub), w["theta"]), w["theta"], d["ys"])
+    pos = np.searchsorted(sub, d["rows"])
+    ex, ev = rel(d["x"], xs[0][pos]), rel(d["v"], vs[0][pos])
+    print(f"full-size step 1 on 48 rows: x {ex:.3e}, var {ev:.3e}")
+    assert np.all(np.isfinite(d["x"])) and np.all(np.isfinite(d["v"]))
+    assert ex < 1e-2 and ev < 1e-3
