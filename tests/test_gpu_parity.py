@@ -312,3 +312,54 @@ def test_h_zero_invariant():
     assert np.all(x == 0.0)
     np.testing.assert_allclose(v, 6.0, rtol=1e-15)
     assert np.all(c == 0.0)
+
+
+# ------------------------------------------------------------------ edge cases
+@pytest.mark.parametrize("dim,n", [(2, 1), (2, 3), (2, 5), (3, 1), (3, 2), (3, 3)])
+@pytest.mark.parametrize("direct", [True, False])
+def test_tiny_grids_match_dense_kf(dim, n, direct):
+    # grids smaller than one leaf: a depth-0 tree of padding plus a few cells
+    case = Case(dim, n, 16, ell=0.3, steps=3, planes=2)
+    _, xs, vs, stats = case.gpu_run(precision="f64", direct=direct)
+    xa, va = case.tier_a()
+    assert stats.last_status == 0 and stats.steps_applied == 3
+    assert max_step_rel(xs, xa) < 1e-10
+    # On one or a few cells every ray sees the same cells, H Q H^T is nearly
+    # rank one and cond(S) ~ |H|^2 / R ~ 1e5; the posterior variance is then a
+    # small difference of two O(var_prior) terms, so its error is relative to
+    # var_prior (prior variance <= var_post + 2 K(0)), not to itself.
+    assert np.abs(vs - va).max() < 1e-9 * (va.max() + 2.0)
+
+
+def test_empty_h_keeps_mean_and_adds_q():
+    # no nonzeros at all: C_Q = 0, G = 0, S = R; the mean stays and every
+    # variance grows by K(0) per step
+    import torch
+    from paper_1404_3816_amd import filter as F
+    p, n = 32, 64
+    rowptr = np.zeros(p + 1, np.int64)
+    pr, keep = F.problem_from_csr(2, n, rowptr, np.zeros(0, np.int32), np.zeros(0),
+                                  np.full(p, 1e-4), ell=0.2)
+    f = F.HikfFilter(pr, F.make_options(4, "f32", False), keep)
+    y = torch.as_tensor(np.random.default_rng(3).standard_normal(p), device="cuda")
+    for k in range(4):
+        f.step(y)
+    x, v, c = [t.cpu().numpy() for t in f.export_state()]
+    cq = f.export_cq().cpu().numpy()
+    st = f.query()
+    f.close()
+    assert st.last_status == 0 and st.steps_applied == 4
+    assert np.all(cq == 0.0) and np.all(c == 0.0) and np.all(x == 0.0)
+    np.testing.assert_allclose(v, 5.0, rtol=1e-15)
+
+
+def test_largest_2d_order_matches_oracle_bbfmm():
+    # n_c = 8 in 2-D (r = 64, the largest r): BF16 k padding is exact, FP32 and
+    # FP64 tiles span the full r
+    case = Case(2, 64, 32, ell=0.2, steps=1)
+    ref = case.cq_bbfmm(8)
+    for prec, tol in (("f64", 1e-12), ("f32", 2e-6), ("bf16x3", 1e-4)):
+        f = case.gpu_filter(n_c=8, precision=prec)
+        cq = f.export_cq().cpu().numpy()
+        f.close()
+        assert rel(cq, ref) < tol, prec
