@@ -123,6 +123,10 @@ typedef struct hikf_options {
                                 (from C_post = K R; O(p^3) instead of a read
                                 of nnz(H) rows of C).  Import_state forces the
                                 next step to gather.                          */
+    int32_t history;         /* steps of history kept for hikf_cov_apply (the
+                                prior cross-covariance and S^{-1} of every
+                                applied step: history * (m p + p^2) doubles
+                                of RESIDENT); 0 = none                        */
     int32_t graph;           /* 1: capture the step's kernels once, at init,
                                 into a HIP graph and replay it per step (y is
                                 first copied into the resident region).
@@ -155,6 +159,7 @@ typedef struct hikf_plan_info {
     int32_t r;               /* Chebyshev nodes per box                      */
     int64_t near_pairs;      /* (target leaf, source leaf) pairs in P2P       */
     int64_t far_pairs;       /* interaction-list pairs over all M2L levels    */
+    size_t query_bytes;      /* scratch needed by hikf_cov_apply              */
 } hikf_plan_info;
 
 typedef struct hikf_stats {
@@ -229,6 +234,23 @@ hikf_status hikf_step(hikf_filter *f, const double *y_dev, double *x_out_dev,
 hikf_status hikf_step_batch(hikf_filter *const *filters, const double *const *y_dev,
                             double *const *x_out_dev, double *const *var_out_dev,
                             int32_t count, void *stream);
+
+/*
+ * Posterior covariance times a vector: out = P_{t|t} v for the current step
+ * t (Sec. 3.1 keeps P only implicitly; Sec. 4 uses variances and
+ * cross-covariances for risk analysis).  With P_{s|s} = P_{s|s-1} -
+ * C_s S_s^{-1} C_s^T and P_{s|s-1} = P_{s-1|s-1} + Q,
+ *   P_t v = P_0 v + t Q v - sum_{s=1..t} C_s (S_s^{-1} (C_s^T v)),
+ * where C_s is the prior cross-covariance and S_s the innovation covariance
+ * of step s, kept in the history (hikf_options.history >= t).  Q v is one
+ * FMM product with the filter's tree and n_c (FP32 for the BF16 modes).
+ * v_dev, out_dev: m doubles in grid order.  scratch: at least
+ * hikf_plan_info.query_bytes, 256-byte aligned.  Synchronises the stream.
+ * Errors: HIKF_E_INVALID (NULL arguments), HIKF_E_UNSUPPORTED (no history,
+ * or more steps applied than it holds), HIKF_E_NOMEM, HIKF_E_DEVICE.
+ */
+hikf_status hikf_cov_apply(hikf_filter *f, const double *v_dev, double *out_dev,
+                           void *scratch, size_t scratch_bytes, void *stream);
 
 /*
  * Synchronise the filter's last stream and read its device status and, if

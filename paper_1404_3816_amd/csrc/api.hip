@@ -38,6 +38,8 @@ Layout make_layout(const Geometry &g) {
     L.GQ = take(p * p * 8);
     L.Gn = take(p * p * 8);
     L.hpart = take(size_t(g.pp / 32) * p * 8);
+    L.histC = take(size_t(g.history) * m * p * 8);
+    L.histS = take(size_t(g.history) * p * p * 8);
     L.ybuf = take(p * 8);
     L.psA = take(size_t(g.pp) * g.pp * 8);
     L.pivs = take(size_t(g.pp / 32) * 8);
@@ -181,6 +183,8 @@ hikf_status build_geometry(const hikf_problem *pr, const hikf_options *op, Geome
     g->far = !g->direct && D >= 2;
     g->fmm_prec = op->fmm_precision;
     g->prior = pr->prior_kind;
+    if (op->history < 0 || op->history > 1000000) return HIKF_E_INVALID;
+    g->history = op->history;
     g->alpha = pr->alpha;
     g->kp.family = pr->kernel_family;
     g->kp.theta = pr->theta;
@@ -190,6 +194,39 @@ hikf_status build_geometry(const hikf_problem *pr, const hikf_options *op, Geome
     int64_t cpr = (per_ray + 63) / 64;
     g->cpr = int(cpr < 1 ? 1 : (cpr > 1024 ? 1024 : cpr));
     return HIKF_OK;
+}
+
+// Covariance queries: Q v runs through the filter's tree with 16 columns
+// (FP32 for the BF16 modes); the scratch holds that FMM's workspace, its
+// m x 16 result, the per-step chunk sums of C_s^T v and the vectors w_s.
+struct QueryPlan {
+    Geometry g;
+    hikf::Layout lay;
+    int nchunk;
+    size_t off_qv, off_part, off_w, bytes;
+};
+
+QueryPlan query_plan(const Geometry &g0) {
+    QueryPlan q;
+    q.g = g0;
+    q.g.p = 16;
+    q.g.pp = 32;
+    q.g.nnz = 0;
+    q.g.history = 0;
+    if (q.g.fmm_prec == HIKF_FMM_BF16X3 || q.g.fmm_prec == HIKF_FMM_BF16) q.g.fmm_prec = HIKF_FMM_F32;
+    q.lay = hikf::make_layout(q.g);
+    const size_t tq = q.g.fmm_prec == HIKF_FMM_F64 ? 8 : 4;
+    int64_t nc = (g0.m + 2047) / 2048;
+    q.nchunk = int(nc < 1 ? 1 : (nc > 256 ? 256 : nc));
+    size_t off = hikf::align256(q.lay.scratch_bytes);
+    q.off_qv = off;
+    off = hikf::align256(off + size_t(g0.m) * 16 * tq);
+    q.off_part = off;
+    off = hikf::align256(off + size_t(g0.history) * q.nchunk * g0.p * 8);
+    q.off_w = off;
+    off = hikf::align256(off + size_t(g0.history) * g0.p * 8);
+    q.bytes = off;
+    return q;
 }
 
 void pair_counts(const Geometry &g, int64_t *near, int64_t *far) {
@@ -230,6 +267,7 @@ hikf_status hikf_plan(const hikf_problem *prob, const hikf_options *opt, hikf_pl
     out->depth = g.depth;
     out->r = g.r;
     pair_counts(g, &out->near_pairs, &out->far_pairs);
+    out->query_bytes = g.history ? query_plan(g).bytes : 0;
     return HIKF_OK;
 }
 
@@ -360,6 +398,29 @@ hikf_status hikf_step(hikf_filter *f, const double *y_dev, double *x_out_dev, do
         if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "copy var", e);
     }
     if (x_out_dev || var_out_dev) hikf::tend(&f->timing, HIKF_PHASE_OUTPUT, s);
+    return HIKF_OK;
+}
+
+hikf_status hikf_cov_apply(hikf_filter *f, const double *v_dev, double *out_dev, void *scratch,
+                           size_t scratch_bytes, void *stream) {
+    if (!f || !v_dev || !out_dev || !scratch) return HIKF_E_INVALID;
+    if (f->g.history == 0) return HIKF_E_UNSUPPORTED;
+    const QueryPlan q = query_plan(f->g);
+    if (scratch_bytes < q.bytes || (reinterpret_cast<uintptr_t>(scratch) & 255)) return HIKF_E_NOMEM;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    f->last_stream = s;
+    long long t = 0;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipMemcpy(&t, f->res + f->lay.steps, 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "query sync", e);
+    if (t > f->g.history) return HIKF_E_UNSUPPORTED;
+    char *scr = static_cast<char *>(scratch);
+    e = hikf::launch_fmm_apply(q.g, q.lay, scr, v_dev, scr + q.off_qv, s);
+    if (e == hipSuccess)
+        e = hikf::launch_cov_tail(f->g, f->lay, f->res, int(t), v_dev, scr + q.off_qv, 16,
+                                  reinterpret_cast<double *>(scr + q.off_part), q.nchunk,
+                                  reinterpret_cast<double *>(scr + q.off_w), out_dev, s);
+    if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "cov apply", e);
     return HIKF_OK;
 }
 

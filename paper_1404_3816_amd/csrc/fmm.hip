@@ -16,6 +16,8 @@
 // (leaf interpolation plus the near-field sum with kernel entries generated
 // on the fly).  Operators are built on the device in FP64 and stored in the
 // pass precision T (float or double).
+#include <algorithm>
+
 #include "hikf_internal.h"
 
 namespace hikf {
@@ -814,23 +816,38 @@ int floor_pow2(int x) {
     return v;
 }
 
+// column 0 of W from a dense m-vector (the other columns stay zero)
+template <typename T>
+__global__ void k_dense_w(int64_t m, int dim, int n, int npad, int p, const double *v, T *W) {
+    for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < m;
+         c += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t x = c % n, y = (c / n) % n, z = dim == 3 ? c / (int64_t(n) * n) : 0;
+        W[(x + int64_t(npad) * (y + int64_t(npad) * z)) * p] = (T)v[c];
+    }
+}
+
+// vdense == nullptr: W = H^T from the CSR arrays in RES, result into C_Q.
+// Otherwise W's first column is vdense and the result goes to out (m x p).
 template <typename T>
 hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, hipStream_t s,
-                   Timing *tm) {
+                   Timing *tm, const double *vdense = nullptr, T *out = nullptr) {
     const int p = g.p, r = g.r, dim = g.dim, D = g.depth;
     const int64_t m = g.m;
     const bool bf16 = g.fmm_prec == HIKF_FMM_BF16X3 || g.fmm_prec == HIKF_FMM_BF16;
     const bool split = g.fmm_prec == HIKF_FMM_BF16X3;
     (void)split;
     T *W = reinterpret_cast<T *>(scr + lay.W);
-    T *CQ = reinterpret_cast<T *>(res + lay.CQ);
-    const int64_t *rowptr = reinterpret_cast<const int64_t *>(res + lay.rowptr);
-    const int32_t *col = reinterpret_cast<const int32_t *>(res + lay.col);
-    const double *val = reinterpret_cast<const double *>(res + lay.val);
+    T *CQ = vdense ? out : reinterpret_cast<T *>(res + lay.CQ);
+    const int64_t *rowptr = res ? reinterpret_cast<const int64_t *>(res + lay.rowptr) : nullptr;
+    const int32_t *col = res ? reinterpret_cast<const int32_t *>(res + lay.col) : nullptr;
+    const double *val = res ? reinterpret_cast<const double *>(res + lay.val) : nullptr;
     tbegin(tm, HIKF_PHASE_INIT, s);
     hipError_t e = hipMemsetAsync(W, 0, size_t(g.mpad) * p * sizeof(T), s);
     if (e != hipSuccess) return e;
-    if (g.nnz > 0) {
+    if (vdense) {
+        hipLaunchKernelGGL(k_dense_w<T>, dim3(unsigned(std::min<int64_t>((m + 255) / 256, 65536))),
+                           dim3(256), 0, s, m, dim, g.n, g.npad, p, vdense, W);
+    } else if (g.nnz > 0) {
         int64_t blocks = (g.nnz + kBlock - 1) / kBlock;
         hipLaunchKernelGGL(k_scatter_w<T>, dim3(unsigned(blocks)), dim3(kBlock), 0, s,
                            g.nnz, p, m, dim, g.n, g.npad, rowptr, col, val, W);
@@ -994,6 +1011,13 @@ hipError_t launch_fmm(const Geometry &g, const Layout &lay, char *res, char *scr
                       Timing *t) {
     if (g.fmm_prec == HIKF_FMM_F64) return run_fmm<double>(g, lay, res, scr, s, t);
     return run_fmm<float>(g, lay, res, scr, s, t);
+}
+
+hipError_t launch_fmm_apply(const Geometry &g, const Layout &lay, char *scr, const double *v,
+                            void *out, hipStream_t s) {
+    if (g.fmm_prec == HIKF_FMM_F64)
+        return run_fmm<double>(g, lay, nullptr, scr, s, nullptr, v, static_cast<double *>(out));
+    return run_fmm<float>(g, lay, nullptr, scr, s, nullptr, v, static_cast<float *>(out));
 }
 
 }  // namespace hikf

@@ -70,6 +70,7 @@ struct Geometry {
     bool far = false;             // far field present (depth >= 2 and not direct)
     int fmm_prec = HIKF_FMM_F32;
     int prior = HIKF_PRIOR_KERNEL;
+    int history = 0;              // steps kept for covariance queries
     double alpha = 0.0;
     KernelParams kp{};
     int64_t boxes(int level) const {
@@ -86,6 +87,7 @@ struct Layout {
     size_t C, CQ, xhat, var, sinv, xbuf, G, hvec, nu, partial;
     size_t rowptr, col, val, rdiag, status, minpiv, steps, negvar, ybuf;
     size_t GQ, Gn, hpart;                     // H C_Q, the next G, shares of the next h
+    size_t histC, histS;                      // per-step C_prior and S^{-1} (history)
     size_t psA, pivs;                         // p-space ping-pong buffer (with xbuf), pivots
     size_t resident_bytes;
     // scratch
@@ -140,6 +142,13 @@ hipError_t launch_advance(const Geometry &g, const Layout &lay, char *res, hipSt
 hipError_t launch_gq(const Geometry &g, const Layout &lay, char *res, hipStream_t s);
 hipError_t launch_widen_cq(const Geometry &g, const Layout &lay, char *res,
                            double *out, hipStream_t s);
+// Q v into column 0 of out (m x g.p in the FMM precision) with the tree of g
+hipError_t launch_fmm_apply(const Geometry &g, const Layout &lay, char *scr, const double *v,
+                            void *out, hipStream_t s);
+// out = P_0 v + t Q v - sum_{s<t} C_s S_s^{-1} C_s^T v from the history
+hipError_t launch_cov_tail(const Geometry &g, const Layout &lay, char *res, int t,
+                           const double *v, const void *qv, int qv_ld, double *part,
+                           int nchunk, double *w, double *out, hipStream_t s);
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 

@@ -21,6 +21,13 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+unsigned grid_for(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    if (b > 65536) b = 65536;
+    if (b < 1) b = 1;
+    return unsigned(b);
+}
+
 // ---------------------------------------------------------------- init
 __global__ void k_validate(int p, int64_t nnz, int64_t m, const int64_t *rowptr,
                            const int32_t *col, const double *val, const double *rdiag,
@@ -165,6 +172,81 @@ k_reduce_g(int p, int cpr, const double *partial, double *G, double *hvec, const
         if (b < p) G[int64_t(a) * p + b] = s;
         else hvec[a] = s;
     }
+}
+
+// ---------------------------------------------------------------- history
+// Covariance queries need every applied step's prior cross-covariance C_s
+// and S_s^{-1}.  The slot of a step is the number of steps applied before
+// it (read on the device, so a rejected step is overwritten by the next).
+template <typename TQ>
+__global__ void k_hist_c(int64_t mp, int history, const long long *steps, const double *C,
+                         const TQ *CQ, double *histC) {
+    const long long s = steps[0];
+    if (s >= history) return;
+    double *dst = histC + s * mp;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < mp;
+         i += int64_t(gridDim.x) * blockDim.x)
+        dst[i] = C[i] + (double)CQ[i];
+}
+
+__global__ void k_hist_s(int64_t pp, int history, const long long *steps, const int *status,
+                         const double *Sinv, double *histS) {
+    if (status[kStStep] != HIKF_OK) return;
+    const long long s = steps[0] - 1;
+    if (s < 0 || s >= history) return;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < pp;
+         i += int64_t(gridDim.x) * blockDim.x)
+        histS[s * pp + i] = Sinv[i];
+}
+
+// ---------------------------------------------------------------- queries
+// part[s][ch][c] = sum over the rows of chunk ch of C_s[i][c] v[i]
+__global__ void __launch_bounds__(256)
+k_cov_u(int p, int64_t m, int nchunk, const double *histC, const double *v, double *part) {
+    const int s = blockIdx.x, ch = blockIdx.y;
+    const int64_t r0 = m * ch / nchunk, r1 = m * (ch + 1) / nchunk;
+    const double *Cs = histC + int64_t(s) * m * p;
+    for (int c = threadIdx.x; c < p; c += blockDim.x) {
+        double acc = 0.0;
+        for (int64_t i = r0; i < r1; ++i) acc += Cs[i * p + c] * v[i];
+        part[(int64_t(s) * nchunk + ch) * p + c] = acc;
+    }
+}
+
+// w_s = S_s^{-1} u_s with u_s the chunk sums in a fixed order
+__global__ void __launch_bounds__(256)
+k_cov_w(int p, int nchunk, const double *part, const double *histS, double *w) {
+    __shared__ double su[kMaxP];
+    const int s = blockIdx.x;
+    for (int c = threadIdx.x; c < p; c += blockDim.x) {
+        double u = 0.0;
+        for (int ch = 0; ch < nchunk; ++ch) u += part[(int64_t(s) * nchunk + ch) * p + c];
+        su[c] = u;
+    }
+    __syncthreads();
+    const double *Ss = histS + int64_t(s) * p * p;
+    for (int c = threadIdx.x; c < p; c += blockDim.x) {
+        double acc = 0.0;
+        for (int k = 0; k < p; ++k) acc += Ss[int64_t(c) * p + k] * su[k];
+        w[int64_t(s) * p + c] = acc;
+    }
+}
+
+// out_i = a v_i + b (Q v)_i - sum_s C_s[i][.] w_s; one wave per row
+template <typename TQ>
+__global__ void __launch_bounds__(256)
+k_cov_out(int64_t m, int p, int t, double a, double b, const double *v, const TQ *qv, int qv_ld,
+          const double *histC, const double *w, double *out) {
+    const int64_t i = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= m) return;
+    double d = 0.0;
+    for (int s = 0; s < t; ++s) {
+        const double *row = histC + (int64_t(s) * m + i) * p;
+        for (int c = lane; c < p; c += 64) d += row[c] * w[int64_t(s) * p + c];
+    }
+    for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
+    if (lane == 0) out[i] = a * v[i] + b * (double)qv[i * qv_ld] - d;
 }
 
 // ---------------------------------------------------------------- 3. p-space
@@ -482,6 +564,12 @@ hipError_t run_step(const Geometry &g, const Layout &lay, char *res, const doubl
     if (gather)
         run_gather<TQ>(g, lay, res, true, reinterpret_cast<double *>(res + lay.G),
                        reinterpret_cast<double *>(res + lay.hvec), s, tm);
+    const long long *steps = reinterpret_cast<const long long *>(res + lay.steps);
+    if (g.history)
+        hipLaunchKernelGGL(k_hist_c<TQ>, dim3(grid_for(g.m * g.p)), dim3(256), 0, s, g.m * g.p,
+                           g.history, steps, reinterpret_cast<const double *>(res + lay.C),
+                           reinterpret_cast<const TQ *>(res + lay.CQ),
+                           reinterpret_cast<double *>(res + lay.histC));
     tbegin(tm, HIKF_PHASE_PSPACE, s);
     {
         hipError_t e = launch_pspace(g, lay, res, y, s);
@@ -489,20 +577,43 @@ hipError_t run_step(const Geometry &g, const Layout &lay, char *res, const doubl
         if (e != hipSuccess) return e;
     }
     tend(tm, HIKF_PHASE_PSPACE, s);
+    if (g.history)
+        hipLaunchKernelGGL(k_hist_s, dim3(grid_for(int64_t(g.p) * g.p)), dim3(256), 0, s,
+                           int64_t(g.p) * g.p, g.history, steps,
+                           reinterpret_cast<const int *>(res + lay.status),
+                           reinterpret_cast<const double *>(res + lay.sinv),
+                           reinterpret_cast<double *>(res + lay.histS));
     tbegin(tm, HIKF_PHASE_ROWPASS, s);
     launch_rowpass<TQ>(g, lay, res, s);
     tend(tm, HIKF_PHASE_ROWPASS, s);
     return hipGetLastError();
 }
 
-unsigned grid_for(int64_t n) {
-    int64_t b = (n + 255) / 256;
-    if (b > 65536) b = 65536;
-    if (b < 1) b = 1;
-    return unsigned(b);
-}
-
 }  // namespace
+
+hipError_t launch_cov_tail(const Geometry &g, const Layout &lay, char *res, int t,
+                           const double *v, const void *qv, int qv_ld, double *part,
+                           int nchunk, double *w, double *out, hipStream_t s) {
+    const double *histC = reinterpret_cast<const double *>(res + lay.histC);
+    if (t > 0) {
+        hipLaunchKernelGGL(k_cov_u, dim3(t, nchunk), dim3(256), 0, s, g.p, g.m, nchunk, histC, v,
+                           part);
+        hipLaunchKernelGGL(k_cov_w, dim3(t), dim3(256), 0, s, g.p, nchunk, part,
+                           reinterpret_cast<const double *>(res + lay.histS), w);
+    }
+    // P_0 v: Q v, alpha v or 0
+    double a = 0.0, b = double(t);
+    if (g.prior == HIKF_PRIOR_KERNEL) b += 1.0;
+    else if (g.prior == HIKF_PRIOR_SCALED_I) a = g.alpha;
+    const unsigned blocks = unsigned((g.m + 3) / 4);
+    if (g.fmm_prec == HIKF_FMM_F64)
+        hipLaunchKernelGGL(k_cov_out<double>, dim3(blocks), dim3(256), 0, s, g.m, g.p, t, a, b, v,
+                           static_cast<const double *>(qv), qv_ld, histC, w, out);
+    else
+        hipLaunchKernelGGL(k_cov_out<float>, dim3(blocks), dim3(256), 0, s, g.m, g.p, t, a, b, v,
+                           static_cast<const float *>(qv), qv_ld, histC, w, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_validate(const Geometry &g, const Layout &lay, char *res, const double *x0,
                            hipStream_t s) {

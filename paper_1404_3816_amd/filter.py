@@ -51,7 +51,8 @@ def problem_from_csr(dim, n, rowptr, col, val, r_diag, family="powexp", theta=1.
     return pr, (t_rowptr, t_col, t_val, t_r, t_x0)
 
 
-def make_options(n_c=4, precision="f32", direct=False, timing=False, graph=False, riccati=0):
+def make_options(n_c=4, precision="f32", direct=False, timing=False, graph=False, riccati=0,
+                 history=0):
     op = H.hikf_options()
     op.n_c = int(n_c)
     op.fmm_precision = PRECISIONS[precision]
@@ -59,6 +60,7 @@ def make_options(n_c=4, precision="f32", direct=False, timing=False, graph=False
     op.timing = 1 if timing else 0
     op.graph = 1 if graph else 0
     op.riccati = int(riccati)
+    op.history = int(history)
     return op
 
 
@@ -122,6 +124,19 @@ class HikfFilter:
                else ctypes.c_void_p(None))
         H.check(H.hikf_import_state(self.handle, ptr(x), ptr(var), ptr(c), _stream_handle(stream)),
                 "hikf_import_state", self.handle)
+
+    def cov_apply(self, v, stream=None):
+        """P_{t|t} v for the current step t (needs options.history >= t)."""
+        v = v.contiguous()
+        assert v.dtype == torch.float64 and v.numel() == self.m and v.is_cuda
+        out = torch.empty_like(v)
+        nbytes = int(self.info.query_bytes)
+        scratch = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=v.device)
+        H.check(H.hikf_cov_apply(self.handle, ctypes.c_void_p(v.data_ptr()),
+                                 ctypes.c_void_p(out.data_ptr()),
+                                 ctypes.c_void_p(scratch.data_ptr()), nbytes,
+                                 _stream_handle(stream)), "hikf_cov_apply", self.handle)
+        return out
 
     def export_cq(self, stream=None):
         out = torch.empty(self.m, self.p, dtype=torch.float64, device=self.resident.device)

@@ -55,12 +55,13 @@ class hikf_problem(ctypes.Structure):
 
 class hikf_options(ctypes.Structure):
     _fields_ = [("n_c", c_i32), ("fmm_precision", c_i32), ("direct", c_i32),
-                ("timing", c_i32), ("riccati", c_i32), ("graph", c_i32)]
+                ("timing", c_i32), ("riccati", c_i32), ("history", c_i32), ("graph", c_i32)]
 
 
 class hikf_plan_info(ctypes.Structure):
     _fields_ = [("resident_bytes", c_sz), ("scratch_bytes", c_sz), ("m", c_i64),
-                ("depth", c_i32), ("r", c_i32), ("near_pairs", c_i64), ("far_pairs", c_i64)]
+                ("depth", c_i32), ("r", c_i32), ("near_pairs", c_i64), ("far_pairs", c_i64),
+                ("query_bytes", c_sz)]
 
 
 HIKF_NUM_PHASES = 12
@@ -83,6 +84,7 @@ _SIGS = {
                           _P(c_vp)]),
     "hikf_step": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     "hikf_step_batch": (c_i32, [_P(c_vp), _P(c_vp), _P(c_vp), _P(c_vp), c_i32, c_vp]),
+    "hikf_cov_apply": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
     "hikf_query": (c_i32, [c_vp, _P(hikf_stats)]),
     "hikf_export_state": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     "hikf_import_state": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
@@ -103,6 +105,7 @@ hikf_plan = _lib.hikf_plan
 hikf_init = _lib.hikf_init
 hikf_step = _lib.hikf_step
 hikf_step_batch = _lib.hikf_step_batch
+hikf_cov_apply = _lib.hikf_cov_apply
 hikf_query = _lib.hikf_query
 hikf_export_state = _lib.hikf_export_state
 hikf_import_state = _lib.hikf_import_state

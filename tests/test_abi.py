@@ -138,3 +138,21 @@ def test_plan_bf16_modes_add_split_operands():
     assert i3.scratch_bytes == i1.scratch_bytes > i32.scratch_bytes
     # W split: 2 copies x 2 bytes per entry of the m x p matrix
     assert i3.scratch_bytes - i32.scratch_bytes >= 2 * 2 * 32 ** 3 * 64
+
+
+def test_plan_query_bytes_only_with_history():
+    from paper_1404_3816_amd import hikf as H
+    pr = _problem(dim=2, n=64, p=32)
+    op = H.hikf_options()
+    op.n_c, op.fmm_precision, op.history = 4, H.HIKF_FMM_F32, 0
+    info = H.hikf_plan_info()
+    assert H.hikf_plan(ctypes.byref(pr), ctypes.byref(op), ctypes.byref(info)) == H.HIKF_OK
+    base, q0 = info.resident_bytes, info.query_bytes
+    op.history = 5
+    assert H.hikf_plan(ctypes.byref(pr), ctypes.byref(op), ctypes.byref(info)) == H.HIKF_OK
+    assert q0 == 0 and info.query_bytes > 64 * 64 * 16 * 4
+    # the history holds C_prior (m p doubles) and S^-1 (p^2 doubles) per step
+    assert info.resident_bytes - base >= 5 * (64 * 64 * 32 + 32 * 32) * 8
+    op.history = -1
+    assert H.hikf_plan(ctypes.byref(pr), ctypes.byref(op), ctypes.byref(info)) == H.HIKF_E_INVALID
+    assert H.hikf_cov_apply(None, None, None, None, 0, None) == H.HIKF_E_INVALID
