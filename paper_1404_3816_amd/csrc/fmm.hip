@@ -598,14 +598,22 @@ __global__ void k_split_t(int64_t nslots, int r, int rt, int kr, const float *T,
 
 // M2L on BF16 MFMA: as k_m2l_mma, with the translation tile (A, [target
 // node][source node]) and M_A (B, [column][source node]) staged as hi / lo.
-template <bool SPLIT, int PT>
+// Software-pipelined over the interaction list: the next source's tiles are
+// loaded into registers while the MFMAs of the current one run, then moved
+// to LDS between two barriers.  KR (nodes padded to 32) is a template
+// parameter so that the per-thread staging counts are compile-time.
+template <bool SPLIT, int PT, int KR>
 __global__ void __launch_bounds__(kBlock)
-k_m2l_bf16(int dim, int r, int kr, int p, int lev, const __bf16 *Mh, const __bf16 *Ml,
+k_m2l_bf16(int dim, int r, int p, int lev, const __bf16 *Mh, const __bf16 *Ml,
            const __bf16 *Th, const __bf16 *Tl, float *L) {
     constexpr int NCT = PT / 16;
-    constexpr int MAXT = 8;                            // tiles per wave (r <= 128)
+    constexpr int MAXT = 8;                            // tiles per wave
+    constexpr int KP = KR + 8;
+    constexpr int KCH = KR / 8;                        // 16-byte chunks per row
+    constexpr int TPT = (KR * KCH + kBlock - 1) / kBlock;   // T chunks per thread (rt16 <= KR)
+    constexpr int MPT = (PT * KCH + kBlock - 1) / kBlock;   // M chunks per thread
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int RT = (r + 15) / 16, rt16 = 16 * RT, KP = kr + 8;
+    const int RT = (r + 15) / 16, rt16 = 16 * RT;
     __bf16 *sTh = reinterpret_cast<__bf16 *>(smem_raw);
     __bf16 *sTl = sTh + rt16 * KP;
     __bf16 *sMh = sTl + rt16 * KP;
@@ -617,40 +625,69 @@ k_m2l_bf16(int dim, int r, int kr, int p, int lev, const __bf16 *Mh, const __bf1
     const int noff = dim == 2 ? 49 : 343;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, q = lane >> 4;
-    const int ntiles = RT * NCT, kch = kr / 8;        // 16-byte chunks per row
+    const int ntiles = RT * NCT;
     int b[3];
     box_coords(B, nb, dim, b);
+    // next interaction-list offset after oi (noff when none); uniform
+    auto next_il = [&](int oi) {
+        for (++oi; oi < noff; ++oi) {
+            int o[3] = {oi % 7 - 3, (oi / 7) % 7 - 3, oi / 49 - 3};
+            if (il_member(b, o, nb, dim)) break;
+        }
+        return oi;
+    };
+    bf8 th[TPT], tl[TPT], mh[MPT], ml[MPT];
+    const bf8 zero8 = {};
+    // load the tiles of interaction-list offset OI into registers
+#define HIKF_M2L_FETCH(OI)                                                                    \
+    do {                                                                                      \
+        const int fo = (OI);                                                                  \
+        const int fa[3] = {b[0] + fo % 7 - 3, b[1] + (fo / 7) % 7 - 3,                        \
+                           dim == 3 ? b[2] + fo / 49 - 3 : 0};                                \
+        const int64_t A = box_index(fa, nb, dim);                                             \
+        const int64_t tbase = int64_t(fo) * rt16 * KR;                                        \
+        _Pragma("unroll") for (int u = 0; u < TPT; ++u) {                                     \
+            const int idx = tid + kBlock * u, i = idx / KCH, ch = idx % KCH;                  \
+            if (i < rt16) {                                                                   \
+                th[u] = *reinterpret_cast<const bf8 *>(Th + tbase + int64_t(i) * KR + 8 * ch); \
+                tl[u] = *reinterpret_cast<const bf8 *>(Tl + tbase + int64_t(i) * KR + 8 * ch); \
+            }                                                                                 \
+        }                                                                                     \
+        _Pragma("unroll") for (int u = 0; u < MPT; ++u) {                                     \
+            const int idx = tid + kBlock * u, c = idx / KCH, ch = idx % KCH;                  \
+            if (c < ncols) {                                                                  \
+                const int64_t g = (A * p + c0 + c) * KR + 8 * ch;                             \
+                mh[u] = *reinterpret_cast<const bf8 *>(Mh + g);                               \
+                ml[u] = *reinterpret_cast<const bf8 *>(Ml + g);                               \
+            } else {                                                                          \
+                mh[u] = ml[u] = zero8;                                                        \
+            }                                                                                 \
+        }                                                                                     \
+    } while (0)
     f4v acc[MAXT];
 #pragma unroll
     for (int u = 0; u < MAXT; ++u) acc[u] = f4v{0, 0, 0, 0};
-    for (int oi = 0; oi < noff; ++oi) {
-        int o[3] = {oi % 7 - 3, (oi / 7) % 7 - 3, oi / 49 - 3};
-        if (!il_member(b, o, nb, dim)) continue;       // uniform
-        int a[3] = {b[0] + o[0], b[1] + o[1], dim == 3 ? b[2] + o[2] : 0};
-        const int64_t A = box_index(a, nb, dim);
-        const int64_t tbase = int64_t(oi) * rt16 * kr;
-        __syncthreads();
-        for (int idx = tid; idx < rt16 * kch; idx += kBlock) {
-            const int i = idx / kch, ch = idx % kch;
-            *reinterpret_cast<bf8 *>(sTh + i * KP + 8 * ch) =
-                *reinterpret_cast<const bf8 *>(Th + tbase + int64_t(i) * kr + 8 * ch);
-            *reinterpret_cast<bf8 *>(sTl + i * KP + 8 * ch) =
-                *reinterpret_cast<const bf8 *>(Tl + tbase + int64_t(i) * kr + 8 * ch);
-        }
-        for (int idx = tid; idx < PT * kch; idx += kBlock) {
-            const int c = idx / kch, ch = idx % kch;
-            bf8 vh, vl;
-            if (c < ncols) {
-                const int64_t g = (A * p + c0 + c) * kr + 8 * ch;
-                vh = *reinterpret_cast<const bf8 *>(Mh + g);
-                vl = *reinterpret_cast<const bf8 *>(Ml + g);
-            } else {
-                for (int e = 0; e < 8; ++e) vh[e] = vl[e] = (__bf16)0.f;
+    int oi = next_il(-1);
+    if (oi < noff) HIKF_M2L_FETCH(oi);
+    while (oi < noff) {
+        __syncthreads();                               // LDS free (previous MFMAs done)
+#pragma unroll
+        for (int u = 0; u < TPT; ++u) {
+            const int idx = tid + kBlock * u, i = idx / KCH, ch = idx % KCH;
+            if (i < rt16) {
+                *reinterpret_cast<bf8 *>(sTh + i * KP + 8 * ch) = th[u];
+                *reinterpret_cast<bf8 *>(sTl + i * KP + 8 * ch) = tl[u];
             }
-            *reinterpret_cast<bf8 *>(sMh + c * KP + 8 * ch) = vh;
-            *reinterpret_cast<bf8 *>(sMl + c * KP + 8 * ch) = vl;
+        }
+#pragma unroll
+        for (int u = 0; u < MPT; ++u) {
+            const int idx = tid + kBlock * u, c = idx / KCH, ch = idx % KCH;
+            *reinterpret_cast<bf8 *>(sMh + c * KP + 8 * ch) = mh[u];
+            *reinterpret_cast<bf8 *>(sMl + c * KP + 8 * ch) = ml[u];
         }
         __syncthreads();
+        const int on = next_il(oi);
+        if (on < noff) HIKF_M2L_FETCH(on);             // in flight during the MFMAs
 #pragma unroll
         for (int u = 0; u < MAXT; ++u) {
             const int tile = wave + 4 * u;
@@ -660,13 +697,16 @@ k_m2l_bf16(int dim, int r, int kr, int p, int lev, const __bf16 *Mh, const __bf1
             const __bf16 *al = sTl + (16 * rt + lr) * KP + 8 * q;
             const __bf16 *bh = sMh + (16 * ct + lr) * KP + 8 * q;
             const __bf16 *bl = sMl + (16 * ct + lr) * KP + 8 * q;
-            for (int k0 = 0; k0 < kr; k0 += 32)
+#pragma unroll
+            for (int k0 = 0; k0 < KR; k0 += 32)
                 acc[u] = mma_bf16<SPLIT>(*reinterpret_cast<const bf8 *>(ah + k0),
                                          *reinterpret_cast<const bf8 *>(al + k0),
                                          *reinterpret_cast<const bf8 *>(bh + k0),
                                          *reinterpret_cast<const bf8 *>(bl + k0), acc[u]);
         }
+        oi = on;
     }
+#undef HIKF_M2L_FETCH
 #pragma unroll
     for (int u = 0; u < MAXT; ++u) {
         const int tile = wave + 4 * u;
@@ -899,8 +939,9 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
                 hipLaunchKernelGGL(k_split_t, dim3(unsigned((nslots * rt16 * kr + 255) / 256)),
                                    dim3(256), 0, s, nslots, r, rt16, kr, Tm2l, Th, Tl);
                 const size_t lds = size_t(rt16 + 128) * (kr + 8) * 2 * sizeof(__bf16);
-                e = allow_lds(k_m2l_bf16<true, 128>, lds);
-                if (e == hipSuccess) e = allow_lds(k_m2l_bf16<false, 128>, lds);
+                e = kr == 32 ? allow_lds(k_m2l_bf16<true, 128, 32>, lds) : allow_lds(k_m2l_bf16<true, 128, 64>, lds);
+                if (e == hipSuccess)
+                    e = kr == 32 ? allow_lds(k_m2l_bf16<false, 128, 32>, lds) : allow_lds(k_m2l_bf16<false, 128, 64>, lds);
                 if (e != hipSuccess) return e;
                 for (int lev = 2; lev <= D; ++lev) {
                     const int64_t nbx = g.boxes(lev);
@@ -910,14 +951,13 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
                                        s, r, kr, p, Mlev(lev), Mh, Ml);
                     const __bf16 *Thl = Th + int64_t(lev - 2) * g.noff() * rt16 * kr;
                     const __bf16 *Tll = Tl + int64_t(lev - 2) * g.noff() * rt16 * kr;
-                    if (split)
-                        hipLaunchKernelGGL((k_m2l_bf16<true, 128>), dim3(unsigned(nbx), (p + 127) / 128),
-                                           dim3(kBlock), lds, s, dim, r, kr, p, lev, Mh, Ml, Thl, Tll,
-                                           Llev(lev));
-                    else
-                        hipLaunchKernelGGL((k_m2l_bf16<false, 128>), dim3(unsigned(nbx), (p + 127) / 128),
-                                           dim3(kBlock), lds, s, dim, r, kr, p, lev, Mh, Ml, Thl, Tll,
-                                           Llev(lev));
+                    const dim3 grid(unsigned(nbx), (p + 127) / 128);
+#define HIKF_M2L_BF16(SPL, KRV)                                                            \
+    hipLaunchKernelGGL((k_m2l_bf16<SPL, 128, KRV>), grid, dim3(kBlock), lds, s, dim, r, p, lev, \
+                       Mh, Ml, Thl, Tll, Llev(lev))
+                    if (split) { if (kr == 32) HIKF_M2L_BF16(true, 32); else HIKF_M2L_BF16(true, 64); }
+                    else       { if (kr == 32) HIKF_M2L_BF16(false, 32); else HIKF_M2L_BF16(false, 64); }
+#undef HIKF_M2L_BF16
                 }
             }
         }
