@@ -441,13 +441,17 @@ k_l2p_p2p_mma(int dim, int n, int npad, int ls, int depth, int r, int rpad, int 
 // tiles), dealt round-robin to the 4 waves; for every interaction-list box A
 // the translation T_{l,o} (r x r) and M_A (r x PT) are staged in LDS (k padded
 // to a multiple of 4 with zeros) and multiplied on MFMA.
-template <typename T, int PT>
+template <typename T, int PT, int RMAX>
 __global__ void __launch_bounds__(kBlock)
 k_m2l_mma(int dim, int r, int p, int lev, const T *M, const T *Tlev, T *L) {
     typedef typename Mma<T>::v4 v4;
     constexpr int NCT = PT / 16;
-    constexpr int MAXT = 8;                            // tiles per wave (r <= 128)
+    constexpr int MAXT = 8;                            // tiles per wave (r <= 64)
     constexpr int WP = PT + Mma<T>::pad;
+    constexpr int VW = 16 / sizeof(T);                 // values per 16-byte load
+    typedef T tv __attribute__((ext_vector_type(VW)));
+    constexpr int MPT = (RMAX * PT / VW + kBlock - 1) / kBlock;    // M loads per thread (r <= RMAX)
+    constexpr int TPT = (RMAX * RMAX + kBlock - 1) / kBlock;       // T values per thread
     extern __shared__ __align__(16) unsigned char smem_raw[];
     // TP = 68 (4 mod 64 words) spreads the 16 rows x 4 k of an A-operand
     // read over distinct LDS banks
@@ -462,27 +466,62 @@ k_m2l_mma(int dim, int r, int p, int lev, const T *M, const T *Tlev, T *L) {
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, q = lane >> 4;
     const int ntiles = RT * NCT;
+    const int nm = KR * (PT / VW), nt = 16 * RT * KR;
     int b[3];
     box_coords(B, nb, dim, b);
+    // The next interaction-list source is loaded into registers while the
+    // MFMAs of the current one run, then moved to LDS between two barriers.
+    tv mreg[MPT];
+    T treg[TPT];
+#define HIKF_M2L_FETCH(OI)                                                                    \
+    do {                                                                                      \
+        const int fo = (OI);                                                                  \
+        const int fa[3] = {b[0] + fo % 7 - 3, b[1] + (fo / 7) % 7 - 3,                        \
+                           dim == 3 ? b[2] + fo / 49 - 3 : 0};                                \
+        const int64_t A = box_index(fa, nb, dim);                                             \
+        const T *Toff = Tlev + int64_t(fo) * r * r;                                           \
+        _Pragma("unroll") for (int u = 0; u < MPT; ++u) {                                     \
+            const int idx = tid + kBlock * u, k = idx / (PT / VW), ch = idx % (PT / VW);      \
+            tv v;                                                                             \
+            if (idx < nm && k < r && VW * ch < ncols) {                                       \
+                v = *reinterpret_cast<const tv *>(M + (A * r + k) * p + c0 + VW * ch);        \
+            } else {                                                                          \
+                _Pragma("unroll") for (int e = 0; e < VW; ++e) v[e] = (T)0;                   \
+            }                                                                                 \
+            mreg[u] = v;                                                                      \
+        }                                                                                     \
+        _Pragma("unroll") for (int u = 0; u < TPT; ++u) {                                     \
+            const int idx = tid + kBlock * u, i = idx / KR, k = idx % KR;                     \
+            treg[u] = (idx < nt && i < r && k < r) ? Toff[i * r + k] : (T)0;                  \
+        }                                                                                     \
+    } while (0)
+    auto next_il = [&](int oi) {
+        for (++oi; oi < noff; ++oi) {
+            int o[3] = {oi % 7 - 3, (oi / 7) % 7 - 3, oi / 49 - 3};
+            if (il_member(b, o, nb, dim)) break;
+        }
+        return oi;
+    };
     v4 acc[MAXT];
 #pragma unroll
     for (int u = 0; u < MAXT; ++u) acc[u] = v4{0, 0, 0, 0};
-    for (int oi = 0; oi < noff; ++oi) {
-        int o[3] = {oi % 7 - 3, (oi / 7) % 7 - 3, oi / 49 - 3};
-        if (!il_member(b, o, nb, dim)) continue;       // uniform
-        int a[3] = {b[0] + o[0], b[1] + o[1], dim == 3 ? b[2] + o[2] : 0};
-        const int64_t A = box_index(a, nb, dim);
-        const T *Toff = Tlev + int64_t(oi) * r * r;
-        __syncthreads();
-        for (int idx = tid; idx < KR * PT; idx += kBlock) {
-            const int k = idx / PT, c = idx % PT;
-            sM[k * WP + c] = (k < r && c < ncols) ? M[(A * r + k) * p + c0 + c] : (T)0;
+    int oi = next_il(-1);
+    if (oi < noff) HIKF_M2L_FETCH(oi);
+    while (oi < noff) {
+        __syncthreads();                               // LDS free (previous MFMAs done)
+#pragma unroll
+        for (int u = 0; u < MPT; ++u) {
+            const int idx = tid + kBlock * u, k = idx / (PT / VW), ch = idx % (PT / VW);
+            if (idx < nm) *reinterpret_cast<tv *>(sM + k * WP + VW * ch) = mreg[u];
         }
-        for (int idx = tid; idx < 16 * RT * KR; idx += kBlock) {
-            const int i = idx / KR, k = idx % KR;
-            sT[i * TP + k] = (i < r && k < r) ? Toff[i * r + k] : (T)0;
+#pragma unroll
+        for (int u = 0; u < TPT; ++u) {
+            const int idx = tid + kBlock * u, i = idx / KR, k = idx % KR;
+            if (idx < nt) sT[i * TP + k] = treg[u];
         }
         __syncthreads();
+        const int on = next_il(oi);
+        if (on < noff) HIKF_M2L_FETCH(on);             // in flight during the MFMAs
 #pragma unroll
         for (int u = 0; u < MAXT; ++u) {
             const int tile = wave + 4 * u;
@@ -493,7 +532,9 @@ k_m2l_mma(int dim, int r, int p, int lev, const T *M, const T *Tlev, T *L) {
             for (int k0 = 0; k0 < KR; k0 += 4)
                 acc[u] = Mma<T>::op(arow[k0], bcol[k0 * WP], acc[u]);
         }
+        oi = on;
     }
+#undef HIKF_M2L_FETCH
 #pragma unroll
     for (int u = 0; u < MAXT; ++u) {
         const int tile = wave + 4 * u;
@@ -965,12 +1006,18 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
             constexpr int MPT = sizeof(T) == 4 ? 128 : 64;
             const int RT = (r + 15) / 16, KR = (r + 3) / 4 * 4;
             const size_t lds = (size_t(KR) * (MPT + Mma<T>::pad) + size_t(16 * RT) * 68) * sizeof(T);
-            e = allow_lds(k_m2l_mma<T, MPT>, lds);
+            e = r <= 32 ? allow_lds(k_m2l_mma<T, MPT, 32>, lds) : allow_lds(k_m2l_mma<T, MPT, 64>, lds);
             if (e != hipSuccess) return e;
-            for (int lev = 2; lev <= D; ++lev)
-                hipLaunchKernelGGL((k_m2l_mma<T, MPT>), dim3(unsigned(g.boxes(lev)), (p + MPT - 1) / MPT),
-                                   dim3(kBlock), lds, s, dim, r, p, lev, Mlev(lev),
-                                   Tm2l + int64_t(lev - 2) * g.noff() * r * r, Llev(lev));
+            for (int lev = 2; lev <= D; ++lev) {
+                const dim3 grid(unsigned(g.boxes(lev)), (p + MPT - 1) / MPT);
+                const T *Tl = Tm2l + int64_t(lev - 2) * g.noff() * r * r;
+                if (r <= 32)
+                    hipLaunchKernelGGL((k_m2l_mma<T, MPT, 32>), grid, dim3(kBlock), lds, s, dim, r, p,
+                                       lev, Mlev(lev), Tl, Llev(lev));
+                else
+                    hipLaunchKernelGGL((k_m2l_mma<T, MPT, 64>), grid, dim3(kBlock), lds, s, dim, r, p,
+                                       lev, Mlev(lev), Tl, Llev(lev));
+            }
         }
         tend(tm, HIKF_PHASE_M2L, s);
         // L2L
