@@ -452,8 +452,10 @@ __device__ __forceinline__ void rowpass_part(double *sB, double *red, int64_t m,
             const dv2 b = dv2{acc[t][2] * rb[0], acc[t][3] * rb[1]};   // h = 1 of own row
             const dv2 g = dv2{swap_pair(odd ? a[0] : b[0]), swap_pair(odd ? a[1] : b[1])};
             const int cc = c0 + (odd ? 8 : 0);
-            if (r0 < m) *reinterpret_cast<dv2 *>(C + r0 * P + cc) = odd ? g : a;
-            if (r0 + 1 < m) *reinterpret_cast<dv2 *>(C + (r0 + 1) * P + cc) = odd ? b : g;
+            // streaming stores: C is not read again within this pass
+            if (r0 < m) __builtin_nontemporal_store(odd ? g : a, reinterpret_cast<dv2 *>(C + r0 * P + cc));
+            if (r0 + 1 < m)
+                __builtin_nontemporal_store(odd ? b : g, reinterpret_cast<dv2 *>(C + (r0 + 1) * P + cc));
         }
     }
     dv += __shfl_xor(dv, 16, 64);
