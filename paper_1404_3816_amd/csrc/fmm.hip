@@ -189,30 +189,63 @@ __global__ void k_scatter_w(int64_t nnz, int p, int64_t m, int dim, int n, int n
 }
 
 // ---------------------------------------------------------------- P2M
+// Panels are staged in LDS with 16-byte loads (rows of PT values are
+// contiguous and 16-byte aligned: p and PT are multiples of 16), and so are
+// the interpolation operators, which every output of the workgroup reads.
+template <typename T>
+__device__ __forceinline__ void stage_rows(T *dst, int dpitch, const T *src, int64_t spitch,
+                                           int rows, int PT, int ncols) {
+    constexpr int VW = 16 / sizeof(T);
+    typedef T tv __attribute__((ext_vector_type(VW)));
+    const int chunks = PT / VW;
+    for (int idx = threadIdx.x; idx < rows * chunks; idx += blockDim.x) {
+        const int k = idx / chunks, ch = idx % chunks;
+        tv v;
+        if (VW * ch < ncols) {
+            v = *reinterpret_cast<const tv *>(src + k * spitch + VW * ch);
+        } else {
+#pragma unroll
+            for (int e = 0; e < VW; ++e) v[e] = (T)0;
+        }
+        *reinterpret_cast<tv *>(dst + k * dpitch + VW * ch) = v;
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_p2m(int dim, int n, int ls, int depth, int r, int p, int PT, const T *W,
       const T *Sleaf, T *Mleaf) {
+    constexpr int VW = 16 / sizeof(T);
+    typedef T tv __attribute__((ext_vector_type(VW)));
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sW = reinterpret_cast<T *>(smem_raw);           // [64][PT]
+    T *sS = sW + kLeafPts * PT;                        // [r][64]
     const int64_t B = blockIdx.x;
     const int c0 = blockIdx.y * PT;
     const int ncols = min(PT, p - c0);
     const int nb = 1 << depth;
     int bc[3];
     box_coords(B, nb, dim, bc);
-    for (int idx = threadIdx.x; idx < kLeafPts * PT; idx += blockDim.x) {
-        int j = idx / PT, c = idx % PT;
-        T v = (T)0;
-        if (c < ncols) v = W[leaf_point(bc, j, dim, n, ls) * p + c0 + c];
-        sW[idx] = v;
+    const int chunks = PT / VW;
+    for (int idx = threadIdx.x; idx < kLeafPts * chunks; idx += blockDim.x) {
+        const int j = idx / chunks, ch = idx % chunks;
+        tv v;
+        if (VW * ch < ncols) {
+            v = *reinterpret_cast<const tv *>(W + leaf_point(bc, j, dim, n, ls) * p + c0 + VW * ch);
+        } else {
+#pragma unroll
+            for (int e = 0; e < VW; ++e) v[e] = (T)0;
+        }
+        *reinterpret_cast<tv *>(sW + j * PT + VW * ch) = v;
     }
+    for (int idx = threadIdx.x; idx < r * kLeafPts; idx += blockDim.x) sS[idx] = Sleaf[idx];
     __syncthreads();
     for (int idx = threadIdx.x; idx < r * PT; idx += blockDim.x) {
-        int k = idx / PT, c = idx % PT;
+        const int k = idx / PT, c = idx % PT;
         if (c >= ncols) continue;
         T acc = (T)0;
-        const T *srow = Sleaf + k * kLeafPts;
+        const T *srow = sS + k * kLeafPts;
+#pragma unroll 16
         for (int j = 0; j < kLeafPts; ++j) acc += srow[j] * sW[j * PT + c];
         Mleaf[(B * r + k) * p + c0 + c] = acc;
     }
@@ -228,26 +261,38 @@ k_m2m(int dim, int r, int p, int lev, int PT, const T *Mchild, const T *Schild, 
     const int c0 = blockIdx.y * PT;
     const int ncols = min(PT, p - c0);
     const int nb = 1 << lev, nbc = nb << 1, nch = 1 << dim;
+    T *sS = sM + nch * r * PT;                          // [r][r] of one child
     int pc[3];
     box_coords(P, nb, dim, pc);
-    for (int idx = threadIdx.x; idx < nch * r * PT; idx += blockDim.x) {
-        int ch = idx / (r * PT), rem = idx % (r * PT);
-        int k = rem / PT, c = rem % PT;
+    for (int ch = 0; ch < nch; ++ch) {
         int cc[3] = {2 * pc[0] + (ch & 1), 2 * pc[1] + ((ch >> 1) & 1), 2 * pc[2] + ((ch >> 2) & 1)};
-        int64_t Bc = box_index(cc, nbc, dim);
-        sM[idx] = (c < ncols) ? Mchild[(Bc * r + k) * p + c0 + c] : (T)0;
+        const int64_t Bc = box_index(cc, nbc, dim);
+        stage_rows(sM + ch * r * PT, PT, Mchild + Bc * r * p + c0, p, r, PT, ncols);
     }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < r * PT; idx += blockDim.x) {
-        int k = idx / PT, c = idx % PT;
-        if (c >= ncols) continue;
-        T acc = (T)0;
-        for (int ch = 0; ch < nch; ++ch) {
-            const T *srow = Schild + (ch * r + k) * r;
-            const T *m = sM + ch * r * PT + c;
-            for (int kq = 0; kq < r; ++kq) acc += srow[kq] * m[kq * PT];
+    // outputs (k, c) per thread, accumulated over the children in order
+    T acc[4] = {(T)0, (T)0, (T)0, (T)0};
+    for (int ch = 0; ch < nch; ++ch) {
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < r * r; idx += blockDim.x) sS[idx] = Schild[ch * r * r + idx];
+        __syncthreads();
+        const T *m = sM + ch * r * PT;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int idx = threadIdx.x + u * blockDim.x;
+            if (idx >= r * PT) break;
+            const int k = idx / PT, c = idx % PT;
+            const T *srow = sS + k * r;
+            T a = (T)0;
+            for (int kq = 0; kq < r; ++kq) a += srow[kq] * m[kq * PT + c];
+            acc[u] += a;
         }
-        Mpar[(P * r + k) * p + c0 + c] = acc;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int idx = threadIdx.x + u * blockDim.x;
+        if (idx >= r * PT) break;
+        const int k = idx / PT, c = idx % PT;
+        if (c < ncols) Mpar[(P * r + k) * p + c0 + c] = acc[u];
     }
 }
 
@@ -272,6 +317,7 @@ __global__ void __launch_bounds__(kBlock)
 k_l2l(int dim, int r, int p, int lev, int PT, const T *Lpar, const T *Schild, T *Lchild) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sL = reinterpret_cast<T *>(smem_raw);           // [r][PT]
+    T *sS = sL + r * PT;                               // [r][r] of this child
     const int64_t Bc = blockIdx.x;                     // child at level lev + 1
     const int c0 = blockIdx.y * PT;
     const int ncols = min(PT, p - c0);
@@ -281,17 +327,14 @@ k_l2l(int dim, int r, int p, int lev, int PT, const T *Lpar, const T *Schild, T 
     int pc[3] = {cc[0] >> 1, cc[1] >> 1, cc[2] >> 1};
     int ch = (cc[0] & 1) | ((cc[1] & 1) << 1) | ((cc[2] & 1) << 2);
     int64_t P = box_index(pc, nb, dim);
-    for (int idx = threadIdx.x; idx < r * PT; idx += blockDim.x) {
-        int k = idx / PT, c = idx % PT;
-        sL[idx] = (c < ncols) ? Lpar[(P * r + k) * p + c0 + c] : (T)0;
-    }
+    stage_rows(sL, PT, Lpar + P * r * p + c0, p, r, PT, ncols);
+    for (int idx = threadIdx.x; idx < r * r; idx += blockDim.x) sS[idx] = Schild[int64_t(ch) * r * r + idx];
     __syncthreads();
     for (int idx = threadIdx.x; idx < r * PT; idx += blockDim.x) {
         int kq = idx / PT, c = idx % PT;
         if (c >= ncols) continue;
         T acc = (T)0;
-        const T *S = Schild + int64_t(ch) * r * r + kq;
-        for (int k = 0; k < r; ++k) acc += S[k * r] * sL[k * PT + c];
+        for (int k = 0; k < r; ++k) acc += sS[k * r + kq] * sL[k * PT + c];
         Lchild[(Bc * r + kq) * p + c0 + c] += acc;
     }
 }
@@ -958,16 +1001,20 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
         tbegin(tm, HIKF_PHASE_P2M, s);
         int PT = min(64, p);
         hipLaunchKernelGGL(k_p2m<T>, dim3(unsigned(g.boxes(D)), (p + PT - 1) / PT), dim3(kBlock),
-                           kLeafPts * PT * sizeof(T), s, dim, g.npad, g.ls, D, r, p, PT, W, Sleaf,
-                           Mlev(D));
+                           (kLeafPts * PT + r * kLeafPts) * sizeof(T), s, dim, g.npad, g.ls, D, r,
+                           p, PT, W, Sleaf, Mlev(D));
         tend(tm, HIKF_PHASE_P2M, s);
         // M2M
         tbegin(tm, HIKF_PHASE_M2M, s);
-        PT = min(p, min(64, floor_pow2(int(lds_cap / ((size_t(1) << dim) * r * sizeof(T))))));
+        // r x PT outputs: at most 4 per thread; the children's panels and one
+        // child matrix share the LDS
+        PT = min(p, min(64, floor_pow2(int((lds_cap / sizeof(T) - size_t(r) * r) /
+                                            ((size_t(1) << dim) * r)))));
+        while (PT > 16 && r * PT > 4 * kBlock) PT /= 2;
         for (int lev = D - 1; lev >= 2; --lev)
             hipLaunchKernelGGL(k_m2m<T>, dim3(unsigned(g.boxes(lev)), (p + PT - 1) / PT),
-                               dim3(kBlock), (size_t(1) << dim) * r * PT * sizeof(T), s, dim, r, p,
-                               lev, PT, Mlev(lev + 1), Schild, Mlev(lev));
+                               dim3(kBlock), ((size_t(1) << dim) * r * PT + size_t(r) * r) * sizeof(T),
+                               s, dim, r, p, lev, PT, Mlev(lev + 1), Schild, Mlev(lev));
         tend(tm, HIKF_PHASE_M2M, s);
         // M2L
         tbegin(tm, HIKF_PHASE_M2L, s);
@@ -1025,8 +1072,8 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
         PT = min(p, 64);
         for (int lev = 2; lev < D; ++lev)
             hipLaunchKernelGGL(k_l2l<T>, dim3(unsigned(g.boxes(lev + 1)), (p + PT - 1) / PT),
-                               dim3(kBlock), size_t(r) * PT * sizeof(T), s, dim, r, p, lev, PT,
-                               Llev(lev), Schild, Llev(lev + 1));
+                               dim3(kBlock), (size_t(r) * PT + size_t(r) * r) * sizeof(T), s, dim,
+                               r, p, lev, PT, Llev(lev), Schild, Llev(lev + 1));
         tend(tm, HIKF_PHASE_L2L, s);
     }
     // near-field kernel blocks by leaf offset (all neighbours are within one
