@@ -391,16 +391,81 @@ k_l2p_p2p_mma(int dim, int n, int npad, int ls, int depth, int r, int rpad, int 
     v4 acc[NTI];
 #pragma unroll
     for (int t = 0; t < NTI; ++t) acc[t] = v4{0, 0, 0, 0};
+    constexpr int VW = 16 / sizeof(T), CH = PT / VW, KC = kLeafPts / VW;
+    typedef T tv __attribute__((ext_vector_type(VW)));
+    if (Knear) {
+        // Neighbour leaves only (3^dim offsets, kernel blocks from the table),
+        // software-pipelined: the next source's W rows and kernel block are
+        // loaded into registers while the MFMAs of the current one run.
+        constexpr int WPT = (kLeafPts * CH + kBlock - 1) / kBlock;
+        constexpr int KPT = (kLeafPts * KC + kBlock - 1) / kBlock;
+        const int nsl = dim == 2 ? 9 : 27;
+        auto next_src = [&](int sl) {
+            for (++sl; sl < nsl; ++sl) {
+                const int a0 = b[0] + sl % 3 - 1, a1 = b[1] + (sl / 3) % 3 - 1, a2 = b[2] + sl / 9 - 1;
+                if (a0 >= 0 && a0 < nb && a1 >= 0 && a1 < nb && (dim == 2 || (a2 >= 0 && a2 < nb))) break;
+            }
+            return sl;
+        };
+        tv wreg[WPT], kreg[KPT];
+#define HIKF_P2P_FETCH(SL)                                                                        \
+        do {                                                                                      \
+            const int fs = (SL);                                                                  \
+            const int fa[3] = {b[0] + fs % 3 - 1, b[1] + (fs / 3) % 3 - 1,                        \
+                               dim == 3 ? b[2] + fs / 9 - 1 : 0};                                 \
+            _Pragma("unroll") for (int u = 0; u < WPT; ++u) {                                     \
+                const int idx = tid + kBlock * u, j = idx / CH, ch = idx % CH;                    \
+                if (VW * ch < ncols) {                                                            \
+                    wreg[u] = *reinterpret_cast<const tv *>(W + leaf_point(fa, j, dim, npad, ls) * p \
+                                                             + c0 + VW * ch);                     \
+                } else {                                                                          \
+                    _Pragma("unroll") for (int e = 0; e < VW; ++e) wreg[u][e] = (T)0;             \
+                }                                                                                 \
+            }                                                                                     \
+            const T *kt = Knear + int64_t(fs) * kLeafPts * kLeafPts;                              \
+            _Pragma("unroll") for (int u = 0; u < KPT; ++u) {                                     \
+                const int idx = tid + kBlock * u, i = idx / KC, ch = idx % KC;                    \
+                kreg[u] = *reinterpret_cast<const tv *>(kt + i * kLeafPts + VW * ch);             \
+            }                                                                                     \
+        } while (0)
+        int sl = next_src(-1);
+        HIKF_P2P_FETCH(sl);                              // the leaf itself always exists
+        while (sl < nsl) {
+            __syncthreads();                             // LDS free (previous MFMAs done)
+#pragma unroll
+            for (int u = 0; u < WPT; ++u) {
+                const int idx = tid + kBlock * u, j = idx / CH, ch = idx % CH;
+                *reinterpret_cast<tv *>(sW + j * WP + VW * ch) = wreg[u];
+            }
+#pragma unroll
+            for (int u = 0; u < KPT; ++u) {
+                const int idx = tid + kBlock * u, i = idx / KC, ch = idx % KC;
+                *reinterpret_cast<tv *>(sK + i * KP + VW * ch) = kreg[u];
+            }
+            __syncthreads();
+            const int sn = next_src(sl);
+            if (sn < nsl) HIKF_P2P_FETCH(sn);            // in flight during the MFMAs
+            const T *arow = sK + (16 * wave + lr) * KP + q;
+            const T *bcol = sW + q * WP + lr;
+#pragma unroll 4
+            for (int k0 = 0; k0 < kLeafPts; k0 += 4) {
+                const T av = arow[k0];
+#pragma unroll
+                for (int t = 0; t < NTI; ++t) acc[t] = Mma<T>::op(av, bcol[k0 * WP + 16 * t], acc[t]);
+            }
+            sl = sn;
+        }
+#undef HIKF_P2P_FETCH
+    }
     const int zlo = dim == 3 ? max(0, b[2] - rad) : 0;
     const int zhi = dim == 3 ? min(nb - 1, b[2] + rad) : 0;
+    if (!Knear)
     for (int az = zlo; az <= zhi; ++az)
     for (int ay = max(0, b[1] - rad); ay <= min(nb - 1, b[1] + rad); ++ay)
     for (int ax = max(0, b[0] - rad); ax <= min(nb - 1, b[0] + rad); ++ax) {
         int a[3] = {ax, ay, az};
         __syncthreads();
         // W_A: 64 rows of PT values as 16-byte pieces
-        constexpr int VW = 16 / sizeof(T), CH = PT / VW;
-        typedef T tv __attribute__((ext_vector_type(VW)));
         for (int idx = tid; idx < kLeafPts * CH; idx += kBlock) {
             const int j = idx / CH, ch = idx % CH;
             tv v;
@@ -412,17 +477,7 @@ k_l2p_p2p_mma(int dim, int n, int npad, int ls, int depth, int r, int rpad, int 
             }
             *reinterpret_cast<tv *>(sW + j * WP + VW * ch) = v;
         }
-        if (Knear) {
-            // the kernel block of offset a - b from the table
-            const int sl = (a[0] - b[0] + 1) + 3 * (a[1] - b[1] + 1) + (dim == 3 ? 9 * (a[2] - b[2] + 1) : 0);
-            const T *kt = Knear + int64_t(sl) * kLeafPts * kLeafPts;
-            constexpr int KC = kLeafPts / VW;
-            for (int idx = tid; idx < kLeafPts * KC; idx += kBlock) {
-                const int i = idx / KC, ch = idx % KC;
-                *reinterpret_cast<tv *>(sK + i * KP + VW * ch) =
-                    *reinterpret_cast<const tv *>(kt + i * kLeafPts + VW * ch);
-            }
-        } else {
+        {
             for (int idx = tid; idx < kLeafPts * kLeafPts; idx += kBlock) {
                 const int i = idx / kLeafPts, j = idx % kLeafPts;
                 int li[3], lj[3];
