@@ -887,8 +887,84 @@ k_l2p_p2p_bf16(int dim, int n, int npad, int ls, int depth, int r, int rpad, int
     f4v acc[NTI];
 #pragma unroll
     for (int t = 0; t < NTI; ++t) acc[t] = f4v{0, 0, 0, 0};
+    if (Knear) {
+        // neighbour leaves only, software-pipelined as in k_l2p_p2p_mma: the
+        // next source's split W panel and FP32 kernel block are loaded into
+        // registers during the current MFMAs; the block is split at staging
+        constexpr int WPT = (PT * 8 + kBlock - 1) / kBlock;
+        constexpr int KPT = (kLeafPts * kLeafPts / 4 + kBlock - 1) / kBlock;
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const int nsl = dim == 2 ? 9 : 27;
+        auto next_src = [&](int sl) {
+            for (++sl; sl < nsl; ++sl) {
+                const int a0 = b[0] + sl % 3 - 1, a1 = b[1] + (sl / 3) % 3 - 1, a2 = b[2] + sl / 9 - 1;
+                if (a0 >= 0 && a0 < nb && a1 >= 0 && a1 < nb && (dim == 2 || (a2 >= 0 && a2 < nb))) break;
+            }
+            return sl;
+        };
+        bf8 whr[WPT], wlr[WPT];
+        f4 kr4[KPT];
+        const bf8 zero8 = {};
+#define HIKF_P2P16_FETCH(SL)                                                                      \
+        do {                                                                                      \
+            const int fs = (SL);                                                                  \
+            const int fa[3] = {b[0] + fs % 3 - 1, b[1] + (fs / 3) % 3 - 1,                        \
+                               dim == 3 ? b[2] + fs / 9 - 1 : 0};                                 \
+            const int64_t A = box_index(fa, nb, dim);                                             \
+            _Pragma("unroll") for (int u = 0; u < WPT; ++u) {                                     \
+                const int idx = tid + kBlock * u, c = idx / 8, ch = idx % 8;                      \
+                if (c < ncols) {                                                                  \
+                    const int64_t g = (A * p + c0 + c) * kLeafPts + 8 * ch;                       \
+                    whr[u] = *reinterpret_cast<const bf8 *>(Wh + g);                              \
+                    wlr[u] = *reinterpret_cast<const bf8 *>(Wl + g);                              \
+                } else {                                                                          \
+                    whr[u] = wlr[u] = zero8;                                                      \
+                }                                                                                 \
+            }                                                                                     \
+            const float *kt = Knear + int64_t(fs) * kLeafPts * kLeafPts;                          \
+            _Pragma("unroll") for (int u = 0; u < KPT; ++u)                                       \
+                kr4[u] = *reinterpret_cast<const f4 *>(kt + 4 * (tid + kBlock * u));              \
+        } while (0)
+        int sl = next_src(-1);
+        HIKF_P2P16_FETCH(sl);
+        while (sl < nsl) {
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < WPT; ++u) {
+                const int idx = tid + kBlock * u, c = idx / 8, ch = idx % 8;
+                *reinterpret_cast<bf8 *>(sWh + c * KPB + 8 * ch) = whr[u];
+                *reinterpret_cast<bf8 *>(sWl + c * KPB + 8 * ch) = wlr[u];
+            }
+#pragma unroll
+            for (int u = 0; u < KPT; ++u) {
+                const int e0 = 4 * (tid + kBlock * u), i = e0 / kLeafPts, j = e0 % kLeafPts;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) split_bf16(kr4[u][e], sKh + i * KPB + j + e, sKl + i * KPB + j + e);
+            }
+            __syncthreads();
+            const int sn = next_src(sl);
+            if (sn < nsl) HIKF_P2P16_FETCH(sn);
+            const __bf16 *ah = sKh + (16 * wave + lr) * KPB + 8 * q;
+            const __bf16 *al = sKl + (16 * wave + lr) * KPB + 8 * q;
+#pragma unroll
+            for (int k0 = 0; k0 < kLeafPts; k0 += 32) {
+                const bf8 avh = *reinterpret_cast<const bf8 *>(ah + k0);
+                const bf8 avl = *reinterpret_cast<const bf8 *>(al + k0);
+#pragma unroll
+                for (int t = 0; t < NTI; ++t) {
+                    const __bf16 *bh = sWh + (16 * t + lr) * KPB + 8 * q + k0;
+                    const __bf16 *bl = sWl + (16 * t + lr) * KPB + 8 * q + k0;
+                    acc[t] = mma_bf16<SPLIT>(avh, avl, *reinterpret_cast<const bf8 *>(bh),
+                                             *reinterpret_cast<const bf8 *>(bl), acc[t]);
+                }
+            }
+            sl = sn;
+        }
+#undef HIKF_P2P16_FETCH
+    }
     const int zlo = dim == 3 ? max(0, b[2] - rad) : 0;
     const int zhi = dim == 3 ? min(nb - 1, b[2] + rad) : 0;
+    if (!Knear)
     for (int az = zlo; az <= zhi; ++az)
     for (int ay = max(0, b[1] - rad); ay <= min(nb - 1, b[1] + rad); ++ay)
     for (int ax = max(0, b[0] - rad); ax <= min(nb - 1, b[0] + rad); ++ax) {
