@@ -168,7 +168,7 @@ def test_steps_direct_f32_match_dense_kf():
     ex, ev = max_step_rel(xs, xa), max_step_rel(vs, va)
     print(f"direct FP32: x err {ex:.3e} var err {ev:.3e}")
     assert stats.last_status == 0
-    # spec target for the FP32 path: 1e-6 relative (no H^2 error here)
+    # the 1e-6 relative target of the FP32 path (no H^2 error in this mode)
     assert ev < 1e-6
     tx, tv = _fp32_tolerances(case, case.cq_exact(), cq)
     assert ex < tx and ev < tv
