@@ -223,7 +223,10 @@ hikf_status hikf_step(hikf_filter *f, const double *y_dev, double *x_out_dev,
 
 /*
  * Grouped step for a serving loop: hikf_step(filters[i], y_dev[i], x_out[i],
- * var_out[i], stream) for i = 0 .. count-1, in order, all on `stream`.
+ * var_out[i]) for i = 0 .. count-1.  The steps run concurrently on a few
+ * internal streams of the device (created on first use, kept for the life
+ * of the process), ordered after the work already queued on `stream`, and
+ * `stream` waits for all of them before anything queued on it later.
  * x_out_dev / var_out_dev may be NULL (no copies for any filter) or hold
  * NULL entries.  Each filter's result is exactly its solo hikf_step result;
  * the filters must be distinct.

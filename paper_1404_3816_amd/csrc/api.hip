@@ -2,6 +2,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 
 #include "hikf_internal.h"
@@ -138,6 +140,35 @@ hipError_t Timing::collect() {
 namespace {
 
 using hikf::Geometry;
+
+// Internal streams of hikf_step_batch, one set per device, created on first
+// use and kept until the process ends (default priority, non-blocking).
+constexpr int kPool = 4;
+struct StreamPool {
+    hipStream_t s[kPool] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kPool] = {};
+    std::mutex mu;
+};
+
+StreamPool *stream_pool() {
+    static std::mutex mu;
+    static std::map<int, StreamPool *> pools;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = pools.find(dev);
+    if (it != pools.end()) return it->second;
+    StreamPool *p = new (std::nothrow) StreamPool();
+    if (!p) return nullptr;
+    bool ok = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; ok && k < kPool; ++k)
+        ok = hipStreamCreateWithFlags(&p->s[k], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&p->join[k], hipEventDisableTiming) == hipSuccess;
+    if (!ok) return nullptr;                      // fall back to one stream
+    pools[dev] = p;
+    return p;
+}
 
 hikf_status build_geometry(const hikf_problem *pr, const hikf_options *op, Geometry *g) {
     if (!pr || !op || !g) return HIKF_E_INVALID;
@@ -430,12 +461,36 @@ hikf_status hikf_step_batch(hikf_filter *const *filters, const double *const *y_
     if (count < 0 || (count > 0 && (!filters || !y_dev))) return HIKF_E_INVALID;
     for (int32_t i = 0; i < count; ++i)
         if (!filters[i] || !y_dev[i]) return HIKF_E_INVALID;
-    for (int32_t i = 0; i < count; ++i) {
-        hikf_status st = hikf_step(filters[i], y_dev[i], x_out_dev ? x_out_dev[i] : nullptr,
-                                   var_out_dev ? var_out_dev[i] : nullptr, stream);
-        if (st != HIKF_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    StreamPool *pool = count > 1 ? stream_pool() : nullptr;
+    if (!pool) {
+        for (int32_t i = 0; i < count; ++i) {
+            hikf_status st = hikf_step(filters[i], y_dev[i], x_out_dev ? x_out_dev[i] : nullptr,
+                                       var_out_dev ? var_out_dev[i] : nullptr, stream);
+            if (st != HIKF_OK) return st;
+        }
+        return HIKF_OK;
     }
-    return HIKF_OK;
+    // Fork onto the device's internal streams (filter i on stream i mod
+    // kPool), join back into the caller's stream; each filter's kernels stay
+    // in order on one stream, so its result is that of a solo step.
+    std::lock_guard<std::mutex> lock(pool->mu);
+    const int used = count < kPool ? count : kPool;
+    hipError_t e = hipEventRecord(pool->fork, s);
+    for (int k = 0; e == hipSuccess && k < used; ++k) e = hipStreamWaitEvent(pool->s[k], pool->fork, 0);
+    if (e != hipSuccess) return set_err(filters[0], HIKF_E_DEVICE, "batch fork", e);
+    hikf_status st = HIKF_OK;
+    int32_t done = 0;
+    for (; done < count && st == HIKF_OK; ++done)
+        st = hikf_step(filters[done], y_dev[done], x_out_dev ? x_out_dev[done] : nullptr,
+                       var_out_dev ? var_out_dev[done] : nullptr, pool->s[done % kPool]);
+    for (int k = 0; e == hipSuccess && k < used; ++k) {
+        e = hipEventRecord(pool->join[k], pool->s[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, pool->join[k], 0);
+    }
+    for (int32_t i = 0; i < done; ++i) filters[i]->last_stream = s;
+    if (e != hipSuccess) return set_err(filters[0], HIKF_E_DEVICE, "batch join", e);
+    return st;
 }
 
 hikf_status hikf_query(hikf_filter *f, hikf_stats *out) {
