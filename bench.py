@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--riccati", type=int, default=0,
                     help="gather G = H C_prior only every N steps and carry it between "
                          "(exact p-space recursion); 0 = every step")
+    ap.add_argument("--w", default="dense", choices=["dense", "sparse"],
+                    help="FMM source side: dense W = H^T, or the nonzeros of H bucketed by leaf")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="approximate seconds of CPU work for the oracle sample")
@@ -285,7 +287,8 @@ def main():
     pr, keep = F.problem_from_csr(dim, n, rowptr, col, val, np.full(p, w["r_var"]),
                                   theta=w["theta"], ell=w["ell"], gamma=w["gamma"],
                                   prior=w["prior"])
-    op = F.make_options(n_c, a.precision, False, timing=True, riccati=a.riccati)
+    op = F.make_options(n_c, a.precision, False, timing=True, riccati=a.riccati,
+                        sparse=a.w == "sparse")
     info = F.plan(pr, op)
     resident = torch.empty(int(info.resident_bytes), dtype=torch.uint8, device="cuda")
     scratch = torch.empty(int(info.scratch_bytes), dtype=torch.uint8, device="cuda")
@@ -396,7 +399,7 @@ def main():
         "config": {"workload": a.workload, "m": m, "p": p, "dim": dim, "n_c": n_c,
                    "kernel": f"theta*exp(-(r/{w['ell']})^{w['gamma']:g})",
                    "fmm_dtype": a.precision, "step_dtype": "f64",
-                   "assim_steps_per_job": K, "gather_every": a.riccati or 1,
+                   "assim_steps_per_job": K, "gather_every": a.riccati or 1, "fmm_w": a.w,
                    "parallelism": "none (1 GPU)"},
         "warm_steps_per_s": round(1e3 / float(np.mean(lat_ms)), 2),
         "step_latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),

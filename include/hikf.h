@@ -132,6 +132,13 @@ typedef struct hikf_options {
                                 first copied into the resident region).
                                 Ignored when timing = 1.  Results are bitwise
                                 those of the launched kernels.                */
+    int32_t sparse;          /* 1: P2M and the near field read only the
+                                nonzeros of W = H^T, bucketed by leaf at init
+                                (no dense m x p W is formed; the scratch
+                                shrinks by m p words).  Same H^2 product up to
+                                the order of rounding; the near field is then
+                                summed in FP32 (FP64 in HIKF_FMM_F64) in every
+                                precision mode.  Ignored when direct = 1.     */
 } hikf_options;
 
 /* Phases timed when hikf_options.timing = 1 (indices of hikf_stats.time_ms). */

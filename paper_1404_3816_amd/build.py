@@ -21,17 +21,34 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
+    """Compile every source (in parallel, one object each) and link the library."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    srcs = [os.path.join(HERE, "csrc", s) for s in SOURCES]
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+    cflags = [f for f in FLAGS if f != "-shared"]
+    jobs = []
+    for src in SOURCES:
+        obj = os.path.join(objdir, src.replace(".hip", ".o"))
+        cmd = [hipcc, *cflags, *inc, "-c", os.path.join(HERE, "csrc", src), "-o", obj]
+        jobs.append((obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                                           text=True)))
+    failed = False
+    for obj, proc in jobs:
+        out, err = proc.communicate()
+        if proc.returncode != 0:
+            failed = True
+            sys.stderr.write(out + err)
+        elif verbose:
+            sys.stderr.write(err)
+    if failed:
+        raise RuntimeError("hipcc failed building libhikf.so")
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *FLAGS, "-I", os.path.join(ROOT, "include"),
-           "-I", os.path.join(HERE, "csrc"), *srcs, "-o", tmp]
-    res = subprocess.run(cmd, capture_output=True, text=True)
+    res = subprocess.run([hipcc, *FLAGS, *[o for o, _ in jobs], "-o", tmp],
+                         capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libhikf.so")
-    if verbose:
-        sys.stderr.write(res.stderr)
+        raise RuntimeError("hipcc failed linking libhikf.so")
     os.replace(tmp, LIB)
     return LIB
 

@@ -48,7 +48,18 @@ Layout make_layout(const Geometry &g) {
     L.resident_bytes = off;
 
     off = 0;
-    L.W = take(size_t(g.mpad) * p * tq);
+    if (g.sparse) {
+        // counting sort of the nonzeros by leaf: cursors, offsets, placed
+        // nonzero indices, then per bucket (ray * 64 + point, value)
+        const size_t leaves = size_t(g.boxes(g.depth)), nz = size_t(g.nnz);
+        L.bcur = take(leaves * 4);
+        L.boff = take((leaves + 1) * 4);
+        L.btmp = take(nz * 4);
+        L.bkey = take(nz * 4);
+        L.bval = take(nz * tq);
+    } else {
+        L.W = take(size_t(g.mpad) * p * tq);
+    }
     L.knear = take(size_t(g.dim == 2 ? 9 : 27) * kLeafPts * kLeafPts * tq);
     if (g.far) {
         const size_t r = size_t(g.r);
@@ -67,7 +78,7 @@ Layout make_layout(const Geometry &g) {
         // box as [column][node], M2L tables as [target node][source node],
         // node counts padded to kr32 = 32 ceil(r / 32)
         const size_t leaves = size_t(g.boxes(g.depth));
-        L.Wsplit = take(2 * leaves * p * kLeafPts * 2);
+        if (!g.sparse) L.Wsplit = take(2 * leaves * p * kLeafPts * 2);
         if (g.far) {
             const size_t kr = size_t(g.kr32()), rt = size_t(g.r + 15) / 16 * 16;
             L.Tsplit = take(2 * size_t(g.depth - 1) * g.noff() * rt * kr * 2);
@@ -212,6 +223,8 @@ hikf_status build_geometry(const hikf_problem *pr, const hikf_options *op, Geome
     if (g->r > hikf::kMaxR) return HIKF_E_UNSUPPORTED;
     g->direct = op->direct != 0;
     g->far = !g->direct && D >= 2;
+    g->sparse = op->sparse != 0 && !g->direct;
+    if (g->sparse && pr->nnz >= (int64_t(1) << 31)) return HIKF_E_UNSUPPORTED;   // int bucket slots
     g->fmm_prec = op->fmm_precision;
     g->prior = pr->prior_kind;
     if (op->history < 0 || op->history > 1000000) return HIKF_E_INVALID;
@@ -244,6 +257,7 @@ QueryPlan query_plan(const Geometry &g0) {
     q.g.pp = 32;
     q.g.nnz = 0;
     q.g.history = 0;
+    q.g.sparse = false;           // Q v runs on a dense first column
     if (q.g.fmm_prec == HIKF_FMM_BF16X3 || q.g.fmm_prec == HIKF_FMM_BF16) q.g.fmm_prec = HIKF_FMM_F32;
     q.lay = hikf::make_layout(q.g);
     const size_t tq = q.g.fmm_prec == HIKF_FMM_F64 ? 8 : 4;

@@ -188,6 +188,135 @@ __global__ void k_scatter_w(int64_t nnz, int p, int64_t m, int dim, int n, int n
     W[(x + int64_t(npad) * (y + int64_t(npad) * z)) * p + lo] = (T)val[e];
 }
 
+// ---------------------------------------------------------------- sparse W
+// W = H^T has nnz(H) nonzeros: a ray crosses O(N) of the m cells.  In the
+// sparse mode the nonzeros are bucketed by the leaf of their cell (a counting
+// sort), and each bucket is then put in nonzero order, so that every sum
+// over a bucket runs in the same order whatever order the atomic placement
+// took.  A bucket entry is (ray * 64 + point of the leaf, value); nonzero
+// order is ray-major, so the entries of one ray within a leaf are adjacent.
+
+// ray of nonzero e, or -1 if e lies in no row of the CSR arrays or its cell
+// is out of range; *leaf and *pt receive the cell's leaf and point index
+__device__ __forceinline__ int sparse_entry(int64_t e, int p, int64_t m, int dim, int n, int ls,
+                                            int depth, const int64_t *rowptr, const int32_t *col,
+                                            int64_t *leaf, int *pt) {
+    int lo = 0, hi = p - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (rowptr[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    if (rowptr[lo] > e || rowptr[lo + 1] <= e) return -1;
+    const int64_t c = col[e];
+    if (c < 0 || c >= m) return -1;
+    const int64_t x = c % n, y = (c / n) % n, z = dim == 3 ? c / (int64_t(n) * n) : 0;
+    const int64_t nb = int64_t(1) << depth;
+    *leaf = x / ls + nb * (y / ls + nb * (z / ls));
+    *pt = int(x % ls + ls * (y % ls) + ls * ls * (z % ls));
+    return lo;
+}
+
+__global__ void k_sp_count(int64_t nnz, int p, int64_t m, int dim, int n, int ls, int depth,
+                           const int64_t *rowptr, const int32_t *col, int *cnt) {
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    int64_t leaf;
+    int pt;
+    if (sparse_entry(e, p, m, dim, n, ls, depth, rowptr, col, &leaf, &pt) >= 0)
+        atomicAdd(cnt + leaf, 1);
+}
+
+// exclusive prefix sum of the bucket sizes (one workgroup of 1024 threads):
+// off[0..nl] = offsets, cnt[0..nl) = the same offsets as placement cursors
+__global__ void __launch_bounds__(1024) k_sp_scan(int64_t nl, int *cnt, int *off) {
+    __shared__ int sv[1024];
+    __shared__ int carry;
+    const int t = threadIdx.x;
+    if (t == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nl; base += 1024) {
+        const int v = base + t < nl ? cnt[base + t] : 0;
+        sv[t] = v;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {
+            const int u = t >= d ? sv[t - d] : 0;
+            __syncthreads();
+            sv[t] += u;
+            __syncthreads();
+        }
+        const int excl = carry + sv[t] - v;
+        if (base + t < nl) { off[base + t] = excl; cnt[base + t] = excl; }
+        __syncthreads();
+        if (t == 1023) carry += sv[1023];
+        __syncthreads();
+    }
+    if (t == 0) off[nl] = carry;
+}
+
+__global__ void k_sp_fill(int64_t nnz, int p, int64_t m, int dim, int n, int ls, int depth,
+                          const int64_t *rowptr, const int32_t *col, int *cur, int *tmp) {
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    int64_t leaf;
+    int pt;
+    if (sparse_entry(e, p, m, dim, n, ls, depth, rowptr, col, &leaf, &pt) >= 0)
+        tmp[atomicAdd(cur + leaf, 1)] = int(e);
+}
+
+// one workgroup per leaf: entry of rank k (by nonzero index) to slot k
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_sp_order(int p, int64_t m, int dim, int n, int ls, int depth, const int64_t *rowptr,
+           const int32_t *col, const double *val, const int *off, const int *tmp, int *key, T *bv) {
+    const int64_t L = blockIdx.x;
+    const int o0 = off[L], cnt = off[L + 1] - o0;
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        const int e = tmp[o0 + i];
+        int rank = 0;
+        for (int j = 0; j < cnt; ++j) rank += tmp[o0 + j] < e;
+        int64_t leaf;
+        int pt;
+        const int ray = sparse_entry(e, p, m, dim, n, ls, depth, rowptr, col, &leaf, &pt);
+        key[o0 + rank] = ray * kLeafPts + pt;
+        bv[o0 + rank] = (T)val[e];
+    }
+}
+
+// P2M from the buckets: one workgroup per leaf; M_B[k][a] sums the entries
+// of ray a (one run of the bucket) times S_leaf[k][point].  Buckets of up to
+// kCap entries are staged in LDS first.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_p2m_sparse(int r, int p, const int *off, const int *key, const T *bv, const T *Sleaf, T *Mleaf) {
+    constexpr int kCap = 1024;
+    __shared__ T sS[kMaxR * kLeafPts];
+    __shared__ int rs[kMaxP], re[kMaxP];
+    __shared__ int sk[kCap];
+    __shared__ T sv[kCap];
+    const int64_t B = blockIdx.x;
+    const int o0 = off[B], cnt = off[B + 1] - o0;
+    const bool staged = cnt <= kCap;
+    for (int a = threadIdx.x; a < p; a += blockDim.x) { rs[a] = 0; re[a] = 0; }
+    for (int idx = threadIdx.x; idx < r * kLeafPts; idx += blockDim.x) sS[idx] = Sleaf[idx];
+    if (staged)
+        for (int i = threadIdx.x; i < cnt; i += blockDim.x) { sk[i] = key[o0 + i]; sv[i] = bv[o0 + i]; }
+    __syncthreads();
+    const int *ek = staged ? sk : key + o0;
+    const T *ev = staged ? sv : bv + o0;
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        const int a = ek[i] / kLeafPts;
+        if (i == 0 || ek[i - 1] / kLeafPts != a) rs[a] = i;
+        if (i == cnt - 1 || ek[i + 1] / kLeafPts != a) re[a] = i + 1;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < r * p; idx += blockDim.x) {
+        const int k = idx / p, a = idx % p;
+        T acc = (T)0;
+        for (int i = rs[a]; i < re[a]; ++i) acc += sS[k * kLeafPts + ek[i] % kLeafPts] * ev[i];
+        Mleaf[(B * r + k) * p + a] = acc;
+    }
+}
+
 // ---------------------------------------------------------------- P2M
 // Panels are staged in LDS with 16-byte loads (rows of PT values are
 // contiguous and 16-byte aligned: p and PT are multiples of 16), and so are
@@ -529,6 +658,122 @@ k_l2p_p2p_mma(int dim, int n, int npad, int ls, int depth, int r, int rpad, int 
             const int i = 16 * wave + Mma<T>::row(q, rr);
             const int64_t g = leaf_point_real(b, i, dim, n, ls);
             if (g >= 0) CQ[g * p + c0 + c] = acc[t][rr];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- L2P + P2P (sparse W)
+// One workgroup per (target leaf B, PT-column tile).  Near field: for every
+// bucket entry (ray a, point j, value v) of the 3^dim neighbour leaves with a
+// in the tile, all 64 targets add K(x_i - x_j) v to their column a of an LDS
+// tile; wave w takes the columns a = w (mod 4), so every tile element is
+// updated by one lane, in bucket order.  A wave reads a bucket 64 entries at
+// a time (one entry per lane), keeps its own by a ballot, and walks them with
+// the kernel value generated from the integer cell offset.  The far field
+// adds S_leaf^T L_B on MFMA as in the dense kernel, and the two meet in the
+// epilogue.
+template <typename T, int PT>
+__global__ void __launch_bounds__(kBlock)
+k_l2p_p2p_sparse(int dim, int n, int ls, int depth, int r, int rpad, int p, int far,
+                 KernelParams kp, T h2, const int *off, const int *key, const T *bv,
+                 const T *Sleaf, const T *Lleaf, T *CQ) {
+    typedef typename Mma<T>::v4 v4;
+    constexpr int NTI = PT / 16;
+    constexpr int NFP = kLeafPts + 1;                  // pitch of the near-field tile
+    constexpr int WP = PT + Mma<T>::pad;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int KP = rpad + 4;
+    T *nf = reinterpret_cast<T *>(smem_raw);           // [PT][NFP]
+    T *sK = nf + PT * NFP;                             // [64][KP]   S_leaf^T
+    T *sW = sK + kLeafPts * KP;                        // [rpad][WP] L_B tile
+    const int64_t B = blockIdx.x;
+    const int c0 = blockIdx.y * PT;
+    const int ncols = min(PT, p - c0);
+    const int nb = 1 << depth;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    int b[3];
+    box_coords(B, nb, dim, b);
+    for (int idx = tid; idx < PT * NFP; idx += kBlock) nf[idx] = (T)0;
+    const int nsl = dim == 2 ? 9 : 27;
+    // lane t < nsl: bucket range of the neighbour leaf in slot t (empty if
+    // that leaf lies outside the tree)
+    int my_lo = 0, my_hi = 0;
+    if (lane < nsl) {
+        const int a[3] = {b[0] + lane % 3 - 1, b[1] + (lane / 3) % 3 - 1,
+                          dim == 3 ? b[2] + lane / 9 - 1 : 0};
+        if (a[0] >= 0 && a[0] < nb && a[1] >= 0 && a[1] < nb && (dim == 2 || (a[2] >= 0 && a[2] < nb))) {
+            const int64_t A = box_index(a, nb, dim);
+            my_lo = off[A];
+            my_hi = off[A + 1];
+        }
+    }
+    int li[3];
+    leaf_local(lane, dim, li);                         // this lane's target point
+    __syncthreads();                                   // tile cleared
+    for (int sl = 0; sl < nsl; ++sl) {
+        const int lo = __builtin_amdgcn_readlane(my_lo, sl), hi = __builtin_amdgcn_readlane(my_hi, sl);
+        const int o[3] = {sl % 3 - 1, (sl / 3) % 3 - 1, sl / 9 - 1};
+        for (int base = lo; base < hi; base += 64) {
+            const int e = base + lane;
+            int kk = 0;
+            T v = (T)0;
+            bool mine = false;
+            if (e < hi) {
+                kk = key[e];
+                v = bv[e];
+                const int c = kk / kLeafPts - c0;
+                mine = c >= 0 && c < ncols && (c & 3) == wave;
+            }
+            uint64_t mask = __ballot(mine);
+            while (mask) {
+                const int src = __builtin_ctzll(mask);
+                mask &= mask - 1;
+                const int ks = __builtin_amdgcn_readlane(kk, src);
+                const T vs = __shfl(v, src);
+                int lj[3];
+                leaf_local(ks % kLeafPts, dim, lj);
+                int dsq = 0;
+                for (int ax = 0; ax < dim; ++ax) {
+                    const int d = o[ax] * ls + lj[ax] - li[ax];
+                    dsq += d * d;
+                }
+                nf[(ks / kLeafPts - c0) * NFP + lane] += kernel_from_r2<T>((T)dsq * h2, kp) * vs;
+            }
+        }
+    }
+    v4 acc[NTI];
+#pragma unroll
+    for (int t = 0; t < NTI; ++t) acc[t] = v4{0, 0, 0, 0};
+    const int lr = lane & 15, q = lane >> 4;
+    if (far) {
+        for (int idx = tid; idx < kLeafPts * rpad; idx += kBlock) {
+            const int i = idx / rpad, k = idx % rpad;
+            sK[i * KP + k] = k < r ? Sleaf[k * kLeafPts + i] : (T)0;
+        }
+        for (int idx = tid; idx < rpad * PT; idx += kBlock) {
+            const int k = idx / PT, c = idx % PT;
+            sW[k * WP + c] = (k < r && c < ncols) ? Lleaf[(B * r + k) * p + c0 + c] : (T)0;
+        }
+    }
+    __syncthreads();                                   // near-field tile and far operands ready
+    if (far) {
+        const T *arow = sK + (16 * wave + lr) * KP + q;
+        const T *bcol = sW + q * WP + lr;
+        for (int k0 = 0; k0 < rpad; k0 += 4) {
+            const T av = arow[k0];
+#pragma unroll
+            for (int t = 0; t < NTI; ++t) acc[t] = Mma<T>::op(av, bcol[k0 * WP + 16 * t], acc[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NTI; ++t) {
+        const int c = 16 * t + lr;
+        if (c >= ncols) continue;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int i = 16 * wave + Mma<T>::row(q, rr);
+            const int64_t g = leaf_point_real(b, i, dim, n, ls);
+            if (g >= 0) CQ[g * p + c0 + c] = acc[t][rr] + nf[c * NFP + i];
         }
     }
 }
@@ -1096,16 +1341,41 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
     const int64_t *rowptr = res ? reinterpret_cast<const int64_t *>(res + lay.rowptr) : nullptr;
     const int32_t *col = res ? reinterpret_cast<const int32_t *>(res + lay.col) : nullptr;
     const double *val = res ? reinterpret_cast<const double *>(res + lay.val) : nullptr;
+    const bool sparse = g.sparse && !vdense;
+    const int64_t leaves = g.boxes(D);
+    int *bcur = sparse ? reinterpret_cast<int *>(scr + lay.bcur) : nullptr;
+    int *boff = sparse ? reinterpret_cast<int *>(scr + lay.boff) : nullptr;
+    int *bkey = sparse ? reinterpret_cast<int *>(scr + lay.bkey) : nullptr;
+    T *bval = sparse ? reinterpret_cast<T *>(scr + lay.bval) : nullptr;
     tbegin(tm, HIKF_PHASE_INIT, s);
-    hipError_t e = hipMemsetAsync(W, 0, size_t(g.mpad) * p * sizeof(T), s);
-    if (e != hipSuccess) return e;
-    if (vdense) {
-        hipLaunchKernelGGL(k_dense_w<T>, dim3(unsigned(std::min<int64_t>((m + 255) / 256, 65536))),
-                           dim3(256), 0, s, m, dim, g.n, g.npad, p, vdense, W);
-    } else if (g.nnz > 0) {
-        int64_t blocks = (g.nnz + kBlock - 1) / kBlock;
-        hipLaunchKernelGGL(k_scatter_w<T>, dim3(unsigned(blocks)), dim3(kBlock), 0, s,
-                           g.nnz, p, m, dim, g.n, g.npad, rowptr, col, val, W);
+    hipError_t e = hipSuccess;
+    if (sparse) {
+        // bucket the nonzeros of H by leaf (no dense W)
+        int *btmp = reinterpret_cast<int *>(scr + lay.btmp);
+        e = hipMemsetAsync(bcur, 0, size_t(leaves) * sizeof(int), s);
+        if (e != hipSuccess) return e;
+        const unsigned nblk = unsigned(std::max<int64_t>(1, (g.nnz + kBlock - 1) / kBlock));
+        if (g.nnz > 0)
+            hipLaunchKernelGGL(k_sp_count, dim3(nblk), dim3(kBlock), 0, s, g.nnz, p, m, dim, g.n,
+                               g.ls, D, rowptr, col, bcur);
+        hipLaunchKernelGGL(k_sp_scan, dim3(1), dim3(1024), 0, s, leaves, bcur, boff);
+        if (g.nnz > 0) {
+            hipLaunchKernelGGL(k_sp_fill, dim3(nblk), dim3(kBlock), 0, s, g.nnz, p, m, dim, g.n,
+                               g.ls, D, rowptr, col, bcur, btmp);
+            hipLaunchKernelGGL(k_sp_order<T>, dim3(unsigned(leaves)), dim3(kBlock), 0, s, p, m, dim,
+                               g.n, g.ls, D, rowptr, col, val, boff, btmp, bkey, bval);
+        }
+    } else {
+        e = hipMemsetAsync(W, 0, size_t(g.mpad) * p * sizeof(T), s);
+        if (e != hipSuccess) return e;
+        if (vdense) {
+            hipLaunchKernelGGL(k_dense_w<T>, dim3(unsigned(std::min<int64_t>((m + 255) / 256, 65536))),
+                               dim3(256), 0, s, m, dim, g.n, g.npad, p, vdense, W);
+        } else if (g.nnz > 0) {
+            int64_t blocks = (g.nnz + kBlock - 1) / kBlock;
+            hipLaunchKernelGGL(k_scatter_w<T>, dim3(unsigned(blocks)), dim3(kBlock), 0, s,
+                               g.nnz, p, m, dim, g.n, g.npad, rowptr, col, val, W);
+        }
     }
     tend(tm, HIKF_PHASE_INIT, s);
     T *Sleaf = reinterpret_cast<T *>(scr + lay.sleaf);
@@ -1131,9 +1401,13 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
         // P2M
         tbegin(tm, HIKF_PHASE_P2M, s);
         int PT = min(64, p);
-        hipLaunchKernelGGL(k_p2m<T>, dim3(unsigned(g.boxes(D)), (p + PT - 1) / PT), dim3(kBlock),
-                           (kLeafPts * PT + r * kLeafPts) * sizeof(T), s, dim, g.npad, g.ls, D, r,
-                           p, PT, W, Sleaf, Mlev(D));
+        if (sparse)
+            hipLaunchKernelGGL(k_p2m_sparse<T>, dim3(unsigned(leaves)), dim3(kBlock), 0, s, r, p,
+                               boff, bkey, bval, Sleaf, Mlev(D));
+        else
+            hipLaunchKernelGGL(k_p2m<T>, dim3(unsigned(g.boxes(D)), (p + PT - 1) / PT), dim3(kBlock),
+                               (kLeafPts * PT + r * kLeafPts) * sizeof(T), s, dim, g.npad, g.ls, D, r,
+                               p, PT, W, Sleaf, Mlev(D));
         tend(tm, HIKF_PHASE_P2M, s);
         // M2M
         tbegin(tm, HIKF_PHASE_M2M, s);
@@ -1210,18 +1484,32 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
     // near-field kernel blocks by leaf offset (all neighbours are within one
     // leaf unless the exact all-pairs sum is requested)
     T *Knear = nullptr;
-    if (!g.direct) {
+    if (!g.direct && !sparse) {
         Knear = reinterpret_cast<T *>(scr + lay.knear);
         const int tot = (dim == 2 ? 9 : 27) * kLeafPts * kLeafPts;
         hipLaunchKernelGGL(k_ops_near<T>, dim3((tot + 255) / 256), dim3(256), 0, s, dim, g.ls, g.kp,
                            1.0 / g.n, Knear);
+    }
+    if (sparse) {
+        constexpr int PPT = sizeof(T) == 4 ? 64 : 32;
+        const int rpad = (r + 3) / 4 * 4;
+        const size_t lds = (size_t(PPT) * (kLeafPts + 1) + size_t(kLeafPts) * (rpad + 4) +
+                            size_t(rpad) * (PPT + Mma<T>::pad)) * sizeof(T);
+        e = allow_lds(k_l2p_p2p_sparse<T, PPT>, lds);
+        if (e != hipSuccess) return e;
+        tbegin(tm, HIKF_PHASE_P2P, s);
+        const double h = 1.0 / g.n;
+        hipLaunchKernelGGL((k_l2p_p2p_sparse<T, PPT>), dim3(unsigned(leaves), (p + PPT - 1) / PPT),
+                           dim3(kBlock), lds, s, dim, g.n, g.ls, D, r, rpad, p, g.far ? 1 : 0,
+                           g.kp, (T)(h * h), boff, bkey, bval, Sleaf, g.far ? Llev(D) : nullptr, CQ);
+        tend(tm, HIKF_PHASE_P2P, s);
+        return hipGetLastError();
     }
     if constexpr (sizeof(T) == 4) {
         if (bf16) {
             const int rpad = (r + 3) / 4 * 4;
             const int rad = g.direct ? (1 << D) : 1;
             const double h = 1.0 / g.n;
-            const int64_t leaves = g.boxes(D);
             __bf16 *Wh = reinterpret_cast<__bf16 *>(scr + lay.Wsplit);
             __bf16 *Wl = Wh + leaves * p * kLeafPts;
             tbegin(tm, HIKF_PHASE_P2P, s);

@@ -68,6 +68,7 @@ struct Geometry {
     int64_t nnz = 0;
     bool direct = false;
     bool far = false;             // far field present (depth >= 2 and not direct)
+    bool sparse = false;          // P2M / near field from the leaf-bucketed nonzeros of H
     int fmm_prec = HIKF_FMM_F32;
     int prior = HIKF_PRIOR_KERNEL;
     int history = 0;              // steps kept for covariance queries
@@ -95,6 +96,7 @@ struct Layout {
     size_t ML_level[24];                      // per-level offset of M (L follows after all M)
     size_t L_base;
     size_t Wsplit, Tsplit, MS_level[24];      // BF16 hi/lo operands (BF16 modes only)
+    size_t bcur, boff, btmp, bkey, bval;      // nonzeros of H by leaf (sparse mode only)
     size_t scratch_bytes;
 };
 

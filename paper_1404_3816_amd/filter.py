@@ -52,7 +52,7 @@ def problem_from_csr(dim, n, rowptr, col, val, r_diag, family="powexp", theta=1.
 
 
 def make_options(n_c=4, precision="f32", direct=False, timing=False, graph=False, riccati=0,
-                 history=0):
+                 history=0, sparse=False):
     op = H.hikf_options()
     op.n_c = int(n_c)
     op.fmm_precision = PRECISIONS[precision]
@@ -61,6 +61,7 @@ def make_options(n_c=4, precision="f32", direct=False, timing=False, graph=False
     op.graph = 1 if graph else 0
     op.riccati = int(riccati)
     op.history = int(history)
+    op.sparse = 1 if sparse else 0
     return op
 
 

@@ -55,7 +55,8 @@ class hikf_problem(ctypes.Structure):
 
 class hikf_options(ctypes.Structure):
     _fields_ = [("n_c", c_i32), ("fmm_precision", c_i32), ("direct", c_i32),
-                ("timing", c_i32), ("riccati", c_i32), ("history", c_i32), ("graph", c_i32)]
+                ("timing", c_i32), ("riccati", c_i32), ("history", c_i32), ("graph", c_i32),
+                ("sparse", c_i32)]
 
 
 class hikf_plan_info(ctypes.Structure):

@@ -76,17 +76,17 @@ class Case:
         return xs, vs
 
     # ---- GPU side
-    def gpu_filter(self, n_c=4, precision="f32", direct=False):
+    def gpu_filter(self, n_c=4, precision="f32", direct=False, **options):
         from paper_1404_3816_amd import filter as F
         pr, keep = F.problem_from_csr(self.dim, self.n, self.rowptr, self.col, self.val,
                                       self.r_diag, prior=self.prior, alpha=self.alpha,
                                       x0=self.x0, **self.kparams())
-        return F.HikfFilter(pr, F.make_options(n_c, precision, direct), keep)
+        return F.HikfFilter(pr, F.make_options(n_c, precision, direct, **options), keep)
 
-    def gpu_run(self, n_c=4, precision="f32", direct=False, steps=None):
+    def gpu_run(self, n_c=4, precision="f32", direct=False, steps=None, **options):
         import torch
         steps = self.steps if steps is None else steps
-        f = self.gpu_filter(n_c, precision, direct)
+        f = self.gpu_filter(n_c, precision, direct, **options)
         cq = f.export_cq().cpu().numpy()
         xs, vs = [], []
         ydev = torch.as_tensor(self.ys, dtype=torch.float64, device="cuda")

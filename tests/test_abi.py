@@ -46,10 +46,10 @@ def _problem(dim=2, n=32, p=16, nnz=100, **kw):
     return pr
 
 
-def _plan(pr, n_c=4, precision=0, direct=0):
+def _plan(pr, n_c=4, precision=0, direct=0, sparse=0):
     from paper_1404_3816_amd import hikf as H
     op = H.hikf_options()
-    op.n_c, op.fmm_precision, op.direct = n_c, precision, direct
+    op.n_c, op.fmm_precision, op.direct, op.sparse = n_c, precision, direct, sparse
     info = H.hikf_plan_info()
     st = H.hikf_plan(ctypes.byref(pr), ctypes.byref(op), ctypes.byref(info))
     return st, info
@@ -138,6 +138,27 @@ def test_plan_bf16_modes_add_split_operands():
     assert i3.scratch_bytes == i1.scratch_bytes > i32.scratch_bytes
     # W split: 2 copies x 2 bytes per entry of the m x p matrix
     assert i3.scratch_bytes - i32.scratch_bytes >= 2 * 2 * 32 ** 3 * 64
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_plan_sparse_mode_drops_dense_w(precision):
+    # the sparse mode keeps the nonzeros by leaf (a few words per nonzero and
+    # per leaf) instead of the dense W over the tree's cells (and, in the BF16
+    # modes, its hi / lo copies); the resident state is the same
+    from paper_1404_3816_amd import hikf as H
+    pr = _problem(dim=2, n=1000, p=256)
+    st_d, i_d = _plan(pr, precision=precision)
+    st_s, i_s = _plan(pr, precision=precision, sparse=1)
+    assert st_d == st_s == H.HIKF_OK
+    assert i_s.resident_bytes == i_d.resident_bytes
+    word = 8 if precision == H.HIKF_FMM_F64 else 4
+    dense_w = 1024 * 1024 * 256 * word + (1024 * 1024 * 256 * 4 if precision == 2 else 0)
+    bucket = 128 * 128 * 8 + pr.nnz * (8 + word) + 4096
+    assert i_d.scratch_bytes - i_s.scratch_bytes >= dense_w - bucket
+    # direct mode has no tree lists to bucket by: the option is ignored
+    st_x, i_x = _plan(_problem(dim=2, n=64, p=32), direct=1, sparse=1)
+    st_y, i_y = _plan(_problem(dim=2, n=64, p=32), direct=1)
+    assert st_x == st_y == H.HIKF_OK and i_x.scratch_bytes == i_y.scratch_bytes
 
 
 def test_plan_query_bytes_only_with_history():
