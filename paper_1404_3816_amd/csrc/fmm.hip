@@ -318,28 +318,9 @@ k_p2m_sparse(int r, int p, const int *off, const int *key, const T *bv, const T 
 }
 
 // ---------------------------------------------------------------- P2M
-// Panels are staged in LDS with 16-byte loads (rows of PT values are
-// contiguous and 16-byte aligned: p and PT are multiples of 16), and so are
-// the interpolation operators, which every output of the workgroup reads.
-template <typename T>
-__device__ __forceinline__ void stage_rows(T *dst, int dpitch, const T *src, int64_t spitch,
-                                           int rows, int PT, int ncols) {
-    constexpr int VW = 16 / sizeof(T);
-    typedef T tv __attribute__((ext_vector_type(VW)));
-    const int chunks = PT / VW;
-    for (int idx = threadIdx.x; idx < rows * chunks; idx += blockDim.x) {
-        const int k = idx / chunks, ch = idx % chunks;
-        tv v;
-        if (VW * ch < ncols) {
-            v = *reinterpret_cast<const tv *>(src + k * spitch + VW * ch);
-        } else {
-#pragma unroll
-            for (int e = 0; e < VW; ++e) v[e] = (T)0;
-        }
-        *reinterpret_cast<tv *>(dst + k * dpitch + VW * ch) = v;
-    }
-}
-
+// The W panel and the interpolation operator, which every output of the
+// workgroup reads, are staged in LDS (W with 16-byte loads: rows of PT
+// values are contiguous and 16-byte aligned, p and PT being multiples of 16).
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_p2m(int dim, int n, int ls, int depth, int r, int p, int PT, const T *W,
@@ -380,51 +361,6 @@ k_p2m(int dim, int n, int ls, int depth, int r, int p, int PT, const T *W,
     }
 }
 
-// ---------------------------------------------------------------- M2M
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
-k_m2m(int dim, int r, int p, int lev, int PT, const T *Mchild, const T *Schild, T *Mpar) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *sM = reinterpret_cast<T *>(smem_raw);           // [nch][r][PT]
-    const int64_t P = blockIdx.x;
-    const int c0 = blockIdx.y * PT;
-    const int ncols = min(PT, p - c0);
-    const int nb = 1 << lev, nbc = nb << 1, nch = 1 << dim;
-    T *sS = sM + nch * r * PT;                          // [r][r] of one child
-    int pc[3];
-    box_coords(P, nb, dim, pc);
-    for (int ch = 0; ch < nch; ++ch) {
-        int cc[3] = {2 * pc[0] + (ch & 1), 2 * pc[1] + ((ch >> 1) & 1), 2 * pc[2] + ((ch >> 2) & 1)};
-        const int64_t Bc = box_index(cc, nbc, dim);
-        stage_rows(sM + ch * r * PT, PT, Mchild + Bc * r * p + c0, p, r, PT, ncols);
-    }
-    // outputs (k, c) per thread, accumulated over the children in order
-    T acc[4] = {(T)0, (T)0, (T)0, (T)0};
-    for (int ch = 0; ch < nch; ++ch) {
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < r * r; idx += blockDim.x) sS[idx] = Schild[ch * r * r + idx];
-        __syncthreads();
-        const T *m = sM + ch * r * PT;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int idx = threadIdx.x + u * blockDim.x;
-            if (idx >= r * PT) break;
-            const int k = idx / PT, c = idx % PT;
-            const T *srow = sS + k * r;
-            T a = (T)0;
-            for (int kq = 0; kq < r; ++kq) a += srow[kq] * m[kq * PT + c];
-            acc[u] += a;
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int idx = threadIdx.x + u * blockDim.x;
-        if (idx >= r * PT) break;
-        const int k = idx / PT, c = idx % PT;
-        if (c < ncols) Mpar[(P * r + k) * p + c0 + c] = acc[u];
-    }
-}
-
 // ---------------------------------------------------------------- M2L
 // Interaction list of B at level l: boxes A = B + o with max|o| >= 2 whose
 // parent is adjacent to (or equal to) B's parent.
@@ -438,34 +374,6 @@ __device__ __forceinline__ bool il_member(const int *b, const int *o, int nb, in
         omax = max(omax, abs(o[ax]));
     }
     return omax >= 2;
-}
-
-// ---------------------------------------------------------------- L2L
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
-k_l2l(int dim, int r, int p, int lev, int PT, const T *Lpar, const T *Schild, T *Lchild) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *sL = reinterpret_cast<T *>(smem_raw);           // [r][PT]
-    T *sS = sL + r * PT;                               // [r][r] of this child
-    const int64_t Bc = blockIdx.x;                     // child at level lev + 1
-    const int c0 = blockIdx.y * PT;
-    const int ncols = min(PT, p - c0);
-    const int nbc = 2 << lev, nb = 1 << lev;
-    int cc[3];
-    box_coords(Bc, nbc, dim, cc);
-    int pc[3] = {cc[0] >> 1, cc[1] >> 1, cc[2] >> 1};
-    int ch = (cc[0] & 1) | ((cc[1] & 1) << 1) | ((cc[2] & 1) << 2);
-    int64_t P = box_index(pc, nb, dim);
-    stage_rows(sL, PT, Lpar + P * r * p + c0, p, r, PT, ncols);
-    for (int idx = threadIdx.x; idx < r * r; idx += blockDim.x) sS[idx] = Schild[int64_t(ch) * r * r + idx];
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < r * PT; idx += blockDim.x) {
-        int kq = idx / PT, c = idx % PT;
-        if (c >= ncols) continue;
-        T acc = (T)0;
-        for (int k = 0; k < r; ++k) acc += sS[k * r + kq] * sL[k * PT + c];
-        Lchild[(Bc * r + kq) * p + c0 + c] += acc;
-    }
 }
 
 // ---------------------------------------------------------------- MFMA forms
@@ -664,23 +572,26 @@ k_l2p_p2p_mma(int dim, int n, int npad, int ls, int depth, int r, int rpad, int 
 
 // ---------------------------------------------------------------- L2P + P2P (sparse W)
 // One workgroup per (target leaf B, PT-column tile).  Near field: for every
-// bucket entry (ray a, point j, value v) of the 3^dim neighbour leaves with a
-// in the tile, all 64 targets add K(x_i - x_j) v to their column a of an LDS
-// tile; wave w takes the columns a = w (mod 4), so every tile element is
-// updated by one lane, in bucket order.  A wave reads a bucket 64 entries at
-// a time (one entry per lane), keeps its own by a ballot, and walks them with
-// the kernel value generated from the integer cell offset.  The far field
-// adds S_leaf^T L_B on MFMA as in the dense kernel, and the two meet in the
-// epilogue.
-template <typename T, int PT>
+// bucket entry (ray a, point j, value v) of the NSL = 3^dim neighbour leaves
+// with a in the tile, all 64 targets add K(x_i - x_j) v to their column a of
+// an LDS tile; wave w takes the columns a = w (mod 4), so every tile element
+// is updated by one lane, in bucket order.  The far-field operands and the
+// first 64 entries of every neighbour bucket (one per lane) are all loaded up
+// front, so a workgroup waits for memory about twice; a wave then keeps its
+// own entries by a ballot and walks them with the kernel value generated from
+// the integer cell offset.  The far field adds S_leaf^T L_B on MFMA as in the
+// dense kernel, and the two meet in the epilogue.
+template <typename T, int PT, int NSL>
 __global__ void __launch_bounds__(kBlock)
-k_l2p_p2p_sparse(int dim, int n, int ls, int depth, int r, int rpad, int p, int far,
-                 KernelParams kp, T h2, const int *off, const int *key, const T *bv,
-                 const T *Sleaf, const T *Lleaf, T *CQ) {
+k_l2p_p2p_sparse(int n, int ls, int depth, int r, int rpad, int p, int far, KernelParams kp,
+                 T h2, const int *off, const int *key, const T *bv, const T *Sleaf,
+                 const T *Lleaf, T *CQ) {
     typedef typename Mma<T>::v4 v4;
+    constexpr int dim = NSL == 9 ? 2 : 3;
     constexpr int NTI = PT / 16;
     constexpr int NFP = kLeafPts + 1;                  // pitch of the near-field tile
     constexpr int WP = PT + Mma<T>::pad;
+    constexpr int FU = (kLeafPts * kMaxR + kBlock - 1) / kBlock;   // far operand loads per thread
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int KP = rpad + 4;
     T *nf = reinterpret_cast<T *>(smem_raw);           // [PT][NFP]
@@ -693,12 +604,10 @@ k_l2p_p2p_sparse(int dim, int n, int ls, int depth, int r, int rpad, int p, int 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     int b[3];
     box_coords(B, nb, dim, b);
-    for (int idx = tid; idx < PT * NFP; idx += kBlock) nf[idx] = (T)0;
-    const int nsl = dim == 2 ? 9 : 27;
-    // lane t < nsl: bucket range of the neighbour leaf in slot t (empty if
+    // lane t < NSL: bucket range of the neighbour leaf in slot t (empty if
     // that leaf lies outside the tree)
     int my_lo = 0, my_hi = 0;
-    if (lane < nsl) {
+    if (lane < NSL) {
         const int a[3] = {b[0] + lane % 3 - 1, b[1] + (lane / 3) % 3 - 1,
                           dim == 3 ? b[2] + lane / 9 - 1 : 0};
         if (a[0] >= 0 && a[0] < nb && a[1] >= 0 && a[1] < nb && (dim == 2 || (a[2] >= 0 && a[2] < nb))) {
@@ -707,55 +616,81 @@ k_l2p_p2p_sparse(int dim, int n, int ls, int depth, int r, int rpad, int p, int 
             my_hi = off[A + 1];
         }
     }
+    // far operands into registers (in flight while the buckets are read)
+    T kreg[FU], lreg[FU];
+    if (far) {
+#pragma unroll
+        for (int u = 0; u < FU; ++u) {
+            const int idx = tid + kBlock * u;
+            kreg[u] = (T)0;
+            lreg[u] = (T)0;
+            if (idx < kLeafPts * rpad) {
+                const int i = idx / rpad, k = idx % rpad;
+                if (k < r) kreg[u] = Sleaf[k * kLeafPts + i];
+            }
+            if (idx < rpad * PT) {
+                const int k = idx / PT, c = idx % PT;
+                if (k < r && c < ncols) lreg[u] = Lleaf[(B * r + k) * p + c0 + c];
+            }
+        }
+    }
+    for (int idx = tid; idx < PT * NFP; idx += kBlock) nf[idx] = (T)0;
+    // the first 64 entries of every neighbour bucket, one per lane
+    int kk[NSL];
+    T vv[NSL];
+#pragma unroll
+    for (int sl = 0; sl < NSL; ++sl) {
+        const int e = __builtin_amdgcn_readlane(my_lo, sl) + lane;
+        const bool in = e < __builtin_amdgcn_readlane(my_hi, sl);
+        kk[sl] = in ? key[e] : -1;
+        vv[sl] = in ? bv[e] : (T)0;
+    }
+    if (far) {
+#pragma unroll
+        for (int u = 0; u < FU; ++u) {
+            const int idx = tid + kBlock * u;
+            if (idx < kLeafPts * rpad) sK[(idx / rpad) * KP + idx % rpad] = kreg[u];
+            if (idx < rpad * PT) sW[(idx / PT) * WP + idx % PT] = lreg[u];
+        }
+    }
     int li[3];
     leaf_local(lane, dim, li);                         // this lane's target point
-    __syncthreads();                                   // tile cleared
-    for (int sl = 0; sl < nsl; ++sl) {
-        const int lo = __builtin_amdgcn_readlane(my_lo, sl), hi = __builtin_amdgcn_readlane(my_hi, sl);
+    __syncthreads();                                   // tile cleared, far operands staged
+    auto add_entries = [&](int kkl, T vl, int sl) {
+        const int c = kkl / kLeafPts - c0;
+        uint64_t mask = __ballot(kkl >= 0 && c >= 0 && c < ncols && (c & 3) == wave);
         const int o[3] = {sl % 3 - 1, (sl / 3) % 3 - 1, sl / 9 - 1};
-        for (int base = lo; base < hi; base += 64) {
+        while (mask) {
+            const int src = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            const int ks = __builtin_amdgcn_readlane(kkl, src);
+            const T vs = __shfl(vl, src);
+            int lj[3];
+            leaf_local(ks % kLeafPts, dim, lj);
+            int dsq = 0;
+#pragma unroll
+            for (int ax = 0; ax < dim; ++ax) {
+                const int d = o[ax] * ls + lj[ax] - li[ax];
+                dsq += d * d;
+            }
+            nf[(ks / kLeafPts - c0) * NFP + lane] += kernel_from_r2<T>((T)dsq * h2, kp) * vs;
+        }
+    };
+#pragma unroll
+    for (int sl = 0; sl < NSL; ++sl) {
+        add_entries(kk[sl], vv[sl], sl);
+        // buckets of more than 64 entries: the rest, 64 at a time
+        const int lo = __builtin_amdgcn_readlane(my_lo, sl), hi = __builtin_amdgcn_readlane(my_hi, sl);
+        for (int base = lo + 64; base < hi; base += 64) {
             const int e = base + lane;
-            int kk = 0;
-            T v = (T)0;
-            bool mine = false;
-            if (e < hi) {
-                kk = key[e];
-                v = bv[e];
-                const int c = kk / kLeafPts - c0;
-                mine = c >= 0 && c < ncols && (c & 3) == wave;
-            }
-            uint64_t mask = __ballot(mine);
-            while (mask) {
-                const int src = __builtin_ctzll(mask);
-                mask &= mask - 1;
-                const int ks = __builtin_amdgcn_readlane(kk, src);
-                const T vs = __shfl(v, src);
-                int lj[3];
-                leaf_local(ks % kLeafPts, dim, lj);
-                int dsq = 0;
-                for (int ax = 0; ax < dim; ++ax) {
-                    const int d = o[ax] * ls + lj[ax] - li[ax];
-                    dsq += d * d;
-                }
-                nf[(ks / kLeafPts - c0) * NFP + lane] += kernel_from_r2<T>((T)dsq * h2, kp) * vs;
-            }
+            add_entries(e < hi ? key[e] : -1, e < hi ? bv[e] : (T)0, sl);
         }
     }
     v4 acc[NTI];
 #pragma unroll
     for (int t = 0; t < NTI; ++t) acc[t] = v4{0, 0, 0, 0};
     const int lr = lane & 15, q = lane >> 4;
-    if (far) {
-        for (int idx = tid; idx < kLeafPts * rpad; idx += kBlock) {
-            const int i = idx / rpad, k = idx % rpad;
-            sK[i * KP + k] = k < r ? Sleaf[k * kLeafPts + i] : (T)0;
-        }
-        for (int idx = tid; idx < rpad * PT; idx += kBlock) {
-            const int k = idx / PT, c = idx % PT;
-            sW[k * WP + c] = (k < r && c < ncols) ? Lleaf[(B * r + k) * p + c0 + c] : (T)0;
-        }
-    }
-    __syncthreads();                                   // near-field tile and far operands ready
+    __syncthreads();                                   // near-field tile complete
     if (far) {
         const T *arow = sK + (16 * wave + lr) * KP + q;
         const T *bcol = sW + q * WP + lr;
@@ -778,15 +713,21 @@ k_l2p_p2p_sparse(int dim, int n, int ls, int depth, int r, int rpad, int p, int 
     }
 }
 
-// ---------------------------------------------------------------- M2L (MFMA)
-// One workgroup per (target box B, PT-column tile).  The output r x PT tile is
+// ---------------------------------------------------------------- M2L, M2M, L2L (MFMA)
+// One workgroup per (output box B, PT-column tile).  The output r x PT tile is
 // cut into 16 x 16 MFMA tiles (target-node rows padded to RT = ceil(r/16)
-// tiles), dealt round-robin to the 4 waves; for every interaction-list box A
-// the translation T_{l,o} (r x r) and M_A (r x PT) are staged in LDS (k padded
-// to a multiple of 4 with zeros) and multiplied on MFMA.
-template <typename T, int PT, int RMAX>
+// tiles), dealt round-robin to the 4 waves; for every source box A the r x r
+// translation and M_A (r x PT) are staged in LDS (k padded to a multiple of 4
+// with zeros) and multiplied on MFMA.  The three translations differ only in
+// their sources and operators:
+//   M2L: B at level lev, A over its interaction list, T_{lev, offset};
+//        L_B = the sum (levels are written before any L2L adds to them)
+//   M2M: B a parent at level lev, A its 2^dim children, S_child; M_B = the sum
+//   L2L: B a child at level lev + 1, A its parent, S_child^T; L_B += the product
+enum { kM2L = 0, kM2M = 1, kL2L = 2 };
+template <typename T, int PT, int RMAX, int MODE>
 __global__ void __launch_bounds__(kBlock)
-k_m2l_mma(int dim, int r, int p, int lev, const T *M, const T *Tlev, T *L) {
+k_trans_mma(int dim, int r, int p, int lev, const T *M, const T *Tlev, T *L) {
     typedef typename Mma<T>::v4 v4;
     constexpr int NCT = PT / 16;
     constexpr int MAXT = 8;                            // tiles per wave (r <= 64)
@@ -804,25 +745,39 @@ k_m2l_mma(int dim, int r, int p, int lev, const T *M, const T *Tlev, T *L) {
     const int64_t B = blockIdx.x;
     const int c0 = blockIdx.y * PT;
     const int ncols = min(PT, p - c0);
-    const int nb = 1 << lev;
-    const int noff = dim == 2 ? 49 : 343;
+    const int nb = 1 << lev;                           // boxes per axis at level lev
+    const int nbB = MODE == kL2L ? 2 * nb : nb;        // ... at the output box's level
+    // sources: the interaction list (M2L, over the 7^dim offset slots), the
+    // 2^dim children (M2M) or the parent (L2L)
+    const int noff = MODE == kM2L ? (dim == 2 ? 49 : 343) : MODE == kM2M ? (1 << dim) : 1;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, q = lane >> 4;
     const int ntiles = RT * NCT;
     const int nm = KR * (PT / VW), nt = 16 * RT * KR;
     int b[3];
-    box_coords(B, nb, dim, b);
-    // The next interaction-list source is loaded into registers while the
+    box_coords(B, nbB, dim, b);
+    const int bch = (b[0] & 1) | ((b[1] & 1) << 1) | ((b[2] & 1) << 2);   // L2L: child slot of B
+    // The next source is loaded into registers while the
     // MFMAs of the current one run, then moved to LDS between two barriers.
     tv mreg[MPT];
     T treg[TPT];
 #define HIKF_M2L_FETCH(OI)                                                                    \
     do {                                                                                      \
         const int fo = (OI);                                                                  \
-        const int fa[3] = {b[0] + fo % 7 - 3, b[1] + (fo / 7) % 7 - 3,                        \
-                           dim == 3 ? b[2] + fo / 49 - 3 : 0};                                \
-        const int64_t A = box_index(fa, nb, dim);                                             \
-        const T *Toff = Tlev + int64_t(fo) * r * r;                                           \
+        int64_t A;                                                                            \
+        if (MODE == kM2L) {                                                                   \
+            const int fa[3] = {b[0] + fo % 7 - 3, b[1] + (fo / 7) % 7 - 3,                    \
+                               dim == 3 ? b[2] + fo / 49 - 3 : 0};                            \
+            A = box_index(fa, nb, dim);                                                       \
+        } else if (MODE == kM2M) {                                                            \
+            const int fa[3] = {2 * b[0] + (fo & 1), 2 * b[1] + ((fo >> 1) & 1),               \
+                               2 * b[2] + ((fo >> 2) & 1)};                                   \
+            A = box_index(fa, 2 * nb, dim);                                                   \
+        } else {                                                                              \
+            const int fa[3] = {b[0] >> 1, b[1] >> 1, b[2] >> 1};                              \
+            A = box_index(fa, nb, dim);                                                       \
+        }                                                                                     \
+        const T *Toff = Tlev + int64_t(MODE == kL2L ? bch : fo) * r * r;                      \
         _Pragma("unroll") for (int u = 0; u < MPT; ++u) {                                     \
             const int idx = tid + kBlock * u, k = idx / (PT / VW), ch = idx % (PT / VW);      \
             tv v;                                                                             \
@@ -835,10 +790,12 @@ k_m2l_mma(int dim, int r, int p, int lev, const T *M, const T *Tlev, T *L) {
         }                                                                                     \
         _Pragma("unroll") for (int u = 0; u < TPT; ++u) {                                     \
             const int idx = tid + kBlock * u, i = idx / KR, k = idx % KR;                     \
-            treg[u] = (idx < nt && i < r && k < r) ? Toff[i * r + k] : (T)0;                  \
+            treg[u] = (idx < nt && i < r && k < r) ? Toff[MODE == kL2L ? k * r + i : i * r + k] \
+                                                   : (T)0;                                    \
         }                                                                                     \
     } while (0)
     auto next_il = [&](int oi) {
+        if (MODE != kM2L) return oi + 1;
         for (++oi; oi < noff; ++oi) {
             int o[3] = {oi % 7 - 3, (oi / 7) % 7 - 3, oi / 49 - 3};
             if (il_member(b, o, nb, dim)) break;
@@ -887,7 +844,10 @@ k_m2l_mma(int dim, int r, int p, int lev, const T *M, const T *Tlev, T *L) {
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
             const int k = 16 * rt + Mma<T>::row(q, rr);
-            if (k < r && c < ncols) L[(B * r + k) * p + c0 + c] = acc[u][rr];
+            if (k < r && c < ncols) {
+                T *dst = L + (B * r + k) * p + c0 + c;
+                *dst = MODE == kL2L ? *dst + acc[u][rr] : acc[u][rr];
+            }
         }
     }
 }
@@ -980,7 +940,7 @@ __global__ void k_split_t(int64_t nslots, int r, int rt, int kr, const float *T,
     split_bf16(v, Th + idx, Tl + idx);
 }
 
-// M2L on BF16 MFMA: as k_m2l_mma, with the translation tile (A, [target
+// M2L on BF16 MFMA: as k_trans_mma, with the translation tile (A, [target
 // node][source node]) and M_A (B, [column][source node]) staged as hi / lo.
 // Software-pipelined over the interaction list: the next source's tiles are
 // loaded into registers while the MFMAs of the current one run, then moved
@@ -1382,7 +1342,6 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
     T *Schild = reinterpret_cast<T *>(scr + lay.schild);
     T *Tm2l = reinterpret_cast<T *>(scr + lay.m2l);
     auto Mlev = [&](int lev) { return reinterpret_cast<T *>(scr + lay.ML_level[lev]); };
-    const size_t lds_cap = 64 * 1024;
     auto Llev = [&](int lev) {
         return reinterpret_cast<T *>(scr + lay.L_base + (lay.ML_level[lev] - lay.ML_level[2]));
     };
@@ -1409,17 +1368,25 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
                                (kLeafPts * PT + r * kLeafPts) * sizeof(T), s, dim, g.npad, g.ls, D, r,
                                p, PT, W, Sleaf, Mlev(D));
         tend(tm, HIKF_PHASE_P2M, s);
-        // M2M
+        // M2M (and L2L below) on MFMA: the tile kernel of M2L with the children
+        // (or the parent) as sources
+        constexpr int TPT = sizeof(T) == 4 ? 128 : 64;
+        const int RTt = (r + 15) / 16, KRt = (r + 3) / 4 * 4;
+        const size_t tlds = (size_t(KRt) * (TPT + Mma<T>::pad) + size_t(16 * RTt) * 68) * sizeof(T);
         tbegin(tm, HIKF_PHASE_M2M, s);
-        // r x PT outputs: at most 4 per thread; the children's panels and one
-        // child matrix share the LDS
-        PT = min(p, min(64, floor_pow2(int((lds_cap / sizeof(T) - size_t(r) * r) /
-                                            ((size_t(1) << dim) * r)))));
-        while (PT > 16 && r * PT > 4 * kBlock) PT /= 2;
-        for (int lev = D - 1; lev >= 2; --lev)
-            hipLaunchKernelGGL(k_m2m<T>, dim3(unsigned(g.boxes(lev)), (p + PT - 1) / PT),
-                               dim3(kBlock), ((size_t(1) << dim) * r * PT + size_t(r) * r) * sizeof(T),
-                               s, dim, r, p, lev, PT, Mlev(lev + 1), Schild, Mlev(lev));
+        e = r <= 32 ? allow_lds(k_trans_mma<T, TPT, 32, kM2M>, tlds) : allow_lds(k_trans_mma<T, TPT, 64, kM2M>, tlds);
+        if (e == hipSuccess)
+            e = r <= 32 ? allow_lds(k_trans_mma<T, TPT, 32, kL2L>, tlds) : allow_lds(k_trans_mma<T, TPT, 64, kL2L>, tlds);
+        if (e != hipSuccess) return e;
+        for (int lev = D - 1; lev >= 2; --lev) {
+            const dim3 grid(unsigned(g.boxes(lev)), (p + TPT - 1) / TPT);
+            if (r <= 32)
+                hipLaunchKernelGGL((k_trans_mma<T, TPT, 32, kM2M>), grid, dim3(kBlock), tlds, s, dim, r, p,
+                                   lev, Mlev(lev + 1), Schild, Mlev(lev));
+            else
+                hipLaunchKernelGGL((k_trans_mma<T, TPT, 64, kM2M>), grid, dim3(kBlock), tlds, s, dim, r, p,
+                                   lev, Mlev(lev + 1), Schild, Mlev(lev));
+        }
         tend(tm, HIKF_PHASE_M2M, s);
         // M2L
         tbegin(tm, HIKF_PHASE_M2L, s);
@@ -1458,27 +1425,31 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
             constexpr int MPT = sizeof(T) == 4 ? 128 : 64;
             const int RT = (r + 15) / 16, KR = (r + 3) / 4 * 4;
             const size_t lds = (size_t(KR) * (MPT + Mma<T>::pad) + size_t(16 * RT) * 68) * sizeof(T);
-            e = r <= 32 ? allow_lds(k_m2l_mma<T, MPT, 32>, lds) : allow_lds(k_m2l_mma<T, MPT, 64>, lds);
+            e = r <= 32 ? allow_lds(k_trans_mma<T, MPT, 32, kM2L>, lds) : allow_lds(k_trans_mma<T, MPT, 64, kM2L>, lds);
             if (e != hipSuccess) return e;
             for (int lev = 2; lev <= D; ++lev) {
                 const dim3 grid(unsigned(g.boxes(lev)), (p + MPT - 1) / MPT);
                 const T *Tl = Tm2l + int64_t(lev - 2) * g.noff() * r * r;
                 if (r <= 32)
-                    hipLaunchKernelGGL((k_m2l_mma<T, MPT, 32>), grid, dim3(kBlock), lds, s, dim, r, p,
+                    hipLaunchKernelGGL((k_trans_mma<T, MPT, 32, kM2L>), grid, dim3(kBlock), lds, s, dim, r, p,
                                        lev, Mlev(lev), Tl, Llev(lev));
                 else
-                    hipLaunchKernelGGL((k_m2l_mma<T, MPT, 64>), grid, dim3(kBlock), lds, s, dim, r, p,
+                    hipLaunchKernelGGL((k_trans_mma<T, MPT, 64, kM2L>), grid, dim3(kBlock), lds, s, dim, r, p,
                                        lev, Mlev(lev), Tl, Llev(lev));
             }
         }
         tend(tm, HIKF_PHASE_M2L, s);
         // L2L
         tbegin(tm, HIKF_PHASE_L2L, s);
-        PT = min(p, 64);
-        for (int lev = 2; lev < D; ++lev)
-            hipLaunchKernelGGL(k_l2l<T>, dim3(unsigned(g.boxes(lev + 1)), (p + PT - 1) / PT),
-                               dim3(kBlock), (size_t(r) * PT + size_t(r) * r) * sizeof(T), s, dim,
-                               r, p, lev, PT, Llev(lev), Schild, Llev(lev + 1));
+        for (int lev = 2; lev < D; ++lev) {
+            const dim3 grid(unsigned(g.boxes(lev + 1)), (p + TPT - 1) / TPT);
+            if (r <= 32)
+                hipLaunchKernelGGL((k_trans_mma<T, TPT, 32, kL2L>), grid, dim3(kBlock), tlds, s, dim, r, p,
+                                   lev, Llev(lev), Schild, Llev(lev + 1));
+            else
+                hipLaunchKernelGGL((k_trans_mma<T, TPT, 64, kL2L>), grid, dim3(kBlock), tlds, s, dim, r, p,
+                                   lev, Llev(lev), Schild, Llev(lev + 1));
+        }
         tend(tm, HIKF_PHASE_L2L, s);
     }
     // near-field kernel blocks by leaf offset (all neighbours are within one
@@ -1495,13 +1466,17 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
         const int rpad = (r + 3) / 4 * 4;
         const size_t lds = (size_t(PPT) * (kLeafPts + 1) + size_t(kLeafPts) * (rpad + 4) +
                             size_t(rpad) * (PPT + Mma<T>::pad)) * sizeof(T);
-        e = allow_lds(k_l2p_p2p_sparse<T, PPT>, lds);
+        e = dim == 2 ? allow_lds(k_l2p_p2p_sparse<T, PPT, 9>, lds) : allow_lds(k_l2p_p2p_sparse<T, PPT, 27>, lds);
         if (e != hipSuccess) return e;
         tbegin(tm, HIKF_PHASE_P2P, s);
         const double h = 1.0 / g.n;
-        hipLaunchKernelGGL((k_l2p_p2p_sparse<T, PPT>), dim3(unsigned(leaves), (p + PPT - 1) / PPT),
-                           dim3(kBlock), lds, s, dim, g.n, g.ls, D, r, rpad, p, g.far ? 1 : 0,
-                           g.kp, (T)(h * h), boff, bkey, bval, Sleaf, g.far ? Llev(D) : nullptr, CQ);
+        const dim3 grid(unsigned(leaves), (p + PPT - 1) / PPT);
+#define HIKF_P2P_SPARSE(NSLV)                                                                   \
+        hipLaunchKernelGGL((k_l2p_p2p_sparse<T, PPT, NSLV>), grid, dim3(kBlock), lds, s, g.n, g.ls, D, \
+                           r, rpad, p, g.far ? 1 : 0, g.kp, (T)(h * h), boff, bkey, bval, Sleaf,  \
+                           g.far ? Llev(D) : nullptr, CQ)
+        if (dim == 2) HIKF_P2P_SPARSE(9); else HIKF_P2P_SPARSE(27);
+#undef HIKF_P2P_SPARSE
         tend(tm, HIKF_PHASE_P2P, s);
         return hipGetLastError();
     }
