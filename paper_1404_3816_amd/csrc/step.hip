@@ -100,8 +100,10 @@ __global__ void k_widen(int64_t n, const TQ *src, double *dst) {
 // ---------------------------------------------------------------- 1. gather
 // One workgroup per (ray a, chunk ch of its nonzeros); thread t < p/2 sums
 // columns 2t and 2t + 1 of sum_e H_ae C_prior[col_e][.] with 16-byte loads,
-// thread p/2 sums H_ae x_hat[col_e].  Eight nonzeros are loaded before any is
-// accumulated, so the row loads of a chunk are in flight together.
+// and the 64 threads after them split sum_e H_ae x_hat[col_e] (nonzero j
+// mod 64 each, then summed in a fixed order).  Eight nonzeros are loaded
+// before any is accumulated, so the row loads of a chunk are in flight
+// together.
 template <typename TQ>
 __global__ void __launch_bounds__(512)
 k_gather(int p, int cpr, int64_t m, int64_t nnz, const int64_t *rowptr, const int32_t *col,
@@ -120,16 +122,23 @@ k_gather(int p, int cpr, int64_t m, int64_t nnz, const int64_t *rowptr, const in
     const int64_t e0 = r0 + len * ch / cpr, e1 = r0 + len * (ch + 1) / cpr;
     double *out = partial + (int64_t(a) * cpr + ch) * (p + 1);
     const int half = p / 2;
-    for (int t = threadIdx.x; t <= half; t += blockDim.x) {
-        if (t == half) {
-            double acc = 0.0;
-            for (int64_t e = e0; e < e1; ++e) {
-                const int64_t c = col[e];
-                if (c >= 0 && c < m) acc += val[e] * xhat[c];
-            }
-            out[p] = acc;
-            continue;
+    const int t = threadIdx.x;
+    __shared__ double hsum[64];
+    if (t >= half && t < half + 64) {
+        double acc = 0.0;
+        for (int64_t e = e0 + (t - half); e < e1; e += 64) {
+            const int64_t c = col[e];
+            if (c >= 0 && c < m) acc += val[e] * xhat[c];
         }
+        hsum[t - half] = acc;
+    }
+    __syncthreads();
+    if (t == half) {
+        double acc = 0.0;
+        for (int j = 0; j < 64; ++j) acc += hsum[j];
+        out[p] = acc;
+    }
+    if (t < half) {
         dv2 acc = dv2{0.0, 0.0};
         int64_t e = e0;
         for (; e + U <= e1; e += U) {
@@ -542,7 +551,7 @@ void run_gather(const Geometry &g, const Layout &lay, char *res, bool with_c, do
                 double *h, hipStream_t s, Timing *tm) {
     const int p = g.p;
     tbegin(tm, HIKF_PHASE_GATHER, s);
-    const unsigned gthreads = unsigned(((p / 2 + 1) + 63) / 64 * 64);
+    const unsigned gthreads = unsigned(((p / 2 + 64) + 63) / 64 * 64);
     hipLaunchKernelGGL(k_gather<TQ>, dim3(p, g.cpr), dim3(gthreads), 0, s, p, g.cpr, g.m, g.nnz,
                        reinterpret_cast<const int64_t *>(res + lay.rowptr),
                        reinterpret_cast<const int32_t *>(res + lay.col),
