@@ -373,7 +373,8 @@ hikf_status hikf_init(const hikf_problem *prob, const hikf_options *opt, void *r
     HIKF_TRY(hikf::launch_fmm(g, lay, res, scr, s, &f->timing), "fmm");
     HIKF_TRY(hikf::launch_init_state(g, lay, res, prob->x0_dev, s), "init state");
     f->riccati = opt->riccati > 0 ? opt->riccati : 0;
-    if (f->riccati) HIKF_TRY(hikf::launch_gq(f->g, lay, res, s), "H C_Q");
+    // H C_Q: the fixed part of every step's G (and of the p-space recursion)
+    HIKF_TRY(hikf::launch_gq(f->g, lay, res, s), "H C_Q");
     if (opt->graph && !opt->timing) {
         // capture on a private stream (the caller's may be the null stream,
         // which cannot be captured); the graph reads y from the resident copy

@@ -99,17 +99,18 @@ __global__ void k_widen(int64_t n, const TQ *src, double *dst) {
 
 // ---------------------------------------------------------------- 1. gather
 // One workgroup per (ray a, chunk ch of its nonzeros); thread t < p/2 sums
-// columns 2t and 2t + 1 of sum_e H_ae C_prior[col_e][.] with 16-byte loads,
+// columns 2t and 2t + 1 of sum_e H_ae X[col_e][.] with 16-byte loads, where
+// X is C (WITH_C; the step adds the fixed H C_Q afterwards, since
+// H C_prior = H C + H C_Q) or C_Q (H C_Q, once at init),
 // and the 64 threads after them split sum_e H_ae x_hat[col_e] (nonzero j
 // mod 64 each, then summed in a fixed order).  Eight nonzeros are loaded
 // before any is accumulated, so the row loads of a chunk are in flight
 // together.
-template <typename TQ>
+template <typename TQ, bool WITH_C>
 __global__ void __launch_bounds__(512)
 k_gather(int p, int cpr, int64_t m, int64_t nnz, const int64_t *rowptr, const int32_t *col,
          const double *val, const double *C, const TQ *CQ, const double *xhat,
          double *partial, const int *status) {
-    // C == nullptr: sums over C_Q alone (H C_Q, once at init)
     typedef double dv2 __attribute__((ext_vector_type(2)));
     typedef TQ qv2 __attribute__((ext_vector_type(2)));
     constexpr int U = 8;
@@ -149,9 +150,12 @@ k_gather(int p, int cpr, int64_t m, int64_t nnz, const int64_t *rowptr, const in
                 const int64_t c = col[e + u];
                 const bool ok = c >= 0 && c < m;
                 const int64_t o = (ok ? c : 0) * p + 2 * t;
-                const dv2 cv = C ? *reinterpret_cast<const dv2 *>(C + o) : dv2{0.0, 0.0};
-                const qv2 qv = *reinterpret_cast<const qv2 *>(CQ + o);
-                x[u] = dv2{cv[0] + (double)qv[0], cv[1] + (double)qv[1]};
+                if constexpr (WITH_C) {
+                    x[u] = *reinterpret_cast<const dv2 *>(C + o);
+                } else {
+                    const qv2 qv = *reinterpret_cast<const qv2 *>(CQ + o);
+                    x[u] = dv2{(double)qv[0], (double)qv[1]};
+                }
                 w[u] = ok ? val[e + u] : 0.0;
             }
 #pragma unroll
@@ -161,9 +165,12 @@ k_gather(int p, int cpr, int64_t m, int64_t nnz, const int64_t *rowptr, const in
             const int64_t c = col[e];
             if (c < 0 || c >= m) continue;
             const int64_t o = c * p + 2 * t;
-            const dv2 cv = C ? *reinterpret_cast<const dv2 *>(C + o) : dv2{0.0, 0.0};
-            const qv2 qv = *reinterpret_cast<const qv2 *>(CQ + o);
-            acc += val[e] * dv2{cv[0] + (double)qv[0], cv[1] + (double)qv[1]};
+            if constexpr (WITH_C) {
+                acc += val[e] * *reinterpret_cast<const dv2 *>(C + o);
+            } else {
+                const qv2 qv = *reinterpret_cast<const qv2 *>(CQ + o);
+                acc += val[e] * dv2{(double)qv[0], (double)qv[1]};
+            }
         }
         out[2 * t] = acc[0];
         out[2 * t + 1] = acc[1];
@@ -171,14 +178,16 @@ k_gather(int p, int cpr, int64_t m, int64_t nnz, const int64_t *rowptr, const in
 }
 
 // ---------------------------------------------------------------- 2. reduce
+// G = the chunk sums (+ GQ = H C_Q when given), h = the chunk sums
 __global__ void __launch_bounds__(256)
-k_reduce_g(int p, int cpr, const double *partial, double *G, double *hvec, const int *status) {
+k_reduce_g(int p, int cpr, const double *partial, const double *GQ, double *G, double *hvec,
+           const int *status) {
     if (status[kStInit] != 0) return;
     const int a = blockIdx.x;
     for (int b = threadIdx.x; b <= p; b += blockDim.x) {
         double s = 0.0;
         for (int c = 0; c < cpr; ++c) s += partial[(int64_t(a) * cpr + c) * (p + 1) + b];
-        if (b < p) G[int64_t(a) * p + b] = s;
+        if (b < p) G[int64_t(a) * p + b] = GQ ? s + GQ[int64_t(a) * p + b] : s;
         else hvec[a] = s;
     }
 }
@@ -552,19 +561,22 @@ void run_gather(const Geometry &g, const Layout &lay, char *res, bool with_c, do
     const int p = g.p;
     tbegin(tm, HIKF_PHASE_GATHER, s);
     const unsigned gthreads = unsigned(((p / 2 + 64) + 63) / 64 * 64);
-    hipLaunchKernelGGL(k_gather<TQ>, dim3(p, g.cpr), dim3(gthreads), 0, s, p, g.cpr, g.m, g.nnz,
+    const auto gk = with_c ? k_gather<TQ, true> : k_gather<TQ, false>;
+    hipLaunchKernelGGL(gk, dim3(p, g.cpr), dim3(gthreads), 0, s, p, g.cpr, g.m, g.nnz,
                        reinterpret_cast<const int64_t *>(res + lay.rowptr),
                        reinterpret_cast<const int32_t *>(res + lay.col),
                        reinterpret_cast<const double *>(res + lay.val),
-                       with_c ? reinterpret_cast<const double *>(res + lay.C) : nullptr,
+                       reinterpret_cast<const double *>(res + lay.C),
                        reinterpret_cast<const TQ *>(res + lay.CQ),
                        reinterpret_cast<const double *>(res + lay.xhat),
                        reinterpret_cast<double *>(res + lay.partial),
                        reinterpret_cast<const int *>(res + lay.status));
     tend(tm, HIKF_PHASE_GATHER, s);
     tbegin(tm, HIKF_PHASE_REDUCE, s);
+    // the step's G adds the H C_Q formed at init
     hipLaunchKernelGGL(k_reduce_g, dim3(p), dim3(256), 0, s, p, g.cpr,
-                       reinterpret_cast<const double *>(res + lay.partial), G, h,
+                       reinterpret_cast<const double *>(res + lay.partial),
+                       with_c ? reinterpret_cast<const double *>(res + lay.GQ) : nullptr, G, h,
                        reinterpret_cast<const int *>(res + lay.status));
     tend(tm, HIKF_PHASE_REDUCE, s);
 }
