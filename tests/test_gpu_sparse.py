@@ -101,3 +101,27 @@ def test_sparse_empty_h():
     st = f.query()
     f.close()
     assert st.last_status == 0 and np.all(cq == 0.0)
+
+
+def test_sparse_with_history_riccati_and_queries():
+    # the sparse mode under the other options: a step graph, the p-space
+    # recursion and the covariance history; in FP64 every output agrees
+    # with the dense-mode filter up to rounding
+    import torch
+    case = Case(2, 64, 32, ell=0.1, steps=4)
+    v = torch.as_tensor(np.random.default_rng(5).standard_normal(case.m), device="cuda")
+    y = torch.as_tensor(case.ys, device="cuda")
+    out = {}
+    for sparse in (False, True):
+        f = case.gpu_filter(n_c=4, precision="f64", sparse=sparse, history=4, riccati=2, graph=True)
+        x = torch.empty(case.m, dtype=torch.float64, device="cuda")
+        var = torch.empty(case.m, dtype=torch.float64, device="cuda")
+        for k in range(case.steps):
+            f.step(y[k], x, var)
+        pv = f.cov_apply(v).cpu().numpy()
+        st = f.query()
+        out[sparse] = (x.cpu().numpy(), var.cpu().numpy(), pv)
+        f.close()
+        assert st.last_status == 0 and st.steps_applied == case.steps
+    for a, b in zip(out[True], out[False]):
+        assert rel(a, b) < 1e-10
