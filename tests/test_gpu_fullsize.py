@@ -1,6 +1,7 @@
 """GPU parity at the benchmark's full size (1024 x 1024 cells, p = 256,
 Gaussian kernel ell = 0.05, n_c = 5, FP32 FMM, FP64 step), in the launch
-configuration bench.py times (phase timing on, eager launches).
+configuration bench.py times (phase timing on, eager launches, sparse
+source side) and with the dense W.
 
 At this size the oracle cannot run the whole filter, so the checks use
 outputs it computes one by one:
@@ -24,8 +25,8 @@ from helpers import rel
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def fullsize():
+@pytest.fixture(scope="module", params=["sparse", "dense"])
+def fullsize(request):
     torch = pytest.importorskip("torch")
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -37,7 +38,8 @@ def fullsize():
     pr, keep = F.problem_from_csr(dim, n, rowptr, col, val, np.full(p, w["r_var"]),
                                   theta=w["theta"], ell=w["ell"], gamma=w["gamma"],
                                   prior=w["prior"])
-    f = F.HikfFilter(pr, F.make_options(w["n_c"], "f32", False, timing=True), keep)
+    f = F.HikfFilter(pr, F.make_options(w["n_c"], "f32", False, timing=True,
+                                        sparse=request.param == "sparse"), keep)
     rows = np.sort(np.random.default_rng(7).choice(m, 48, replace=False))
     cq = f.export_cq()[torch.as_tensor(rows, device="cuda")].cpu().numpy()
     x = torch.empty(m, dtype=torch.float64, device="cuda")
