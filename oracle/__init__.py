@@ -24,8 +24,6 @@ Contents, each a plain NumPy/SciPy restatement of what the paper defines:
                   cited there); reference for the GPU's H^2 error split.
 * ``truth``       random-walk truths with covariance Q (Sec. 2.1 eq.
                   ``equation_random_walk``) for building test streams.
-* ``pins``        closed forms and brute-force checks the tests pin the
-                  oracle to.
 
 Parity status: every function above is pinned by a test in
 ``tests/test_oracle_*.py`` except where its docstring says

@@ -42,23 +42,3 @@ def random_walk_stream(Q, H, r_var, steps, seed, P0=None, mu0=None):
         ys.append(H @ x + np.sqrt(r_var) * v)
     return np.array(xs), np.array(ys)
 
-
-def measurement_space_stream(GQ, r_var, steps, seed, G0=None):
-    """Observations y_k = H x_k + v_k drawn in measurement space.
-
-    With P0 = Q, H x_k is a random walk started at N(0, H P0 H^T) with
-    increments N(0, H Q H^T); GQ = H Q H^T (p x p).  Exact in distribution
-    and never forms an m-vector, for grids too large for a dense Q.
-    """
-    p = GQ.shape[0]
-    G0 = GQ if G0 is None else G0
-    z = normal_draws(seed, p + steps * 2 * p)
-    sq, s0 = _sqrt_psd(GQ), _sqrt_psd(G0)
-    hx = s0 @ z[:p]
-    ys = []
-    off = p
-    for _ in range(steps):
-        hx = hx + sq @ z[off:off + p]
-        ys.append(hx + np.sqrt(r_var) * z[off + p:off + 2 * p])
-        off += 2 * p
-    return np.array(ys)

@@ -199,3 +199,23 @@ def test_storage_matches_paper_table():
         assert round(per_row * m / 1e6, 1) == pytest.approx(hikf_mb, abs=0.06)
     # the smallest grid's KF storage is exactly one m x m FP64 matrix
     assert round(8 * 3245 ** 2 / 1e6, 1) == rows[0][2]
+
+
+def test_random_walk_truth_follows_the_model():
+    # Sec. 2.1: x_k = x_{k-1} + w_k, w_k ~ N(0, Q); y_k = H x_k + v_k,
+    # v_k ~ N(0, R).  With a diagonal Q the square root is elementwise, so
+    # the stream is fixed by the standard-normal draws taken in the order
+    # x_0, then (w_k, v_k) for every k.
+    m, p, steps, r_var = 5, 3, 4, 0.04
+    q = np.array([0.5, 1.0, 2.0, 0.25, 3.0])
+    H = np.arange(1.0, 16.0).reshape(p, m) / 10.0
+    xs, ys = truth.random_walk_stream(np.diag(q), H, r_var, steps, seed=11)
+    z = synth.normal_draws(11, m + steps * (m + p))
+    x = np.sqrt(q) * z[:m]                     # x_0 ~ N(0, P_0 = Q)
+    off = m
+    for k in range(steps):
+        x = x + np.sqrt(q) * z[off:off + m]
+        y = H @ x + np.sqrt(r_var) * z[off + m:off + m + p]
+        off += m + p
+        np.testing.assert_allclose(xs[k], x, rtol=1e-14, atol=1e-14)
+        np.testing.assert_allclose(ys[k], y, rtol=1e-14, atol=1e-14)
