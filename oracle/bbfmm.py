@@ -23,6 +23,9 @@ N = leaf * 2^D):
 Arrays are held coordinate-major: box arrays have shape
 (2^l,)*dim + (r, p) with axis 0 = x; node and point multi-indices are
 flattened in C order over (x, y[, z]), which is the order of ``numpy.kron``.
+Every operator acts on the node (or point) axis of all boxes and all
+right-hand sides at once: ``numpy.matmul(op, X)`` with X of shape
+(..., nodes, p) gives out[..., a, c] = sum_b op[a, b] X[..., b, c].
 """
 
 import itertools
@@ -179,11 +182,11 @@ def _bbfmm_tree(dim, n, h, W, nc, leaf, family, theta, ell, gamma):
         Ko = K(np.sqrt((diff * diff).sum(-1)))           # (tgt, src)
         tsl = tuple(slice(max(0, -v), nl - max(0, v)) for v in o)
         ssl = tuple(slice(max(0, v), nl - max(0, -v)) for v in o)
-        F[tsl] += np.einsum("ts,...sp->...tp", Ko, Wl[ssl])
+        F[tsl] += np.matmul(Ko, Wl[ssl])
 
     if D >= 2:
         # 2. P2M
-        M = {D: np.einsum("kj,...jp->...kp", S_leaf, Wl)}
+        M = {D: np.matmul(S_leaf, Wl)}
         # 3. M2M, levels D-1 .. 2
         for lev in range(D - 1, 1, -1):
             child = M[lev + 1]
@@ -191,7 +194,7 @@ def _bbfmm_tree(dim, n, h, W, nc, leaf, family, theta, ell, gamma):
             for c in itertools.product((0, 1), repeat=dim):
                 Sc = _kron_all([S_half[v] for v in c])
                 sl = tuple(slice(v, None, 2) for v in c)
-                acc += np.einsum("kq,...qp->...kp", Sc, child[sl])
+                acc += np.matmul(Sc, child[sl])
             M[lev] = acc
         # 4. M2L, levels 2 .. D
         L = {}
@@ -208,15 +211,15 @@ def _bbfmm_tree(dim, n, h, W, nc, leaf, family, theta, ell, gamma):
                     continue
                 sb = [t + v for t, v in zip(tb, o)]
                 src = M[lev][np.ix_(*sb)]
-                acc[np.ix_(*tb)] += np.einsum("kq,...qp->...kp", T, src)
+                acc[np.ix_(*tb)] += np.matmul(T, src)
             L[lev] = acc
         # 5. L2L, levels 2 .. D-1 -> children
         for lev in range(2, D):
             for c in itertools.product((0, 1), repeat=dim):
                 Sc = _kron_all([S_half[v] for v in c])
                 sl = tuple(slice(v, None, 2) for v in c)
-                L[lev + 1][sl] += np.einsum("kq,...kp->...qp", Sc, L[lev])
+                L[lev + 1][sl] += np.matmul(Sc.T, L[lev])
         # 6. L2P
-        F += np.einsum("kj,...kp->...jp", S_leaf, L[D])
+        F += np.matmul(S_leaf.T, L[D])
 
     return _from_leaves(F, dim, n, leaf)
