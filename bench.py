@@ -68,16 +68,13 @@ def parse():
 
 
 def kernel_source_digest():
-    """SHA-256 over the source of the row-pass kernel (its section of step.hip,
-    from its heading to its launcher) and the shared header."""
+    """SHA-256 over the source of the row-pass kernel (rowpass.h) and the
+    shared header."""
     csrc = os.path.join(ROOT, "paper_1404_3816_amd", "csrc")
-    with open(os.path.join(csrc, "step.hip")) as fh:
-        src = fh.read()
-    a = src.index("// ---------------------------------------------------------------- 4. row pass")
-    b = src.index("void run_gather(", a)
-    h = hashlib.sha256(src[a:b].encode())
-    with open(os.path.join(csrc, "hikf_internal.h"), "rb") as fh:
-        h.update(fh.read())
+    h = hashlib.sha256()
+    for name in ("rowpass.h", "hikf_internal.h"):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()
 
 

@@ -138,6 +138,9 @@ hipError_t launch_init_state(const Geometry &g, const Layout &lay, char *res,
 hipError_t launch_step(const Geometry &g, const Layout &lay, char *res,
                        const double *y, hipStream_t s, Timing *t, bool gather = true,
                        bool advance = false);
+// fused row pass for p = 16 NT (rowpass.h, instantiated in rowpass_*.hip)
+template <typename TQ, int NT>
+hipError_t rowpass_launch(const Geometry &g, const Layout &lay, char *res, hipStream_t s);
 hipError_t launch_pspace(const Geometry &g, const Layout &lay, char *res,
                          const double *y, hipStream_t s);
 hipError_t launch_advance(const Geometry &g, const Layout &lay, char *res, hipStream_t s);

@@ -1,0 +1,302 @@
+// Fused row pass of one assimilation step (Algorithm Algorithm_HiKF: gain,
+// state, variance and cross-covariance rows), included by the rowpass_*.hip
+// units, each of which instantiates rowpass_launch for a quarter of the
+// supported p / 16 values and one C_Q type (the 64 variants compile in
+// parallel).  Selected by HIKF_RP_TQ (float or double) and HIKF_RP_SEL
+// (p / 16 mod 4).
+#pragma once
+
+#include "hikf_internal.h"
+
+namespace hikf {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// 512 threads = 8 waves per tile of 16 RG rows.  Wave w takes row group
+// g = w % RG (rows [16 (RG b + g), +16); lane l owns row l % 16 of them) and
+// column part c = w / RG (column tiles [T0, T1) of the P = 16 NT columns, the
+// CS = 8 / RG parts splitting them as evenly as possible).  P <= 256 runs 4
+// row groups x 2 column halves, P <= 512 runs 2 row groups x 4 quarters, so
+// every wave holds at most 8 column tiles.
+//
+// v_mfma_f64_16x16x4 computes D += A B with lane l supplying A[l%16][l/16] and
+// B[l/16][l%16] and holding D[l/16 + 4 r][l%16] (the FP64 variant interleaves
+// the rows).  The kernel computes tiles of K^T = S^{-1} C_prior^T: A is a
+// 16 x 4 piece of a slab of S^{-1} (symmetric) read from LDS and B is 4
+// values of the lane's own row of C_prior, so the result stays in the lane
+// that owns the row.  Columns are assigned so that every lane handles pairs
+// of adjacent columns: with q = l/16, lane l holds, for tile t and r = 0..3,
+//     K[row][16 t + col(q, r)],   col(q, r) = 8 (r/2) + 2 q + r % 2,
+// (output row i = q + 4 r of the MFMA tile is column col(i%4, i/4)), and the
+// MFMA step s of k block kb pairs lane group q with k = 16 kb + col(q, s).
+// The C_prior values a lane loads in its own column part are then exactly
+// the columns of K it ends up holding (no second read of C or C_Q), and every
+// global access of C, C_Q and the stores of C are 16-byte (two-column)
+// vector accesses.  S^{-1} is streamed through a double-buffered LDS slab of
+// 16 rows (row pitch P + 8 doubles: lane groups q and q + 1 read rows two
+// apart, which then fall on disjoint banks), prefetched into registers one
+// block ahead as 16-byte loads; LDS operands are read two MFMAs ahead.
+template <int NT, int CS, int RG_>
+struct RowSplit {
+    static constexpr int RG = RG_;
+    static constexpr int NTH = 64 * CS * RG_;  // threads of the workgroup
+    static constexpr int P = NT * 16;
+    static constexpr int LDB = P + 8;           // row pitch of the LDS slab (doubles)
+    static constexpr int SLAB = 16 * LDB;
+    static constexpr int PER2 = (8 * P + NTH - 1) / NTH;  // slab column pairs per thread
+    static constexpr int t0(int c) { return (c * NT + CS - 1) / CS; }
+};
+
+// column offset inside a 16-column tile of MFMA output row i (see above)
+__device__ __forceinline__ constexpr int rp_col(int q, int r) { return 8 * (r >> 1) + 2 * q + (r & 1); }
+
+template <typename TQ> struct Pair;
+template <> struct Pair<float> { typedef float v2 __attribute__((ext_vector_type(2))); };
+template <> struct Pair<double> { typedef double v2 __attribute__((ext_vector_type(2))); };
+typedef double dv2 __attribute__((ext_vector_type(2)));
+
+template <typename TQ, int NT, int CS, int RG_, int PART>
+__device__ __forceinline__ void rowpass_part(double *sB, double *red, int64_t m, double *C,
+                                             const TQ *CQ, const double *Sinv, const double *nu,
+                                             const double *rdiag) {
+    using RS = RowSplit<NT, CS, RG_>;
+    typedef typename Pair<TQ>::v2 qv2;
+    constexpr int RG = RS::RG, P = RS::P, LDB = RS::LDB, SLAB = RS::SLAB, PER2 = RS::PER2;
+    constexpr int NTH = RS::NTH;
+    constexpr int T0 = RS::t0(PART);
+    constexpr int T1 = RS::t0(PART + 1);
+    constexpr int NH = T1 - T0;
+    constexpr int NQ = 4 * NH;                  // (s, t) pairs per k block
+    constexpr int PH = PER2 > 4 && NQ >= 4 ? (PER2 + 1) / 2 : PER2;  // slab pairs in flight
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, q = lane >> 4, grp = wave % RG;
+    const int64_t row = int64_t(blockIdx.x) * (16 * RG) + grp * 16 + lr;
+    const bool ok = row < m;
+    const int64_t rbase = (ok ? row : 0) * P + 2 * q;
+    // A operand column of this lane inside a tile, and its slab row for step s
+    const int acol = rp_col(lr & 3, lr >> 2);
+
+    double keep[NH > 0 ? NH : 1][4];            // C_prior[row][16 t + col(q, s)], t in [T0, T1)
+    double cur[4];
+    dv2 nc[2];                                  // next block's C and C_Q, kept apart so the
+    qv2 nq[2];                                  // loads are waited for only where they are used
+    dv2 bpre[PH];
+    d4 acc[NH > 0 ? NH : 1];
+#pragma unroll
+    for (int t = 0; t < NH; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+
+#pragma unroll
+    for (int u = 0; u < PER2; ++u) {
+        const int idx = tid + NTH * u, rr = idx / (P / 2), c = 2 * (idx % (P / 2));
+        if (idx < 8 * P)
+            *reinterpret_cast<dv2 *>(sB + rr * LDB + c) =
+                *reinterpret_cast<const dv2 *>(Sinv + int64_t(rr) * P + c);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const dv2 cv = *reinterpret_cast<const dv2 *>(C + rbase + 8 * h);
+        const qv2 qv = *reinterpret_cast<const qv2 *>(CQ + rbase + 8 * h);
+        cur[2 * h] = ok ? cv[0] + (double)qv[0] : 0.0;
+        cur[2 * h + 1] = ok ? cv[1] + (double)qv[1] : 0.0;
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int kb = 0; kb < NT; ++kb) {
+        if (kb > 0) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                cur[2 * h] = ok ? nc[h][0] + (double)nq[h][0] : 0.0;
+                cur[2 * h + 1] = ok ? nc[h][1] + (double)nq[h][1] : 0.0;
+            }
+        }
+        if (kb + 1 < NT) {
+            // slab first: it is needed first (end of this block), C_prior next
+#pragma unroll
+            for (int u = 0; u < PH; ++u) {
+                const int idx = tid + NTH * u, rr = idx / (P / 2), c = 2 * (idx % (P / 2));
+                if (idx < 8 * P)
+                    bpre[u] = *reinterpret_cast<const dv2 *>(Sinv + int64_t(16 * (kb + 1) + rr) * P + c);
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                nc[h] = *reinterpret_cast<const dv2 *>(C + rbase + 16 * (kb + 1) + 8 * h);
+                nq[h] = *reinterpret_cast<const qv2 *>(CQ + rbase + 16 * (kb + 1) + 8 * h);
+            }
+        }
+        if (kb >= T0 && kb < T1) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) keep[kb - T0][s] = cur[s];
+        }
+        if (NH > 0) {
+            const double *B = sB + (kb & 1) * SLAB + 2 * q * LDB + acol + 16 * T0;
+            // step s reads slab row col(q, s) = 8 (s/2) + 2 q + s % 2
+            auto aop = [&](int i) {
+                constexpr int NHp = NH > 0 ? NH : 1;
+                const int si = i / NHp, ti = i % NHp;
+                return B[(8 * (si >> 1) + (si & 1)) * LDB + 16 * ti];
+            };
+            double ring[3];
+            ring[0] = aop(0);
+            if (NQ > 1) ring[1] = aop(1);
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) {
+                if (i + 2 < NQ) ring[(i + 2) % 3] = aop(i + 2);
+                const int si = i / NH, ti = i % NH;
+                acc[ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(ring[i % 3], cur[si], acc[ti], 0, 0, 0);
+                if (PH < PER2 && i == NQ / 2 - 1 && kb + 1 < NT) {
+                    // wide slabs go in two halves to bound the registers they hold;
+                    // the target buffer was last read before the previous barrier
+#pragma unroll
+                    for (int u = 0; u < PH; ++u) {
+                        const int idx = tid + NTH * u, rr = idx / (P / 2), c = 2 * (idx % (P / 2));
+                        if (idx < 8 * P)
+                            *reinterpret_cast<dv2 *>(sB + ((kb + 1) & 1) * SLAB + rr * LDB + c) = bpre[u];
+                    }
+#pragma unroll
+                    for (int u = PH; u < PER2; ++u) {
+                        const int idx = tid + NTH * u, rr = idx / (P / 2), c = 2 * (idx % (P / 2));
+                        if (idx < 8 * P)
+                            bpre[u - PH] = *reinterpret_cast<const dv2 *>(Sinv + int64_t(16 * (kb + 1) + rr) * P + c);
+                    }
+                }
+            }
+        }
+        if (kb + 1 < NT) {
+            constexpr int U0 = PH < PER2 ? PH : 0;
+#pragma unroll
+            for (int u = U0; u < PER2; ++u) {
+                const int idx = tid + NTH * u, rr = idx / (P / 2), c = 2 * (idx % (P / 2));
+                if (idx < 8 * P)
+                    *reinterpret_cast<dv2 *>(sB + ((kb + 1) & 1) * SLAB + rr * LDB + c) = bpre[u - U0];
+            }
+        }
+        __syncthreads();
+    }
+
+    // epilogue: lane holds K[row][16 t + col(q, r)] = acc[t - T0][r] and
+    // C_prior[row][16 t + col(q, r)] = keep[t - T0][r]
+    double dv = 0.0, dx = 0.0;
+#pragma unroll
+    for (int t = 0; t < NH; ++t)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int c = 16 * (T0 + t) + 8 * h + 2 * q;
+            const dv2 nv = *reinterpret_cast<const dv2 *>(nu + c);
+            const double k0 = acc[t][2 * h], k1 = acc[t][2 * h + 1];
+            dv += k0 * keep[t][2 * h] + k1 * keep[t][2 * h + 1];
+            dx += k0 * nv[0] + k1 * nv[1];
+        }
+    // C <- K R.  A row's 16 columns of tile t sit in its 4 lanes as two
+    // 64-byte halves (h = 0: columns 0..7, h = 1: 8..15).  Lanes of rows 2j
+    // and 2j + 1 (adjacent lanes) swap one half each (DPP quad permutation
+    // [1,0,3,2]), so that every store instruction writes whole 128-byte rows:
+    // first rows 2j (the even lane's h = 0 and, from the odd lane, the even
+    // row's h = 1), then rows 2j + 1.
+    {
+        const bool odd = lr & 1;
+        const int64_t r0 = row - odd;
+        auto swap_pair = [](double x) {
+            int2 v = __builtin_bit_cast(int2, x);
+            v.x = __builtin_amdgcn_mov_dpp(v.x, 0xB1, 0xF, 0xF, false);
+            v.y = __builtin_amdgcn_mov_dpp(v.y, 0xB1, 0xF, 0xF, false);
+            return __builtin_bit_cast(double, v);
+        };
+#pragma unroll
+        for (int t = 0; t < NH; ++t) {
+            const int c0 = 16 * (T0 + t) + 2 * q;
+            const dv2 ra = *reinterpret_cast<const dv2 *>(rdiag + c0);
+            const dv2 rb = *reinterpret_cast<const dv2 *>(rdiag + c0 + 8);
+            const dv2 a = dv2{acc[t][0] * ra[0], acc[t][1] * ra[1]};   // h = 0 of own row
+            const dv2 b = dv2{acc[t][2] * rb[0], acc[t][3] * rb[1]};   // h = 1 of own row
+            const dv2 g = dv2{swap_pair(odd ? a[0] : b[0]), swap_pair(odd ? a[1] : b[1])};
+            const int cc = c0 + (odd ? 8 : 0);
+            // streaming stores: C is not read again within this pass
+            if (r0 < m) __builtin_nontemporal_store(odd ? g : a, reinterpret_cast<dv2 *>(C + r0 * P + cc));
+            if (r0 + 1 < m)
+                __builtin_nontemporal_store(odd ? b : g, reinterpret_cast<dv2 *>(C + (r0 + 1) * P + cc));
+        }
+    }
+    dv += __shfl_xor(dv, 16, 64);
+    dx += __shfl_xor(dx, 16, 64);
+    dv += __shfl_xor(dv, 32, 64);
+    dx += __shfl_xor(dx, 32, 64);
+    if (q == 0) {
+        red[((PART * RG + grp) * 16 + lr) * 2 + 0] = dv;
+        red[((PART * RG + grp) * 16 + lr) * 2 + 1] = dx;
+    }
+}
+
+template <typename TQ, int NT, int CS, int RG>
+__global__ void __launch_bounds__(64 * CS * RG)
+k_rowpass(int64_t m, double *C, const TQ *CQ, const double *Sinv, const double *nu,
+          const double *rdiag, double *xhat, double *var, double kdiag, const int *status,
+          unsigned long long *negvar) {
+    using RS = RowSplit<NT, CS, RG>;
+    __shared__ __align__(16) double sB[2 * RS::SLAB];
+    __shared__ double red[CS * RG * 16 * 2];
+    if (status[kStStep] != HIKF_OK) return;
+    const int part = (threadIdx.x >> 6) / RG;
+    if (part == 0)
+        rowpass_part<TQ, NT, CS, RG, 0>(sB, red, m, C, CQ, Sinv, nu, rdiag);
+    else if (part == 1)
+        rowpass_part<TQ, NT, CS, RG, 1>(sB, red, m, C, CQ, Sinv, nu, rdiag);
+    else if (CS > 2 && part == 2)
+        rowpass_part<TQ, NT, CS, RG, (CS > 2 ? 2 : 0)>(sB, red, m, C, CQ, Sinv, nu, rdiag);
+    else if (CS > 3)
+        rowpass_part<TQ, NT, CS, RG, (CS > 3 ? 3 : 0)>(sB, red, m, C, CQ, Sinv, nu, rdiag);
+    __syncthreads();
+    const int tid = threadIdx.x;
+    if (tid < 16 * RG) {
+        const int64_t row = int64_t(blockIdx.x) * (16 * RG) + tid;
+        if (row < m) {
+            double dv = 0.0, dx = 0.0;
+#pragma unroll
+            for (int c = 0; c < CS; ++c) {
+                dv += red[(c * 16 * RG + tid) * 2];
+                dx += red[(c * 16 * RG + tid) * 2 + 1];
+            }
+            const double v = var[row] + kdiag - dv;
+            var[row] = v;
+            xhat[row] += dx;
+            if (v < 0.0) atomicAdd(negvar, 1ull);
+        }
+    }
+}
+
+}  // namespace
+
+template <typename TQ, int NT>
+hipError_t rowpass_launch(const Geometry &g, const Layout &lay, char *res, hipStream_t s) {
+    constexpr int CS = NT <= 16 ? 2 : 4;
+    constexpr int RG = NT <= 16 ? 4 : 2;     // 8 waves; 4-wave workgroups of 32 rows measured slower
+    constexpr int rows = 16 * RG;
+    const unsigned blocks = unsigned((g.m + rows - 1) / rows);
+    hipLaunchKernelGGL((k_rowpass<TQ, NT, CS, RG>), dim3(blocks), dim3(64 * CS * RG), 0, s, g.m,
+                       reinterpret_cast<double *>(res + lay.C),
+                       reinterpret_cast<const TQ *>(res + lay.CQ),
+                       reinterpret_cast<const double *>(res + lay.sinv),
+                       reinterpret_cast<const double *>(res + lay.nu),
+                       reinterpret_cast<const double *>(res + lay.rdiag),
+                       reinterpret_cast<double *>(res + lay.xhat),
+                       reinterpret_cast<double *>(res + lay.var), g.kp.family == HIKF_KERNEL_TEST_R2 ? 0.0 : g.kp.theta,
+                       reinterpret_cast<const int *>(res + lay.status),
+                       reinterpret_cast<unsigned long long *>(res + lay.negvar));
+    return hipGetLastError();
+}
+
+#define HIKF_RP(N) \
+    template hipError_t rowpass_launch<HIKF_RP_TQ, N>(const Geometry &, const Layout &, char *, hipStream_t);
+#if HIKF_RP_SEL == 1
+HIKF_RP(1) HIKF_RP(5) HIKF_RP(9) HIKF_RP(13) HIKF_RP(17) HIKF_RP(21) HIKF_RP(25) HIKF_RP(29)
+#elif HIKF_RP_SEL == 2
+HIKF_RP(2) HIKF_RP(6) HIKF_RP(10) HIKF_RP(14) HIKF_RP(18) HIKF_RP(22) HIKF_RP(26) HIKF_RP(30)
+#elif HIKF_RP_SEL == 3
+HIKF_RP(3) HIKF_RP(7) HIKF_RP(11) HIKF_RP(15) HIKF_RP(19) HIKF_RP(23) HIKF_RP(27) HIKF_RP(31)
+#else
+HIKF_RP(4) HIKF_RP(8) HIKF_RP(12) HIKF_RP(16) HIKF_RP(20) HIKF_RP(24) HIKF_RP(28) HIKF_RP(32)
+#endif
+#undef HIKF_RP
+
+}  // namespace hikf

@@ -1,0 +1,4 @@
+// Row-pass instantiations: C_Q in float, p / 16 = 2 mod 4.
+#define HIKF_RP_TQ float
+#define HIKF_RP_SEL 2
+#include "rowpass.h"
