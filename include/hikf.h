@@ -15,7 +15,9 @@
  * Notation: m = number of grid cells (unknowns), p = number of measurements
  * (the paper's n), r = n_c^dim Chebyshev nodes per box.
  *
- * Memory model.  The library never allocates device memory.  The caller
+ * Memory model.  The library never allocates device memory (its one fixed
+ * array, the workspace of hikf_cov_apply_noalloc, is part of its device code
+ * and is loaded with it).  The caller
  * obtains the two sizes from hikf_plan, allocates a RESIDENT region (kept
  * for the filter's lifetime) and a SCRATCH region (needed only until the
  * work queued by hikf_init has finished on its stream) and passes both to
@@ -261,6 +263,25 @@ hikf_status hikf_step_batch(hikf_filter *const *filters, const double *const *y_
  */
 hikf_status hikf_cov_apply(hikf_filter *f, const double *v_dev, double *out_dev,
                            void *scratch, size_t scratch_bytes, void *stream);
+
+/*
+ * hikf_cov_apply without a workspace argument, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid allocation).  The workspace is a fixed array of
+ * HIKF_NOALLOC_SCRATCH_BYTES inside the library's device code, one per
+ * device, held until the process ends; the call allocates nothing and
+ * frees nothing.  Every call on a device shares that device's array, so
+ * calls that overlap on one device (on different streams or host threads)
+ * race: serialise them.  Results equal hikf_cov_apply's.  Synchronises the
+ * stream.
+ * Errors: as hikf_cov_apply; HIKF_E_NOMEM when the query needs more than
+ * HIKF_NOALLOC_SCRATCH_BYTES (hikf_plan_info.query_bytes; about 11 MB for a
+ * 256 x 256 grid, p = 64, eight steps of history), with the sizes in
+ * hikf_last_error.
+ */
+#define HIKF_NOALLOC_SCRATCH_BYTES (32u << 20)
+hikf_status hikf_cov_apply_noalloc(hikf_filter *f, const double *v_dev, double *out_dev,
+                                   void *stream);
 
 /*
  * Synchronise the filter's last stream and read its device status and, if

@@ -274,6 +274,28 @@ QueryPlan query_plan(const Geometry &g0) {
     return q;
 }
 
+hikf_status set_err(hikf_filter *f, hikf_status st, const char *what, hipError_t e);
+
+// P_t v for hikf_cov_apply and hikf_cov_apply_noalloc: the FMM product Q v
+// and the history terms, with every workspace array inside `scr`.
+hikf_status cov_apply_run(hikf_filter *f, const QueryPlan &q, const double *v_dev,
+                          double *out_dev, char *scr, void *stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    f->last_stream = s;
+    long long t = 0;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipMemcpy(&t, f->res + f->lay.steps, 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "query sync", e);
+    if (t > f->g.history) return HIKF_E_UNSUPPORTED;
+    e = hikf::launch_fmm_apply(q.g, q.lay, scr, v_dev, scr + q.off_qv, s);
+    if (e == hipSuccess)
+        e = hikf::launch_cov_tail(f->g, f->lay, f->res, int(t), v_dev, scr + q.off_qv, 16,
+                                  reinterpret_cast<double *>(scr + q.off_part), q.nchunk,
+                                  reinterpret_cast<double *>(scr + q.off_w), out_dev, s);
+    if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "cov apply", e);
+    return HIKF_OK;
+}
+
 void pair_counts(const Geometry &g, int64_t *near, int64_t *far) {
     const int64_t nl = int64_t(1) << g.depth;
     int64_t per_axis = g.direct ? nl * nl : nl + 2 * (nl - 1);
@@ -289,6 +311,42 @@ void pair_counts(const Geometry &g, int64_t *near, int64_t *far) {
             f += pa - pb;
         }
     *far = f;
+}
+
+// Workspace of hikf_cov_apply_noalloc: a fixed array in the library's
+// device code object, so the call needs no allocation.  Each device holds its
+// own copy; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device (the array's name is a
+// host-side stand-in, not a device address).
+constexpr size_t kNoAllocBytes = size_t(HIKF_NOALLOC_SCRATCH_BYTES);
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+// Device address of `scratch` on device `dev`, looked up once per device
+// (with that device current; the caller's current device is restored) and
+// kept for the life of the process.  hikf_init performs the lookup for its
+// device, so the entry point normally only reads the table.
+hipError_t noalloc_scratch(int dev, char **out) {
+    static std::mutex mu;
+    static std::map<int, char *> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(dev);
+    if (it == addr.end()) {
+        int prev = 0;
+        hipError_t e = hipGetDevice(&prev);
+        if (e == hipSuccess && prev != dev) e = hipSetDevice(dev);
+        if (e != hipSuccess) return e;
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (prev != dev) {
+            hipError_t e2 = hipSetDevice(prev);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255)) return hipErrorInvalidSymbol;
+        it = addr.emplace(dev, static_cast<char *>(ptr)).first;
+    }
+    *out = it->second;
+    return hipSuccess;
 }
 
 hikf_status set_err(hikf_filter *f, hikf_status st, const char *what, hipError_t e) {
@@ -344,6 +402,14 @@ hikf_status hikf_init(const hikf_problem *prob, const hikf_options *opt, void *r
         e = hipDeviceGetAttribute(&f->g.num_cu, hipDeviceAttributeMultiprocessorCount, f->device);
     if (e != hipSuccess) { hikf_status r = set_err(f, HIKF_E_DEVICE, "device query", e); delete f; return r; }
     if (f->g.num_cu < 1) f->g.num_cu = 1;
+    {
+        // the fixed workspace of hikf_cov_apply_noalloc: resolve its device
+        // address now, with this device current.  A failure here only
+        // affects that entry point (it retries and reports), so it is
+        // cleared instead of failing the filter.
+        char *unused = nullptr;
+        if (noalloc_scratch(f->device, &unused) != hipSuccess) (void)hipGetLastError();
+    }
 #define HIKF_TRY(call, what)                                              \
     do {                                                                  \
         hipError_t e_ = (call);                                           \
@@ -453,21 +519,25 @@ hikf_status hikf_cov_apply(hikf_filter *f, const double *v_dev, double *out_dev,
     if (f->g.history == 0) return HIKF_E_UNSUPPORTED;
     const QueryPlan q = query_plan(f->g);
     if (scratch_bytes < q.bytes || (reinterpret_cast<uintptr_t>(scratch) & 255)) return HIKF_E_NOMEM;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    f->last_stream = s;
-    long long t = 0;
-    hipError_t e = hipStreamSynchronize(s);
-    if (e == hipSuccess) e = hipMemcpy(&t, f->res + f->lay.steps, 8, hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "query sync", e);
-    if (t > f->g.history) return HIKF_E_UNSUPPORTED;
-    char *scr = static_cast<char *>(scratch);
-    e = hikf::launch_fmm_apply(q.g, q.lay, scr, v_dev, scr + q.off_qv, s);
-    if (e == hipSuccess)
-        e = hikf::launch_cov_tail(f->g, f->lay, f->res, int(t), v_dev, scr + q.off_qv, 16,
-                                  reinterpret_cast<double *>(scr + q.off_part), q.nchunk,
-                                  reinterpret_cast<double *>(scr + q.off_w), out_dev, s);
-    if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "cov apply", e);
-    return HIKF_OK;
+    return cov_apply_run(f, q, v_dev, out_dev, static_cast<char *>(scratch), stream);
+}
+
+hikf_status hikf_cov_apply_noalloc(hikf_filter *f, const double *v_dev, double *out_dev,
+                                   void *stream) {
+    if (!f || !v_dev || !out_dev) return HIKF_E_INVALID;
+    if (f->g.history == 0) return HIKF_E_UNSUPPORTED;
+    const QueryPlan q = query_plan(f->g);
+    if (q.bytes > kNoAllocBytes) {
+        snprintf(f->err, sizeof(f->err),
+                 "cov_apply_noalloc: the query needs %zu bytes of workspace, above the %zu-byte "
+                 "fixed workspace (use hikf_cov_apply with a caller workspace)",
+                 q.bytes, kNoAllocBytes);
+        return HIKF_E_NOMEM;
+    }
+    char *scr = nullptr;
+    hipError_t e = noalloc_scratch(f->device, &scr);
+    if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "noalloc workspace", e);
+    return cov_apply_run(f, q, v_dev, out_dev, scr, stream);
 }
 
 hikf_status hikf_step_batch(hikf_filter *const *filters, const double *const *y_dev,

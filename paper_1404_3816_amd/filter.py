@@ -139,6 +139,18 @@ class HikfFilter:
                                  _stream_handle(stream)), "hikf_cov_apply", self.handle)
         return out
 
+    def cov_apply_noalloc(self, v, out=None, stream=None):
+        """P_{t|t} v through the entry point that allocates nothing (its
+        workspace is the library's fixed device array); out may be given so
+        that this call allocates nothing on the torch side either."""
+        assert v.dtype == torch.float64 and v.numel() == self.m and v.is_cuda and v.is_contiguous()
+        if out is None:
+            out = torch.empty_like(v)
+        H.check(H.hikf_cov_apply_noalloc(self.handle, ctypes.c_void_p(v.data_ptr()),
+                                         ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
+                "hikf_cov_apply_noalloc", self.handle)
+        return out
+
     def export_cq(self, stream=None):
         out = torch.empty(self.m, self.p, dtype=torch.float64, device=self.resident.device)
         H.check(H.hikf_export_cq(self.handle, ctypes.c_void_p(out.data_ptr()),

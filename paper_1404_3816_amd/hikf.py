@@ -38,6 +38,8 @@ HIKF_FMM_F32 = 0
 HIKF_FMM_F64 = 1
 HIKF_FMM_BF16X3 = 2
 HIKF_FMM_BF16 = 3
+# size of the fixed workspace of hikf_cov_apply_noalloc
+HIKF_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 c_i32, c_i64, c_dbl, c_vp, c_sz = (ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
                                    ctypes.c_void_p, ctypes.c_size_t)
@@ -86,6 +88,7 @@ _SIGS = {
     "hikf_step": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     "hikf_step_batch": (c_i32, [_P(c_vp), _P(c_vp), _P(c_vp), _P(c_vp), c_i32, c_vp]),
     "hikf_cov_apply": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
+    "hikf_cov_apply_noalloc": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
     "hikf_query": (c_i32, [c_vp, _P(hikf_stats)]),
     "hikf_export_state": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     "hikf_import_state": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
@@ -107,6 +110,7 @@ hikf_init = _lib.hikf_init
 hikf_step = _lib.hikf_step
 hikf_step_batch = _lib.hikf_step_batch
 hikf_cov_apply = _lib.hikf_cov_apply
+hikf_cov_apply_noalloc = _lib.hikf_cov_apply_noalloc
 hikf_query = _lib.hikf_query
 hikf_export_state = _lib.hikf_export_state
 hikf_import_state = _lib.hikf_import_state
