@@ -124,7 +124,9 @@ typedef struct hikf_options {
                                   G <- G S^{-1} R + H C_Q,  h <- h + G S^{-1} nu
                                 (from C_post = K R; O(p^3) instead of a read
                                 of nnz(H) rows of C).  Import_state forces the
-                                next step to gather.                          */
+                                next step to gather.  Every periodic gather
+                                also measures the drift of the carried values
+                                (hikf_stats.riccati_drift_g / _h).            */
     int32_t history;         /* steps of history kept for hikf_cov_apply (the
                                 prior cross-covariance and S^{-1} of every
                                 applied step: history * (m p + p^2) doubles
@@ -141,6 +143,23 @@ typedef struct hikf_options {
                                 the order of rounding; the near field is then
                                 summed in FP32 (FP64 in HIKF_FMM_F64) in every
                                 precision mode.  Ignored when direct = 1.     */
+    int32_t rowpass_variant; /* launch form of the fused row pass (the step's
+                                dominant kernel).  0: automatic, i.e. the
+                                entry of tune_cache for this p and C_Q type
+                                (nearest m) when tune_cache names a readable
+                                cache, else the built-in default.  1 + v
+                                forces variant v = 0..3: v & 1 persistent
+                                workgroups (one per compute unit, looping over
+                                row tiles; needs p / 16 even, else ignored),
+                                v & 2 32-row tiles with the columns in four
+                                parts instead of 64-row tiles in two halves
+                                (always the case for p > 256).  Results do not
+                                depend on the variant.                        */
+    int32_t reserved1;
+    const char *tune_cache;  /* path of a JSON tuning cache written by the
+                                package's tuner (python -m
+                                paper_1404_3816_amd.tune), or NULL; read by
+                                hikf_init only                                */
 } hikf_options;
 
 /* Phases timed when hikf_options.timing = 1 (indices of hikf_stats.time_ms). */
@@ -169,6 +188,10 @@ typedef struct hikf_plan_info {
     int64_t near_pairs;      /* (target leaf, source leaf) pairs in P2P       */
     int64_t far_pairs;       /* interaction-list pairs over all M2L levels    */
     size_t query_bytes;      /* scratch needed by hikf_cov_apply              */
+    int32_t rowpass_variant; /* the row-pass variant hikf_init will use (0..3):
+                                forced by the options, else from tune_cache,
+                                else the built-in default                     */
+    int32_t reserved3;
 } hikf_plan_info;
 
 typedef struct hikf_stats {
@@ -180,6 +203,16 @@ typedef struct hikf_stats {
                                 over all steps since init (no clamping)       */
     double time_ms[HIKF_NUM_PHASES];     /* summed event time per phase       */
     int64_t time_count[HIKF_NUM_PHASES]; /* timed executions per phase        */
+    int32_t rowpass_variant; /* row-pass variant in use (0..3, see options)    */
+    int32_t reserved2;
+    /* Drift of the p-space recursion (options.riccati >= 1): at every
+     * periodic gather the carried G = H C_prior and h = H x_hat are compared
+     * with the gathered ones; the largest max-norm difference relative to
+     * the max-norm of the gathered value seen since init, for G and for h,
+     * and the number of such checks.  Zero without the recursion.           */
+    double riccati_drift_g;
+    double riccati_drift_h;
+    int64_t riccati_checks;
 } hikf_stats;
 
 typedef struct hikf_filter hikf_filter;
@@ -188,7 +221,8 @@ typedef struct hikf_filter hikf_filter;
  * Validate a problem and report the workspace it needs.  Host only; reads
  * no device memory and allocates nothing.
  * Errors: HIKF_E_INVALID (dim not 2/3, N < 1, p < 1, nnz < 0, theta/ell not
- * positive, gamma outside (0, 2], n_c outside 1..8, NULL arrays),
+ * positive, gamma outside (0, 2], n_c outside 1..8, rowpass_variant outside
+ * 0..4, NULL arrays),
  * HIKF_E_UNSUPPORTED (p not a multiple of 16 or above 512, n_c^dim above
  * 64, a tree of 2^31 cells or more).  Any N >= 1 is accepted: the tree
  * covers Npad = leaf * 2^D >= N cells per axis (leaf 8 in 2-D, 4 in 3-D) of
@@ -239,8 +273,9 @@ hikf_status hikf_step(hikf_filter *f, const double *y_dev, double *x_out_dev,
  * x_out_dev / var_out_dev may be NULL (no copies for any filter) or hold
  * NULL entries.  Each filter's result is exactly its solo hikf_step result;
  * the filters must be distinct.
- * Errors: HIKF_E_INVALID (count < 0, NULL arrays, a NULL filter or y: then
- * no filter is stepped), otherwise the first immediate error of a step
+ * Errors: HIKF_E_INVALID (count < 0, NULL arrays, a NULL filter or y, a
+ * filter listed twice: then no filter is stepped), otherwise the first
+ * immediate error of a step
  * (the filters before it have been stepped, the ones after it have not).
  */
 hikf_status hikf_step_batch(hikf_filter *const *filters, const double *const *y_dev,

@@ -5,6 +5,8 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <string>
+#include <vector>
 
 #include "hikf_internal.h"
 
@@ -45,6 +47,9 @@ Layout make_layout(const Geometry &g) {
     L.ybuf = take(p * 8);
     L.psA = take(size_t(g.pp) * g.pp * 8);
     L.pivs = take(size_t(g.pp / 32) * 8);
+    L.Gg = take(p * p * 8);
+    L.hg = take(p * 8);
+    L.drift = take(3 * 8);
     L.resident_bytes = off;
 
     off = 0;
@@ -181,6 +186,96 @@ StreamPool *stream_pool() {
     return p;
 }
 
+// Built-in row-pass variant (rowpass.h) when neither the options nor a
+// tuning cache choose one.
+constexpr int kDefaultRowpassVariant = 0;
+
+// The row-pass variant a tuning cache records for (p, C_Q type): the entry
+// with the same p and type whose m is nearest (in log scale) to this m, or
+// -1.  The cache is the JSON file the package's tuner writes:
+//   {"rowpass": [{"p": 256, "cq": "f32", "m": 1048576, "variant": 1, ...}, ...], ...}
+// Only that array is read; unknown keys are skipped.
+int cached_rowpass_variant(const char *path, int p, bool cq64, int64_t m) {
+    if (!path) return -1;
+    FILE *fp = fopen(path, "rb");
+    if (!fp) return -1;
+    std::string txt;
+    char buf[4096];
+    size_t n;
+    while ((n = fread(buf, 1, sizeof(buf), fp)) > 0 && txt.size() < (size_t(1) << 24))
+        txt.append(buf, n);
+    fclose(fp);
+    size_t pos = txt.find("\"rowpass\"");
+    if (pos == std::string::npos) return -1;
+    pos = txt.find('[', pos);
+    if (pos == std::string::npos) return -1;
+    // the top-level objects of that array (brackets inside strings do not
+    // occur in this file's format)
+    std::vector<std::string> objs;
+    {
+        int depth = 0;
+        size_t start = 0;
+        for (size_t i = pos + 1; i < txt.size(); ++i) {
+            const char ch = txt[i];
+            if (ch == '{' || ch == '[') {
+                if (depth == 0 && ch == '{') start = i;
+                ++depth;
+            } else if (ch == '}' || ch == ']') {
+                if (depth == 0) break;            // end of the rowpass array
+                --depth;
+                if (depth == 0 && ch == '}') objs.push_back(txt.substr(start, i - start + 1));
+            }
+        }
+    }
+    // value of "key" inside the object text obj (number or quoted string)
+    auto field = [](const std::string &obj, const char *key, std::string *out) {
+        const std::string k = std::string("\"") + key + "\"";
+        size_t i = obj.find(k);
+        if (i == std::string::npos) return false;
+        i = obj.find(':', i + k.size());
+        if (i == std::string::npos) return false;
+        ++i;
+        while (i < obj.size() && (obj[i] == ' ' || obj[i] == '\t' || obj[i] == '\n' || obj[i] == '\r')) ++i;
+        size_t j = i;
+        if (j < obj.size() && obj[j] == '"') {
+            const size_t e = obj.find('"', j + 1);
+            if (e == std::string::npos) return false;
+            *out = obj.substr(j + 1, e - j - 1);
+            return true;
+        }
+        while (j < obj.size() && obj[j] != ',' && obj[j] != '}') ++j;
+        *out = obj.substr(i, j - i);
+        return true;
+    };
+    int best = -1;
+    double best_d = 1e300;
+    for (const std::string &obj : objs) {
+        std::string vp, vcq, vm, vv;
+        if (!field(obj, "p", &vp) || !field(obj, "cq", &vcq) || !field(obj, "m", &vm) ||
+            !field(obj, "variant", &vv))
+            continue;
+        char *ep = nullptr;
+        const long ep_p = strtol(vp.c_str(), &ep, 10);
+        const double em = strtod(vm.c_str(), nullptr);
+        const long ev = strtol(vv.c_str(), nullptr, 10);
+        if (ep_p != p || vcq != (cq64 ? "f64" : "f32") || ev < 0 || ev > 3 || !(em > 0)) continue;
+        const double d = fabs(log(em / double(m)));
+        if (d < best_d) {
+            best_d = d;
+            best = int(ev);
+        }
+    }
+    return best;
+}
+
+// The row-pass variant hikf_init uses: the forced one, else the tuning
+// cache's, else the built-in default.
+int resolve_rowpass_variant(const Geometry &g, const hikf_options *op) {
+    if (op->rowpass_variant > 0) return op->rowpass_variant - 1;
+    const int v = cached_rowpass_variant(op->tune_cache, g.p, g.fmm_prec == HIKF_FMM_F64, g.m);
+    return v >= 0 ? v : kDefaultRowpassVariant;
+}
+
 hikf_status build_geometry(const hikf_problem *pr, const hikf_options *op, Geometry *g) {
     if (!pr || !op || !g) return HIKF_E_INVALID;
     if (pr->dim != 2 && pr->dim != 3) return HIKF_E_INVALID;
@@ -228,6 +323,8 @@ hikf_status build_geometry(const hikf_problem *pr, const hikf_options *op, Geome
     g->fmm_prec = op->fmm_precision;
     g->prior = pr->prior_kind;
     if (op->history < 0 || op->history > 1000000) return HIKF_E_INVALID;
+    if (op->rowpass_variant < 0 || op->rowpass_variant > 4) return HIKF_E_INVALID;
+    g->rp_variant = op->rowpass_variant > 0 ? op->rowpass_variant - 1 : kDefaultRowpassVariant;
     g->history = op->history;
     g->alpha = pr->alpha;
     g->kp.family = pr->kernel_family;
@@ -371,6 +468,7 @@ hikf_status hikf_plan(const hikf_problem *prob, const hikf_options *opt, hikf_pl
     out->r = g.r;
     pair_counts(g, &out->near_pairs, &out->far_pairs);
     out->query_bytes = g.history ? query_plan(g).bytes : 0;
+    out->rowpass_variant = resolve_rowpass_variant(g, opt);
     return HIKF_OK;
 }
 
@@ -425,6 +523,7 @@ hikf_status hikf_init(const hikf_problem *prob, const hikf_options *opt, void *r
     HIKF_TRY(hipMemsetAsync(res + lay.status, 0, hikf::kNumStatus * 4, s), "status clear");
     HIKF_TRY(hipMemsetAsync(res + lay.steps, 0, 8, s), "steps clear");
     HIKF_TRY(hipMemsetAsync(res + lay.negvar, 0, 8, s), "counter clear");
+    HIKF_TRY(hipMemsetAsync(res + lay.drift, 0, 3 * 8, s), "drift clear");
     HIKF_TRY(hipMemcpyAsync(res + lay.rowptr, prob->h_rowptr_dev, size_t(g.p + 1) * 8,
                             hipMemcpyDeviceToDevice, s), "copy rowptr");
     if (g.nnz > 0) {
@@ -439,6 +538,7 @@ hikf_status hikf_init(const hikf_problem *prob, const hikf_options *opt, void *r
     HIKF_TRY(hikf::launch_fmm(g, lay, res, scr, s, &f->timing), "fmm");
     HIKF_TRY(hikf::launch_init_state(g, lay, res, prob->x0_dev, s), "init state");
     f->riccati = opt->riccati > 0 ? opt->riccati : 0;
+    f->g.rp_variant = resolve_rowpass_variant(g, opt);
     // H C_Q: the fixed part of every step's G (and of the p-space recursion)
     HIKF_TRY(hikf::launch_gq(f->g, lay, res, s), "H C_Q");
     if (opt->graph && !opt->timing) {
@@ -544,8 +644,12 @@ hikf_status hikf_step_batch(hikf_filter *const *filters, const double *const *y_
                             double *const *x_out_dev, double *const *var_out_dev, int32_t count,
                             void *stream) {
     if (count < 0 || (count > 0 && (!filters || !y_dev))) return HIKF_E_INVALID;
-    for (int32_t i = 0; i < count; ++i)
+    for (int32_t i = 0; i < count; ++i) {
         if (!filters[i] || !y_dev[i]) return HIKF_E_INVALID;
+        // one filter twice would be stepped concurrently on two streams
+        for (int32_t j = 0; j < i; ++j)
+            if (filters[j] == filters[i]) return HIKF_E_INVALID;
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
     StreamPool *pool = count > 1 ? stream_pool() : nullptr;
     if (!pool) {
@@ -596,6 +700,13 @@ hikf_status hikf_query(hikf_filter *f, hikf_stats *out) {
     out->last_status = st[hikf::kStStep];
     out->init_status = st[hikf::kStInit];
     out->min_pivot = mp;
+    out->rowpass_variant = f->g.rp_variant;
+    double drift[3] = {0.0, 0.0, 0.0};
+    e = hipMemcpy(drift, f->res + f->lay.drift, sizeof(drift), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "read drift", e);
+    out->riccati_drift_g = drift[0];
+    out->riccati_drift_h = drift[1];
+    out->riccati_checks = int64_t(drift[2]);
     if (f->timing.on) {
         e = f->timing.collect();
         if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "timing", e);
@@ -635,8 +746,12 @@ hikf_status hikf_import_state(hikf_filter *f, const double *x_dev, const double 
         e = hipMemcpyAsync(f->res + f->lay.var, var_dev, mb, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess && c_dev)
         e = hipMemcpyAsync(f->res + f->lay.C, c_dev, mb * f->g.p, hipMemcpyDeviceToDevice, s);
+    // the carried G, h no longer match: the next step gathers, and there is
+    // nothing carried to check against
+    if (e == hipSuccess)
+        e = hipMemsetAsync(f->res + f->lay.status + 4 * hikf::kStCarried, 0, 4, s);
     if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "import", e);
-    f->force_gather = true;                      // the carried G, h no longer match
+    f->force_gather = true;
     return HIKF_OK;
 }
 

@@ -19,6 +19,7 @@ constexpr int kNumStatus = 8;     // ints in the device status block
 enum : int {
     kStStep = 0,                  // hikf_status of the last step
     kStInit = 1,                  // hikf_status of the device-side init checks
+    kStCarried = 2,               // 1 while G, h hold values carried by the p-space recursion
 };
 
 struct KernelParams {
@@ -63,6 +64,7 @@ struct Geometry {
     int pp = 32;                  // p rounded up to 32 (p-space layout)
     int cpr = 1;                  // gather chunks per ray
     int num_cu = 256;             // compute units of the device (persistent grids)
+    int rp_variant = 0;           // row-pass variant (rowpass.h): bit 0 persistent, bit 1 narrow
     int64_t m = 0;                // n^dim cells (state size)
     int64_t mpad = 0;             // npad^dim cells of the tree
     int64_t nnz = 0;
@@ -90,6 +92,7 @@ struct Layout {
     size_t GQ, Gn, hpart;                     // H C_Q, the next G, shares of the next h
     size_t histC, histS;                      // per-step C_prior and S^{-1} (history)
     size_t psA, pivs;                         // p-space ping-pong buffer (with xbuf), pivots
+    size_t Gg, hg, drift;                     // gathered G, h (drift check), drift record
     size_t resident_bytes;
     // scratch
     size_t W, knear, sleaf, schild, m2l, lev_off;   // lev_off: start of M/L storage

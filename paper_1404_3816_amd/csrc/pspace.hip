@@ -282,8 +282,9 @@ k_ps_advance(int p, int nbk, const double *G, const double *Sinv, const double *
 }
 
 __global__ void k_ps_finish(int p, int nbk, const double *Gn, const double *hpart, double *G,
-                            double *h, const int *status) {
+                            double *h, int *status) {
     if (status[kStStep] != HIKF_OK) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) status[kStCarried] = 1;
     const int64_t n = int64_t(p) * p;
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
          i += int64_t(gridDim.x) * blockDim.x) {
@@ -339,7 +340,7 @@ hipError_t launch_advance(const Geometry &g, const Layout &lay, char *res, hipSt
     const int64_t n = int64_t(g.p) * g.p;
     hipLaunchKernelGGL(k_ps_finish, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, g.p, nbk,
                        Gn, hpart, reinterpret_cast<double *>(res + lay.G),
-                       reinterpret_cast<double *>(res + lay.hvec), status);
+                       reinterpret_cast<double *>(res + lay.hvec), const_cast<int *>(status));
     return hipGetLastError();
 }
 

@@ -56,10 +56,18 @@ template <> struct Pair<float> { typedef float v2 __attribute__((ext_vector_type
 template <> struct Pair<double> { typedef double v2 __attribute__((ext_vector_type(2))); };
 typedef double dv2 __attribute__((ext_vector_type(2)));
 
-template <typename TQ, int NT, int CS, int RG_, int PART>
-__device__ __forceinline__ void rowpass_part(double *sB, double *red, int64_t m, double *C,
-                                             const TQ *CQ, const double *Sinv, const double *nu,
-                                             const double *rdiag) {
+// The row pass of one or (PERSIST) several row tiles.  A persistent
+// workgroup takes tiles blockIdx.x, blockIdx.x + gridDim.x, ...; during the
+// last k block of a tile it already loads the first S^{-1} slab and the first
+// C_prior values of its next tile, so that tile's MFMAs start as soon as the
+// epilogue of the current one has issued its stores (the stores then drain
+// while the next tile computes).
+template <typename TQ, int NT, int CS, int RG_, int PART, bool PERSIST>
+__device__ __forceinline__ void rowpass_part(double *sB, double *red, int64_t m, int64_t ntiles,
+                                             double *C, const TQ *CQ, const double *Sinv,
+                                             const double *nu, const double *rdiag, double *xhat,
+                                             double *var, double kdiag,
+                                             unsigned long long *negvar) {
     using RS = RowSplit<NT, CS, RG_>;
     typedef typename Pair<TQ>::v2 qv2;
     constexpr int RG = RS::RG, P = RS::P, LDB = RS::LDB, SLAB = RS::SLAB, PER2 = RS::PER2;
@@ -71,11 +79,10 @@ __device__ __forceinline__ void rowpass_part(double *sB, double *red, int64_t m,
     constexpr int PH = PER2 > 4 && NQ >= 4 ? (PER2 + 1) / 2 : PER2;  // slab pairs in flight
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, q = lane >> 4, grp = wave % RG;
-    const int64_t row = int64_t(blockIdx.x) * (16 * RG) + grp * 16 + lr;
-    const bool ok = row < m;
-    const int64_t rbase = (ok ? row : 0) * P + 2 * q;
     // A operand column of this lane inside a tile, and its slab row for step s
     const int acol = rp_col(lr & 3, lr >> 2);
+    int64_t tile = blockIdx.x;
+    auto row_of = [&](int64_t tl) { return tl * (16 * RG) + grp * 16 + lr; };
 
     double keep[NH > 0 ? NH : 1][4];            // C_prior[row][16 t + col(q, s)], t in [T0, T1)
     double cur[4];
@@ -83,9 +90,8 @@ __device__ __forceinline__ void rowpass_part(double *sB, double *red, int64_t m,
     qv2 nq[2];                                  // loads are waited for only where they are used
     dv2 bpre[PH];
     d4 acc[NH > 0 ? NH : 1];
-#pragma unroll
-    for (int t = 0; t < NH; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
 
+    // prologue: slab 0 into buffer 0, the first tile's first C_prior block
 #pragma unroll
     for (int u = 0; u < PER2; ++u) {
         const int idx = tid + NTH * u, rr = idx / (P / 2), c = 2 * (idx % (P / 2));
@@ -93,197 +99,267 @@ __device__ __forceinline__ void rowpass_part(double *sB, double *red, int64_t m,
             *reinterpret_cast<dv2 *>(sB + rr * LDB + c) =
                 *reinterpret_cast<const dv2 *>(Sinv + int64_t(rr) * P + c);
     }
+    {
+        const int64_t r = row_of(tile);
+        const int64_t rb = (r < m ? r : 0) * P + 2 * q;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const dv2 cv = *reinterpret_cast<const dv2 *>(C + rbase + 8 * h);
-        const qv2 qv = *reinterpret_cast<const qv2 *>(CQ + rbase + 8 * h);
-        cur[2 * h] = ok ? cv[0] + (double)qv[0] : 0.0;
-        cur[2 * h + 1] = ok ? cv[1] + (double)qv[1] : 0.0;
+        for (int h = 0; h < 2; ++h) {
+            nc[h] = *reinterpret_cast<const dv2 *>(C + rb + 8 * h);
+            nq[h] = *reinterpret_cast<const qv2 *>(CQ + rb + 8 * h);
+        }
     }
     __syncthreads();
+    // LDS buffer of k block kb: kb % 2 (a tile has an even number of k
+    // blocks in the persistent form, so every tile starts in buffer 0)
+    static_assert(!PERSIST || NT % 2 == 0, "persistent row pass needs an even block count");
+
+    for (;;) {
+        const int64_t row = row_of(tile);
+        const bool ok = row < m;
+        const int64_t rbase = (ok ? row : 0) * P + 2 * q;
+        const int64_t next = tile + gridDim.x;
+        const bool more = PERSIST && next < ntiles;
+        int64_t nrbase = 0;
+        if (more) {
+            const int64_t nr = row_of(next);
+            nrbase = (nr < m ? nr : 0) * P + 2 * q;
+        }
+#pragma unroll
+        for (int t = 0; t < NH; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+        // the S^{-1} slabs are the same for every tile: the empty asm keeps
+        // their loads inside this tile's k loop instead of hoisted out of
+        // the tile loop
+        const double *Sv = Sinv;
+        if (PERSIST) asm volatile("" : "+s"(Sv));
 
 #pragma unroll
-    for (int kb = 0; kb < NT; ++kb) {
-        if (kb > 0) {
+        for (int kb = 0; kb < NT; ++kb) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 cur[2 * h] = ok ? nc[h][0] + (double)nq[h][0] : 0.0;
                 cur[2 * h + 1] = ok ? nc[h][1] + (double)nq[h][1] : 0.0;
             }
-        }
-        if (kb + 1 < NT) {
-            // slab first: it is needed first (end of this block), C_prior next
+            // what the next k block needs: slab kb + 1 and this tile's
+            // C_prior block kb + 1, or after the last block slab 0 and the
+            // next tile's first block
+            const bool pf = kb + 1 < NT || more;
+            const int nslab = kb + 1 < NT ? 16 * (kb + 1) : 0;
+            const int64_t pbase = kb + 1 < NT ? rbase + 16 * (kb + 1) : nrbase;
+            double *nbuf = sB + ((kb + 1) & 1) * SLAB;
+            if (pf) {
+                // slab first: it is needed first (end of this block), C_prior next
 #pragma unroll
-            for (int u = 0; u < PH; ++u) {
-                const int idx = tid + NTH * u, rr = idx / (P / 2), c = 2 * (idx % (P / 2));
-                if (idx < 8 * P)
-                    bpre[u] = *reinterpret_cast<const dv2 *>(Sinv + int64_t(16 * (kb + 1) + rr) * P + c);
+                for (int u = 0; u < PH; ++u) {
+                    const int idx = tid + NTH * u, rr = idx / (P / 2), c = 2 * (idx % (P / 2));
+                    if (idx < 8 * P)
+                        bpre[u] = *reinterpret_cast<const dv2 *>(Sv + int64_t(nslab + rr) * P + c);
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    nc[h] = *reinterpret_cast<const dv2 *>(C + pbase + 8 * h);
+                    nq[h] = *reinterpret_cast<const qv2 *>(CQ + pbase + 8 * h);
+                }
             }
+            if (kb >= T0 && kb < T1) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                nc[h] = *reinterpret_cast<const dv2 *>(C + rbase + 16 * (kb + 1) + 8 * h);
-                nq[h] = *reinterpret_cast<const qv2 *>(CQ + rbase + 16 * (kb + 1) + 8 * h);
+                for (int s = 0; s < 4; ++s) keep[kb - T0][s] = cur[s];
             }
-        }
-        if (kb >= T0 && kb < T1) {
+            if (NH > 0) {
+                const double *B = sB + (kb & 1) * SLAB + 2 * q * LDB + acol + 16 * T0;
+                // step s reads slab row col(q, s) = 8 (s/2) + 2 q + s % 2
+                auto aop = [&](int i) {
+                    constexpr int NHp = NH > 0 ? NH : 1;
+                    const int si = i / NHp, ti = i % NHp;
+                    return B[(8 * (si >> 1) + (si & 1)) * LDB + 16 * ti];
+                };
+                double ring[3];
+                ring[0] = aop(0);
+                if (NQ > 1) ring[1] = aop(1);
 #pragma unroll
-            for (int s = 0; s < 4; ++s) keep[kb - T0][s] = cur[s];
-        }
-        if (NH > 0) {
-            const double *B = sB + (kb & 1) * SLAB + 2 * q * LDB + acol + 16 * T0;
-            // step s reads slab row col(q, s) = 8 (s/2) + 2 q + s % 2
-            auto aop = [&](int i) {
-                constexpr int NHp = NH > 0 ? NH : 1;
-                const int si = i / NHp, ti = i % NHp;
-                return B[(8 * (si >> 1) + (si & 1)) * LDB + 16 * ti];
-            };
-            double ring[3];
-            ring[0] = aop(0);
-            if (NQ > 1) ring[1] = aop(1);
+                for (int i = 0; i < NQ; ++i) {
+                    if (i + 2 < NQ) ring[(i + 2) % 3] = aop(i + 2);
+                    const int si = i / NH, ti = i % NH;
+                    acc[ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(ring[i % 3], cur[si], acc[ti], 0, 0, 0);
+                    if (PH < PER2 && i == NQ / 2 - 1 && pf) {
+                        // wide slabs go in two halves to bound the registers they
+                        // hold; the target buffer was last read before the
+                        // previous barrier
 #pragma unroll
-            for (int i = 0; i < NQ; ++i) {
-                if (i + 2 < NQ) ring[(i + 2) % 3] = aop(i + 2);
-                const int si = i / NH, ti = i % NH;
-                acc[ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(ring[i % 3], cur[si], acc[ti], 0, 0, 0);
-                if (PH < PER2 && i == NQ / 2 - 1 && kb + 1 < NT) {
-                    // wide slabs go in two halves to bound the registers they hold;
-                    // the target buffer was last read before the previous barrier
+                        for (int u = 0; u < PH; ++u) {
+                            const int idx = tid + NTH * u, rr = idx / (P / 2), c = 2 * (idx % (P / 2));
+                            if (idx < 8 * P)
+                                *reinterpret_cast<dv2 *>(nbuf + rr * LDB + c) = bpre[u];
+                        }
 #pragma unroll
-                    for (int u = 0; u < PH; ++u) {
-                        const int idx = tid + NTH * u, rr = idx / (P / 2), c = 2 * (idx % (P / 2));
-                        if (idx < 8 * P)
-                            *reinterpret_cast<dv2 *>(sB + ((kb + 1) & 1) * SLAB + rr * LDB + c) = bpre[u];
-                    }
-#pragma unroll
-                    for (int u = PH; u < PER2; ++u) {
-                        const int idx = tid + NTH * u, rr = idx / (P / 2), c = 2 * (idx % (P / 2));
-                        if (idx < 8 * P)
-                            bpre[u - PH] = *reinterpret_cast<const dv2 *>(Sinv + int64_t(16 * (kb + 1) + rr) * P + c);
+                        for (int u = PH; u < PER2; ++u) {
+                            const int idx = tid + NTH * u, rr = idx / (P / 2), c = 2 * (idx % (P / 2));
+                            if (idx < 8 * P)
+                                bpre[u - PH] = *reinterpret_cast<const dv2 *>(Sv + int64_t(nslab + rr) * P + c);
+                        }
                     }
                 }
             }
-        }
-        if (kb + 1 < NT) {
-            constexpr int U0 = PH < PER2 ? PH : 0;
+            if (pf) {
+                constexpr int U0 = PH < PER2 ? PH : 0;
 #pragma unroll
-            for (int u = U0; u < PER2; ++u) {
-                const int idx = tid + NTH * u, rr = idx / (P / 2), c = 2 * (idx % (P / 2));
-                if (idx < 8 * P)
-                    *reinterpret_cast<dv2 *>(sB + ((kb + 1) & 1) * SLAB + rr * LDB + c) = bpre[u - U0];
+                for (int u = U0; u < PER2; ++u) {
+                    const int idx = tid + NTH * u, rr = idx / (P / 2), c = 2 * (idx % (P / 2));
+                    if (idx < 8 * P)
+                        *reinterpret_cast<dv2 *>(nbuf + rr * LDB + c) = bpre[u - U0];
+                }
+            }
+            __syncthreads();
+        }
+
+        // epilogue: lane holds K[row][16 t + col(q, r)] = acc[t - T0][r] and
+        // C_prior[row][16 t + col(q, r)] = keep[t - T0][r].  The nu and R
+        // pointers pass through an empty asm statement so that their loads
+        // stay here and are not hoisted out of the tile loop (which would
+        // hold them in registers for the whole kernel).
+        const double *nu_t = nu, *rdiag_t = rdiag;
+        if (PERSIST) asm volatile("" : "+s"(nu_t), "+s"(rdiag_t));
+        double dv = 0.0, dx = 0.0;
+#pragma unroll
+        for (int t = 0; t < NH; ++t)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int c = 16 * (T0 + t) + 8 * h + 2 * q;
+                const dv2 nv = *reinterpret_cast<const dv2 *>(nu_t + c);
+                const double k0 = acc[t][2 * h], k1 = acc[t][2 * h + 1];
+                dv += k0 * keep[t][2 * h] + k1 * keep[t][2 * h + 1];
+                dx += k0 * nv[0] + k1 * nv[1];
+            }
+        // C <- K R.  A row's 16 columns of tile t sit in its 4 lanes as two
+        // 64-byte halves (h = 0: columns 0..7, h = 1: 8..15).  Lanes of rows
+        // 2j and 2j + 1 (adjacent lanes) swap one half each (DPP quad
+        // permutation [1,0,3,2]), so that every store instruction writes whole
+        // 128-byte rows: first rows 2j (the even lane's h = 0 and, from the
+        // odd lane, the even row's h = 1), then rows 2j + 1.
+        {
+            const bool odd = lr & 1;
+            const int64_t r0 = row - odd;
+            auto swap_pair = [](double x) {
+                int2 v = __builtin_bit_cast(int2, x);
+                v.x = __builtin_amdgcn_mov_dpp(v.x, 0xB1, 0xF, 0xF, false);
+                v.y = __builtin_amdgcn_mov_dpp(v.y, 0xB1, 0xF, 0xF, false);
+                return __builtin_bit_cast(double, v);
+            };
+#pragma unroll
+            for (int t = 0; t < NH; ++t) {
+                const int c0 = 16 * (T0 + t) + 2 * q;
+                const dv2 ra = *reinterpret_cast<const dv2 *>(rdiag_t + c0);
+                const dv2 rb = *reinterpret_cast<const dv2 *>(rdiag_t + c0 + 8);
+                const dv2 a = dv2{acc[t][0] * ra[0], acc[t][1] * ra[1]};   // h = 0 of own row
+                const dv2 b = dv2{acc[t][2] * rb[0], acc[t][3] * rb[1]};   // h = 1 of own row
+                const dv2 g = dv2{swap_pair(odd ? a[0] : b[0]), swap_pair(odd ? a[1] : b[1])};
+                const int cc = c0 + (odd ? 8 : 0);
+                // streaming stores: C is not read again within this pass
+                if (r0 < m) __builtin_nontemporal_store(odd ? g : a, reinterpret_cast<dv2 *>(C + r0 * P + cc));
+                if (r0 + 1 < m)
+                    __builtin_nontemporal_store(odd ? b : g, reinterpret_cast<dv2 *>(C + (r0 + 1) * P + cc));
             }
         }
+        dv += __shfl_xor(dv, 16, 64);
+        dx += __shfl_xor(dx, 16, 64);
+        dv += __shfl_xor(dv, 32, 64);
+        dx += __shfl_xor(dx, 32, 64);
+        if (q == 0) {
+            red[((PART * RG + grp) * 16 + lr) * 2 + 0] = dv;
+            red[((PART * RG + grp) * 16 + lr) * 2 + 1] = dx;
+        }
         __syncthreads();
-    }
-
-    // epilogue: lane holds K[row][16 t + col(q, r)] = acc[t - T0][r] and
-    // C_prior[row][16 t + col(q, r)] = keep[t - T0][r]
-    double dv = 0.0, dx = 0.0;
+        // the parts' sums, in a fixed order: x_hat += K nu, var += K(0) - K . C_prior
+        if (tid < 16 * RG) {
+            const int64_t r = tile * (16 * RG) + tid;
+            if (r < m) {
+                double sv = 0.0, sx = 0.0;
 #pragma unroll
-    for (int t = 0; t < NH; ++t)
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int c = 16 * (T0 + t) + 8 * h + 2 * q;
-            const dv2 nv = *reinterpret_cast<const dv2 *>(nu + c);
-            const double k0 = acc[t][2 * h], k1 = acc[t][2 * h + 1];
-            dv += k0 * keep[t][2 * h] + k1 * keep[t][2 * h + 1];
-            dx += k0 * nv[0] + k1 * nv[1];
+                for (int c = 0; c < CS; ++c) {
+                    sv += red[(c * 16 * RG + tid) * 2];
+                    sx += red[(c * 16 * RG + tid) * 2 + 1];
+                }
+                const double v = var[r] + kdiag - sv;
+                var[r] = v;
+                xhat[r] += sx;
+                if (v < 0.0) atomicAdd(negvar, 1ull);
+            }
         }
-    // C <- K R.  A row's 16 columns of tile t sit in its 4 lanes as two
-    // 64-byte halves (h = 0: columns 0..7, h = 1: 8..15).  Lanes of rows 2j
-    // and 2j + 1 (adjacent lanes) swap one half each (DPP quad permutation
-    // [1,0,3,2]), so that every store instruction writes whole 128-byte rows:
-    // first rows 2j (the even lane's h = 0 and, from the odd lane, the even
-    // row's h = 1), then rows 2j + 1.
-    {
-        const bool odd = lr & 1;
-        const int64_t r0 = row - odd;
-        auto swap_pair = [](double x) {
-            int2 v = __builtin_bit_cast(int2, x);
-            v.x = __builtin_amdgcn_mov_dpp(v.x, 0xB1, 0xF, 0xF, false);
-            v.y = __builtin_amdgcn_mov_dpp(v.y, 0xB1, 0xF, 0xF, false);
-            return __builtin_bit_cast(double, v);
-        };
-#pragma unroll
-        for (int t = 0; t < NH; ++t) {
-            const int c0 = 16 * (T0 + t) + 2 * q;
-            const dv2 ra = *reinterpret_cast<const dv2 *>(rdiag + c0);
-            const dv2 rb = *reinterpret_cast<const dv2 *>(rdiag + c0 + 8);
-            const dv2 a = dv2{acc[t][0] * ra[0], acc[t][1] * ra[1]};   // h = 0 of own row
-            const dv2 b = dv2{acc[t][2] * rb[0], acc[t][3] * rb[1]};   // h = 1 of own row
-            const dv2 g = dv2{swap_pair(odd ? a[0] : b[0]), swap_pair(odd ? a[1] : b[1])};
-            const int cc = c0 + (odd ? 8 : 0);
-            // streaming stores: C is not read again within this pass
-            if (r0 < m) __builtin_nontemporal_store(odd ? g : a, reinterpret_cast<dv2 *>(C + r0 * P + cc));
-            if (r0 + 1 < m)
-                __builtin_nontemporal_store(odd ? b : g, reinterpret_cast<dv2 *>(C + (r0 + 1) * P + cc));
-        }
-    }
-    dv += __shfl_xor(dv, 16, 64);
-    dx += __shfl_xor(dx, 16, 64);
-    dv += __shfl_xor(dv, 32, 64);
-    dx += __shfl_xor(dx, 32, 64);
-    if (q == 0) {
-        red[((PART * RG + grp) * 16 + lr) * 2 + 0] = dv;
-        red[((PART * RG + grp) * 16 + lr) * 2 + 1] = dx;
+        // `red` is written again only after the next tile's k loop, whose
+        // barriers order it after these reads
+        if (!more) break;
+        tile = next;
     }
 }
 
-template <typename TQ, int NT, int CS, int RG>
+template <typename TQ, int NT, int CS, int RG, bool PERSIST>
 __global__ void __launch_bounds__(64 * CS * RG)
-k_rowpass(int64_t m, double *C, const TQ *CQ, const double *Sinv, const double *nu,
-          const double *rdiag, double *xhat, double *var, double kdiag, const int *status,
-          unsigned long long *negvar) {
+k_rowpass(int64_t m, int64_t ntiles, double *C, const TQ *CQ, const double *Sinv,
+          const double *nu, const double *rdiag, double *xhat, double *var, double kdiag,
+          const int *status, unsigned long long *negvar) {
     using RS = RowSplit<NT, CS, RG>;
     __shared__ __align__(16) double sB[2 * RS::SLAB];
     __shared__ double red[CS * RG * 16 * 2];
     if (status[kStStep] != HIKF_OK) return;
+    if (int64_t(blockIdx.x) >= ntiles) return;
     const int part = (threadIdx.x >> 6) / RG;
+#define HIKF_RP_PART(K)                                                                        \
+    rowpass_part<TQ, NT, CS, RG, (K), PERSIST>(sB, red, m, ntiles, C, CQ, Sinv, nu, rdiag, xhat, \
+                                             var, kdiag, negvar)
     if (part == 0)
-        rowpass_part<TQ, NT, CS, RG, 0>(sB, red, m, C, CQ, Sinv, nu, rdiag);
+        HIKF_RP_PART(0);
     else if (part == 1)
-        rowpass_part<TQ, NT, CS, RG, 1>(sB, red, m, C, CQ, Sinv, nu, rdiag);
+        HIKF_RP_PART(1);
     else if (CS > 2 && part == 2)
-        rowpass_part<TQ, NT, CS, RG, (CS > 2 ? 2 : 0)>(sB, red, m, C, CQ, Sinv, nu, rdiag);
+        HIKF_RP_PART(CS > 2 ? 2 : 0);
     else if (CS > 3)
-        rowpass_part<TQ, NT, CS, RG, (CS > 3 ? 3 : 0)>(sB, red, m, C, CQ, Sinv, nu, rdiag);
-    __syncthreads();
-    const int tid = threadIdx.x;
-    if (tid < 16 * RG) {
-        const int64_t row = int64_t(blockIdx.x) * (16 * RG) + tid;
-        if (row < m) {
-            double dv = 0.0, dx = 0.0;
-#pragma unroll
-            for (int c = 0; c < CS; ++c) {
-                dv += red[(c * 16 * RG + tid) * 2];
-                dx += red[(c * 16 * RG + tid) * 2 + 1];
-            }
-            const double v = var[row] + kdiag - dv;
-            var[row] = v;
-            xhat[row] += dx;
-            if (v < 0.0) atomicAdd(negvar, 1ull);
-        }
-    }
+        HIKF_RP_PART(CS > 3 ? 3 : 0);
+#undef HIKF_RP_PART
 }
 
-}  // namespace
-
-template <typename TQ, int NT>
-hipError_t rowpass_launch(const Geometry &g, const Layout &lay, char *res, hipStream_t s) {
-    constexpr int CS = NT <= 16 ? 2 : 4;
-    constexpr int RG = NT <= 16 ? 4 : 2;     // 8 waves; 4-wave workgroups of 32 rows measured slower
+template <typename TQ, int NT, int CS, int RG, bool PERSIST>
+hipError_t rowpass_go(const Geometry &g, const Layout &lay, char *res, hipStream_t s) {
     constexpr int rows = 16 * RG;
-    const unsigned blocks = unsigned((g.m + rows - 1) / rows);
-    hipLaunchKernelGGL((k_rowpass<TQ, NT, CS, RG>), dim3(blocks), dim3(64 * CS * RG), 0, s, g.m,
+    const int64_t ntiles = (g.m + rows - 1) / rows;
+    int64_t blocks = ntiles;
+    if (PERSIST) {
+        // one resident workgroup per compute unit (the LDS slabs and the
+        // registers of an 8-wave group leave room for one)
+        blocks = g.num_cu > 0 ? g.num_cu : 256;
+        if (blocks > ntiles) blocks = ntiles;
+    }
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((k_rowpass<TQ, NT, CS, RG, PERSIST>), dim3(unsigned(blocks)),
+                       dim3(64 * CS * RG), 0, s, g.m, ntiles,
                        reinterpret_cast<double *>(res + lay.C),
                        reinterpret_cast<const TQ *>(res + lay.CQ),
                        reinterpret_cast<const double *>(res + lay.sinv),
                        reinterpret_cast<const double *>(res + lay.nu),
                        reinterpret_cast<const double *>(res + lay.rdiag),
                        reinterpret_cast<double *>(res + lay.xhat),
-                       reinterpret_cast<double *>(res + lay.var), g.kp.family == HIKF_KERNEL_TEST_R2 ? 0.0 : g.kp.theta,
+                       reinterpret_cast<double *>(res + lay.var),
+                       g.kp.family == HIKF_KERNEL_TEST_R2 ? 0.0 : g.kp.theta,
                        reinterpret_cast<const int *>(res + lay.status),
                        reinterpret_cast<unsigned long long *>(res + lay.negvar));
     return hipGetLastError();
+}
+
+}  // namespace
+
+// Row-pass variants (Geometry::rp_variant): bit 0 = persistent workgroups
+// (for an even number of 16-column blocks; otherwise ignored), bit 1 = the
+// narrow split (32-row tiles, columns in four parts) instead of 64-row tiles
+// in two column halves; p > 256 always uses the narrow split, which its
+// register budget needs.
+template <typename TQ, int NT>
+hipError_t rowpass_launch(const Geometry &g, const Layout &lay, char *res, hipStream_t s) {
+    constexpr bool kCanPersist = NT % 2 == 0;
+    const bool persist = kCanPersist && (g.rp_variant & 1);
+    const bool narrow = NT > 16 || (g.rp_variant & 2);
+    if (narrow)
+        return persist ? rowpass_go<TQ, NT, 4, 2, kCanPersist>(g, lay, res, s)
+                       : rowpass_go<TQ, NT, 4, 2, false>(g, lay, res, s);
+    return persist ? rowpass_go<TQ, NT, (NT > 16 ? 4 : 2), (NT > 16 ? 2 : 4), kCanPersist>(g, lay, res, s)
+                   : rowpass_go<TQ, NT, (NT > 16 ? 4 : 2), (NT > 16 ? 2 : 4), false>(g, lay, res, s);
 }
 
 #define HIKF_RP(N) \

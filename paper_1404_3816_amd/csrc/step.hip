@@ -192,6 +192,56 @@ k_reduce_g(int p, int cpr, const double *partial, const double *GQ, double *G, d
     }
 }
 
+// ---------------------------------------------------------------- drift check
+// With the p-space recursion, every periodic gather is also a check: the G
+// and h carried since the previous gather are compared with the gathered
+// ones (max-norm difference relative to the max-norm of the gathered value),
+// the largest drift seen so far is kept in drift[0] (G) and drift[1] (h) and
+// the number of checks in drift[2]; then the gathered values replace the
+// carried ones.  Skipped when nothing was carried (the first step, after an
+// import, or if every step since the last gather failed).
+__global__ void __launch_bounds__(256)
+k_drift(int p, const double *Gg, const double *hg, double *G, double *h, double *drift,
+        int *status) {
+    __shared__ double red[4][256];
+    if (status[kStInit] != 0) return;
+    const int t = threadIdx.x;
+    const bool carried = status[kStCarried] == 1;
+    double dg = 0.0, mg = 0.0, dh = 0.0, mh = 0.0;
+    const int64_t n = int64_t(p) * p;
+    for (int64_t i = t; i < n; i += 256) {
+        const double a = Gg[i];
+        dg = fmax(dg, fabs(G[i] - a));
+        mg = fmax(mg, fabs(a));
+    }
+    for (int i = t; i < p; i += 256) {
+        const double a = hg[i];
+        dh = fmax(dh, fabs(h[i] - a));
+        mh = fmax(mh, fabs(a));
+    }
+    red[0][t] = dg;
+    red[1][t] = mg;
+    red[2][t] = dh;
+    red[3][t] = mh;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s)
+            for (int k = 0; k < 4; ++k) red[k][t] = fmax(red[k][t], red[k][t + s]);
+        __syncthreads();
+    }
+    if (t == 0 && carried) {
+        const double rg = red[1][0] > 0.0 ? red[0][0] / red[1][0] : red[0][0];
+        const double rh = red[3][0] > 0.0 ? red[2][0] / red[3][0] : red[2][0];
+        drift[0] = fmax(drift[0], rg);
+        drift[1] = fmax(drift[1], rh);
+        drift[2] += 1.0;
+    }
+    __syncthreads();
+    for (int64_t i = t; i < n; i += 256) G[i] = Gg[i];
+    for (int i = t; i < p; i += 256) h[i] = hg[i];
+    if (t == 0) status[kStCarried] = 0;
+}
+
 // ---------------------------------------------------------------- history
 // Covariance queries need every applied step's prior cross-covariance C_s
 // and S_s^{-1}.  The slot of a step is the number of steps applied before
@@ -315,9 +365,22 @@ void run_gather(const Geometry &g, const Layout &lay, char *res, bool with_c, do
 template <typename TQ>
 hipError_t run_step(const Geometry &g, const Layout &lay, char *res, const double *y,
                     hipStream_t s, Timing *tm, bool gather, bool advance) {
-    if (gather)
+    if (gather && !advance) {
         run_gather<TQ>(g, lay, res, true, reinterpret_cast<double *>(res + lay.G),
                        reinterpret_cast<double *>(res + lay.hvec), s, tm);
+    } else if (gather) {
+        // recursion mode: gather aside, compare with the carried G, h, keep
+        // the gathered ones
+        run_gather<TQ>(g, lay, res, true, reinterpret_cast<double *>(res + lay.Gg),
+                       reinterpret_cast<double *>(res + lay.hg), s, tm);
+        hipLaunchKernelGGL(k_drift, dim3(1), dim3(256), 0, s, g.p,
+                           reinterpret_cast<const double *>(res + lay.Gg),
+                           reinterpret_cast<const double *>(res + lay.hg),
+                           reinterpret_cast<double *>(res + lay.G),
+                           reinterpret_cast<double *>(res + lay.hvec),
+                           reinterpret_cast<double *>(res + lay.drift),
+                           reinterpret_cast<int *>(res + lay.status));
+    }
     const long long *steps = reinterpret_cast<const long long *>(res + lay.steps);
     if (g.history)
         hipLaunchKernelGGL(k_hist_c<TQ>, dim3(grid_for(g.m * g.p)), dim3(256), 0, s, g.m * g.p,

@@ -52,7 +52,9 @@ def problem_from_csr(dim, n, rowptr, col, val, r_diag, family="powexp", theta=1.
 
 
 def make_options(n_c=4, precision="f32", direct=False, timing=False, graph=False, riccati=0,
-                 history=0, sparse=False):
+                 history=0, sparse=False, rowpass_variant=None, tune_cache=None):
+    """hikf_options; rowpass_variant None = automatic (tuning cache or the
+    built-in default), else the variant 0..3 to force."""
     op = H.hikf_options()
     op.n_c = int(n_c)
     op.fmm_precision = PRECISIONS[precision]
@@ -62,6 +64,8 @@ def make_options(n_c=4, precision="f32", direct=False, timing=False, graph=False
     op.riccati = int(riccati)
     op.history = int(history)
     op.sparse = 1 if sparse else 0
+    op.rowpass_variant = 0 if rowpass_variant is None else 1 + int(rowpass_variant)
+    op.tune_cache = tune_cache.encode() if tune_cache else None
     return op
 
 
@@ -90,16 +94,24 @@ class HikfFilter:
                          ctypes.c_void_p(self.scratch.data_ptr()), self.info.scratch_bytes,
                          _stream_handle(stream), ctypes.byref(self.handle))
         H.check(st, "hikf_init")
+        if stream is not None:
+            # init's work is queued on `stream`: tell torch's allocator, so the
+            # regions are not handed out for other streams' work before it ends
+            self.scratch.record_stream(stream)
+            self.resident.record_stream(stream)
         if not keep_scratch:
             # the scratch region may be reused once init's work has finished;
-            # torch's allocator orders the reuse on this stream
+            # torch's allocator orders the reuse after `stream` (or the
+            # current stream) has passed this point
             self.scratch = None
 
     def step(self, y, x_out=None, var_out=None, stream=None):
         """Queue one assimilation step with measurement y (p doubles on the device)."""
-        y = y.contiguous()
-        assert y.dtype == torch.float64 and y.numel() == self.p and y.is_cuda
-        st = H.hikf_step(self.handle, ctypes.c_void_p(y.data_ptr()),
+        yc = y.contiguous()
+        assert yc.dtype == torch.float64 and yc.numel() == self.p and yc.is_cuda
+        if stream is not None and yc is not y:
+            yc.record_stream(stream)          # a temporary read on `stream`
+        st = H.hikf_step(self.handle, ctypes.c_void_p(yc.data_ptr()),
                          ctypes.c_void_p(x_out.data_ptr() if x_out is not None else None),
                          ctypes.c_void_p(var_out.data_ptr() if var_out is not None else None),
                          _stream_handle(stream))
@@ -121,10 +133,15 @@ class HikfFilter:
         return x, v, c
 
     def import_state(self, x=None, var=None, c=None, stream=None):
-        ptr = (lambda t: ctypes.c_void_p(t.contiguous().data_ptr()) if t is not None
+        ts = [None if t is None else t.contiguous() for t in (x, var, c)]
+        if stream is not None:
+            for t, orig in zip(ts, (x, var, c)):
+                if t is not None and t is not orig:
+                    t.record_stream(stream)   # temporaries read on `stream`
+        ptr = (lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None
                else ctypes.c_void_p(None))
-        H.check(H.hikf_import_state(self.handle, ptr(x), ptr(var), ptr(c), _stream_handle(stream)),
-                "hikf_import_state", self.handle)
+        H.check(H.hikf_import_state(self.handle, ptr(ts[0]), ptr(ts[1]), ptr(ts[2]),
+                                    _stream_handle(stream)), "hikf_import_state", self.handle)
 
     def cov_apply(self, v, stream=None):
         """P_{t|t} v for the current step t (needs options.history >= t)."""

@@ -58,13 +58,14 @@ class hikf_problem(ctypes.Structure):
 class hikf_options(ctypes.Structure):
     _fields_ = [("n_c", c_i32), ("fmm_precision", c_i32), ("direct", c_i32),
                 ("timing", c_i32), ("riccati", c_i32), ("history", c_i32), ("graph", c_i32),
-                ("sparse", c_i32)]
+                ("sparse", c_i32), ("rowpass_variant", c_i32), ("reserved1", c_i32),
+                ("tune_cache", ctypes.c_char_p)]
 
 
 class hikf_plan_info(ctypes.Structure):
     _fields_ = [("resident_bytes", c_sz), ("scratch_bytes", c_sz), ("m", c_i64),
                 ("depth", c_i32), ("r", c_i32), ("near_pairs", c_i64), ("far_pairs", c_i64),
-                ("query_bytes", c_sz)]
+                ("query_bytes", c_sz), ("rowpass_variant", c_i32), ("reserved3", c_i32)]
 
 
 HIKF_NUM_PHASES = 12
@@ -76,7 +77,10 @@ class hikf_stats(ctypes.Structure):
     _fields_ = [("steps_applied", c_i64), ("last_status", c_i32), ("init_status", c_i32),
                 ("min_pivot", c_dbl), ("negative_variances", c_i64),
                 ("time_ms", c_dbl * HIKF_NUM_PHASES),
-                ("time_count", c_i64 * HIKF_NUM_PHASES)]
+                ("time_count", c_i64 * HIKF_NUM_PHASES),
+                ("rowpass_variant", c_i32), ("reserved2", c_i32),
+                ("riccati_drift_g", c_dbl), ("riccati_drift_h", c_dbl),
+                ("riccati_checks", c_i64)]
 
 
 _P = ctypes.POINTER

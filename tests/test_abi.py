@@ -125,6 +125,11 @@ def test_step_batch_rejects_bad_arguments_without_a_device():
     arr = ctypes.c_void_p * 2
     assert H.hikf_step_batch(arr(None, None), arr(None, None), None, None, 2,
                              None) == H.HIKF_E_INVALID
+    # the same filter twice (the handles are never dereferenced: the check
+    # comes first)
+    fake, y = 4096, 8192
+    assert H.hikf_step_batch(arr(fake, fake), arr(y, y), None, None, 2,
+                             None) == H.HIKF_E_INVALID
 
 
 def test_plan_bf16_modes_add_split_operands():
@@ -177,3 +182,49 @@ def test_plan_query_bytes_only_with_history():
     op.history = -1
     assert H.hikf_plan(ctypes.byref(pr), ctypes.byref(op), ctypes.byref(info)) == H.HIKF_E_INVALID
     assert H.hikf_cov_apply(None, None, None, None, 0, None) == H.HIKF_E_INVALID
+
+
+def test_plan_rowpass_variant_range():
+    from paper_1404_3816_amd import hikf as H
+    pr = _problem(dim=2, n=64, p=32)
+    op = H.hikf_options()
+    op.n_c, op.fmm_precision = 4, H.HIKF_FMM_F32
+    info = H.hikf_plan_info()
+    for v in range(5):
+        op.rowpass_variant = v
+        assert H.hikf_plan(ctypes.byref(pr), ctypes.byref(op), ctypes.byref(info)) == H.HIKF_OK
+    for v in (-1, 5):
+        op.rowpass_variant = v
+        assert H.hikf_plan(ctypes.byref(pr), ctypes.byref(op),
+                           ctypes.byref(info)) == H.HIKF_E_INVALID
+
+
+def test_plan_reads_tuning_cache(tmp_path):
+    # the tuning cache entry with the same p and C_Q type and the nearest m
+    # chooses the variant; a forced variant wins; no match -> default 0
+    import json
+    from paper_1404_3816_amd import hikf as H
+    cache = tmp_path / "tune.json"
+    cache.write_text(json.dumps({"device": "x", "rowpass": [
+        {"p": 32, "cq": "f32", "m": 4096, "variant": 3, "ms": [1, 1, 1, 0.5]},
+        {"p": 32, "cq": "f32", "m": 10 ** 6, "variant": 1, "ms": [1, 0.5, 1, 1]},
+        {"p": 32, "cq": "f64", "m": 4096, "variant": 2, "ms": [1, 1, 0.5, None]},
+        {"p": 64, "cq": "f32", "m": 4096, "variant": 1, "ms": [1, 0.5, 1, 1]}]}, indent=1))
+
+    def variant(n, p, prec, forced=0, path=str(cache)):
+        pr = _problem(dim=2, n=n, p=p)
+        op = H.hikf_options()
+        op.n_c, op.fmm_precision, op.rowpass_variant = 4, prec, forced
+        op.tune_cache = path.encode() if path else None
+        info = H.hikf_plan_info()
+        assert H.hikf_plan(ctypes.byref(pr), ctypes.byref(op), ctypes.byref(info)) == H.HIKF_OK
+        return info.rowpass_variant
+
+    assert variant(64, 32, H.HIKF_FMM_F32) == 3           # m = 4096
+    assert variant(1024, 32, H.HIKF_FMM_F32) == 1         # m = 1M: nearest entry
+    assert variant(64, 32, H.HIKF_FMM_F64) == 2
+    assert variant(64, 64, H.HIKF_FMM_F32) == 1
+    assert variant(64, 48, H.HIKF_FMM_F32) == 0           # no entry for p = 48
+    assert variant(64, 32, H.HIKF_FMM_F32, forced=3) == 2  # forced variant 2
+    assert variant(64, 32, H.HIKF_FMM_F32, path=None) == 0
+    assert variant(64, 32, H.HIKF_FMM_F32, path=str(tmp_path / "missing.json")) == 0

@@ -169,3 +169,114 @@ def test_riccati_import_forces_a_gather():
     fb.close()
     assert float(((xb - xa).norm() / xa.norm())) < 1e-12
     assert float(((vb - va).norm() / va.norm())) < 1e-12
+
+
+@pytest.mark.parametrize("p", [64, 96, 256, 512])
+def test_rowpass_variants_agree(p):
+    # the four launch forms of the row pass: K, hence C_post, is summed in the
+    # same order in all of them (bitwise equal); x_hat and the variance add
+    # the column parts' dot products in two or four groups (rounding only);
+    # the persistent form equals its one-tile-per-workgroup twin bitwise
+    import torch
+    from paper_1404_3816_amd import filter as F
+    case = Case(2, 96, p, ell=0.2, steps=3)
+    y = torch.as_tensor(case.ys, device="cuda")
+    out = {}
+    for v in (0, 1, 2, 3):
+        pr, keep = F.problem_from_csr(2, case.n, case.rowptr, case.col, case.val, case.r_diag,
+                                      **case.kparams())
+        f = F.HikfFilter(pr, F.make_options(4, "f64", False, rowpass_variant=v,
+                                            graph=(v == 1)), keep)
+        for k in range(case.steps):
+            f.step(y[k])
+        st = f.query()
+        assert st.last_status == 0 and st.steps_applied == case.steps
+        out[v] = (st.rowpass_variant, f.export_state())
+        f.close()
+    for v in (1, 2, 3):
+        eff, (x, var, c) = out[v]
+        x0, v0, c0 = out[0][1]
+        assert torch.equal(c, c0), v
+        assert torch.allclose(x, x0, rtol=1e-12, atol=1e-14 * x0.abs().max().item()), v
+        assert torch.allclose(var, v0, rtol=1e-12, atol=1e-14), v
+    for v in (0, 1, 2, 3):
+        assert out[v][0] == v
+        assert all(torch.equal(a, b) for a, b in zip(out[v][1], out[v ^ 1][1])), v
+
+
+def test_tune_cache_is_read_by_init(tmp_path):
+    # hikf_init takes the row-pass variant from the tuning cache entry with
+    # the same p and C_Q type and the nearest m
+    import json
+    import torch
+    from paper_1404_3816_amd import filter as F
+    case = Case(2, 64, 32, ell=0.2, steps=1)
+    cache = tmp_path / "tune.json"
+    cache.write_text(json.dumps({"device": "x", "rowpass": [
+        {"p": 32, "cq": "f32", "m": 4096, "variant": 3, "ms": [1, 1, 1, 0.5]},
+        {"p": 32, "cq": "f32", "m": 10 ** 6, "variant": 1, "ms": [1, 0.5, 1, 1]},
+        {"p": 32, "cq": "f64", "m": 4096, "variant": 2, "ms": [1, 1, 0.5, 1]},
+        {"p": 64, "cq": "f32", "m": 4096, "variant": 1, "ms": [1, 0.5, 1, 1]}]}))
+    got = {}
+    for prec in ("f32", "f64"):
+        pr, keep = F.problem_from_csr(2, case.n, case.rowptr, case.col, case.val, case.r_diag,
+                                      **case.kparams())
+        f = F.HikfFilter(pr, F.make_options(4, prec, False, tune_cache=str(cache)), keep)
+        f.step(torch.as_tensor(case.ys[0], device="cuda"))
+        got[prec] = f.query().rowpass_variant
+        f.close()
+    assert got == {"f32": 3, "f64": 2}
+    # no cache, or a cache without a matching entry: the built-in default (0)
+    pr, keep = F.problem_from_csr(2, case.n, case.rowptr, case.col, case.val, case.r_diag,
+                                  **case.kparams())
+    f = F.HikfFilter(pr, F.make_options(4, "f32", False, tune_cache=str(tmp_path / "none")),
+                     keep)
+    assert f.query().rowpass_variant == 0
+    f.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("riccati", [1, 3])
+def test_recursion_matches_oracle_and_reports_drift(precision, riccati):
+    # G and h carried by the exact p-space recursion between gathers (period
+    # `riccati`): the filter still matches the oracle's literal cross-
+    # covariance filter on the same C_Q (the oracle's FP64 bbFMM product, so
+    # FP32 mode is held to its C_Q bound times the sensitivity ceiling), and
+    # every gather after the first measures the drift of the carried values,
+    # which is rounding only
+    from helpers import CQ_TOL, KAPPA, max_step_rel, rel
+    case = Case(2, 64, 32, ell=0.1, gamma=2.0, steps=4)
+    cq, xs, vs, stats = case.gpu_run(n_c=5, precision=precision, riccati=riccati)
+    ref = case.cq_bbfmm(5)
+    xb, vb = case.tier_b(ref)
+    ex, ev = max_step_rel(xs, xb), max_step_rel(vs, vb)
+    print(f"recursion period {riccati} ({precision}): x {ex:.3e} var {ev:.3e}, drift "
+          f"G {stats.riccati_drift_g:.3e} h {stats.riccati_drift_h:.3e} "
+          f"over {stats.riccati_checks} checks")
+    assert stats.last_status == 0 and stats.steps_applied == case.steps
+    assert stats.riccati_checks == (case.steps - 1) // riccati
+    assert stats.riccati_drift_g < 1e-10 and stats.riccati_drift_h < 1e-10
+    if precision == "f64":
+        assert ex < 1e-9 and ev < 1e-10
+    else:
+        kx, kv = KAPPA[("fmm", 64, 32, 5)]
+        assert rel(cq, ref) < CQ_TOL["f32"]
+        assert ex < kx * CQ_TOL["f32"] and ev < kv * CQ_TOL["f32"]
+
+
+def test_recursion_drift_is_not_checked_after_import():
+    # an imported state has nothing carried: the next gather is no check
+    import torch
+    case = Case(2, 64, 32, ell=0.1, steps=4)
+    f = _filter(case, riccati=2)
+    y = torch.as_tensor(case.ys, device="cuda")
+    f.step(y[0])
+    f.step(y[1])
+    x, v, c = f.export_state()
+    f.import_state(x, v, c)
+    f.step(y[2])                          # forced gather: no check
+    st = f.query()
+    assert st.riccati_checks == 0 and st.steps_applied == 3
+    f.step(y[3])                          # carried, not gathered (period 2)
+    assert f.query().riccati_checks == 0
+    f.close()

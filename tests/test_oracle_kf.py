@@ -219,3 +219,39 @@ def test_random_walk_truth_follows_the_model():
         off += m + p
         np.testing.assert_allclose(xs[k], x, rtol=1e-14, atol=1e-14)
         np.testing.assert_allclose(ys[k], y, rtol=1e-14, atol=1e-14)
+
+
+def test_pspace_recursion_identity():
+    # The GPU may carry G = H C_prior and h = H x_hat across steps instead of
+    # gathering them from the rows of C.  Both follow from the posterior
+    # cross-covariance identity C_post = K R (= C_prior - K G, Sec. 3.1 eq.
+    # eqn_KF_pred_new with S - R = G):  H C_post = G S^{-1} R, so the next
+    # prior G is G S^{-1} R + H C_Q; and H x_hat_post = h + G S^{-1} nu.
+    # Pinned here on the literal tier-B recursion, without any GPU.
+    w = synth.workload("crosswell-32x32-p16")
+    n, p, m = w["n"], w["p"], w["m"]
+    rp, col, val = synth.crosswell_h(2, n, p)
+    H = cq_exact.h_dense(rp, col, val, m)
+    Q = kernels.dense_q(synth.cell_centres(2, n), "powexp", 1.0, 0.3, 1.0)
+    CQ = Q @ H.T
+    GQ = H @ CQ
+    R = 1e-4 * np.eye(p)
+    _, ys = truth.random_walk_stream(Q, H, 1e-4, 5, 0)
+    C, x = CQ.copy(), np.zeros(m)
+    G_rec = h_rec = None
+    for y in ys:
+        C = C + CQ
+        G = H @ C
+        h = H @ x
+        if G_rec is not None:
+            assert _rel(G_rec, G) < 1e-12 and _rel(h_rec, h) < 1e-12
+        S = 0.5 * (G + G.T) + R
+        K = np.linalg.solve(S, C.T).T
+        nu = y - h
+        Sinv = np.linalg.inv(S)
+        G_rec = G @ Sinv @ R + GQ
+        h_rec = h + G @ Sinv @ nu
+        x = x + K @ nu
+        C = C - K @ G
+        # the recursion's value for H C_post, before the next prediction
+        assert _rel(H @ C, G @ Sinv @ R) < 1e-11
