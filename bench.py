@@ -20,6 +20,7 @@ import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -54,6 +55,16 @@ def parse():
     ap.add_argument("--w", default="sparse", choices=["dense", "sparse"],
                     help="FMM source side: dense W = H^T, or the nonzeros of H bucketed by leaf")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the accuracy job against the full-size oracle references")
+    ap.add_argument("--eager", action="store_true",
+                    help="time eager launches with phase events instead of the step graph")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the row-pass autotuning (use --tune-cache as it is, or the default)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="tuning cache to read and update (default: a file in the temp dir)")
+    ap.add_argument("--phase-jobs", type=int, default=2,
+                    help="jobs of the separate phase-timed pass (eager launches, HIP events)")
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="approximate seconds of CPU work for the oracle sample")
     ap.add_argument("--serving", action="store_true",
@@ -96,10 +107,22 @@ def measured_traffic(workload, kernel):
     return None
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, assim_steps, budget):
     """The FP64 oracle on a bounded sample of the workload, scaled to the
-    whole job: exact C_Q by FFT (oracle tier C) on a few right-hand sides and
-    cross-covariance steps (tier B) on a subset of rows."""
+    whole job: exact C_Q by FFT (oracle tier C) on some of the p right-hand
+    sides, and one cross-covariance step (tier B) on a subset of the rows,
+    with the workload's own sparse H restricted to those rows."""
+    import scipy.sparse as sp
     from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import cq_exact, kf_crosscov
@@ -107,6 +130,9 @@ def cpu_baseline(w, assim_steps, budget):
 
     dim, n, p, m = w["dim"], w["n"], w["p"], w["m"]
     rowptr, col, val = synth.crosswell_h(dim, n, p, planes=8)
+    Hfull = sp.csr_matrix((val, col, rowptr), shape=(p, m))
+    cells = np.unique(col)
+
     def fft_cols(cols):
         Ht = np.zeros((m, cols))
         for a in range(cols):
@@ -116,17 +142,16 @@ def cpu_baseline(w, assim_steps, budget):
         return time.perf_counter() - t0
 
     def tier_b_rows(rows, steps):
-        rng = np.random.default_rng(0)
-        Hs = np.zeros((p, rows))
-        for a in range(p):
-            Hs[a, rng.choice(rows, 8, replace=False)] = 1.0 / n
-        # Q = I on the sample keeps H C_Q positive semidefinite; the cost of
-        # the dense FP64 work does not depend on the values
-        CQ = np.ascontiguousarray(Hs.T)
-        ys = rng.standard_normal((steps, p)) * 1e-2
+        # the first `rows` ray cells: H restricted to them is the workload's
+        # own operator on that sample; C_Q := H_s^T keeps S positive definite
+        # (the cost of the dense FP64 work does not depend on the values)
+        sub = cells[:rows] if rows <= len(cells) else np.arange(rows)
+        Hs = Hfull[:, sub].tocsr()
+        CQ = np.ascontiguousarray(Hs.T.toarray())
+        ys = np.random.default_rng(0).standard_normal((steps, p)) * 1e-2
         t0 = time.perf_counter()
-        kf_crosscov.crosscov_kf(CQ, Hs, w["r_var"] * np.eye(p), np.zeros(rows), CQ,
-                                np.ones(rows), 1.0, ys)
+        kf_crosscov.crosscov_kf(CQ, Hs, w["r_var"] * np.eye(p), np.zeros(len(sub)), CQ,
+                                np.ones(len(sub)), 1.0, ys)
         return time.perf_counter() - t0
 
     def measure(budget):
@@ -153,13 +178,51 @@ def cpu_baseline(w, assim_steps, budget):
     job1 = t_cq1 + assim_steps * t_step1
     return {
         "value": assim_steps / job, "unit": "assim steps/s", "cores": int(threads),
-        "kind": "oracle",
+        "kind": "oracle", "cpu": cpu_model(),
         "sample": (f"exact C_Q by FFT on {cols} of {p} rays ({t_fft:.1f} s, scaled x{p / cols:g}); "
-                   f"1 cross-covariance step on {rows} of {m} rows ({t_b:.1f} s, scaled "
-                   f"x{m / rows:g}); job = C_Q + {assim_steps} steps = {job:.0f} s"),
+                   f"1 cross-covariance step on {rows} of {m} rows with the workload's sparse H "
+                   f"({t_b:.1f} s, scaled x{m / rows:g}); job = C_Q + {assim_steps} steps = "
+                   f"{job:.0f} s"),
         "cq_fft_s": round(t_cq, 2), "step_s": round(t_step, 4),
         "single_thread": {"value": assim_steps / job1, "cq_fft_s": round(t_cq1, 2),
                           "step_s": round(t_step1, 4)},
+    }
+
+
+def accuracy_report(workload, K, x_rows, v_rows, cq_rows, stats):
+    """Relative errors of the GPU's x_hat_k, diag P_k and C_Q on the report
+    rows against the full-size oracle references (tests/golden): eps_total
+    against the filter with the exact C_Q, eps_H2 of the oracle's own FP64
+    black-box FMM (the Chebyshev order's error), eps_arith of the GPU against
+    that oracle filter; max over the steps (Sec. 4.3 normwise metric)."""
+    path = os.path.join(ROOT, "tests", "golden", f"fullsize_{workload}.npz")
+    if not os.path.exists(path):
+        return None
+    ref = np.load(path, allow_pickle=False)
+    if int(ref["steps"]) != K:
+        return None
+
+    def mrel(a, b):
+        return float(max(np.linalg.norm(a[k] - b[k]) / np.linalg.norm(b[k]) for k in range(len(b))))
+
+    def split(gpu, exact, fmm):
+        return {"eps_total": mrel(gpu, exact), "eps_H2": mrel(fmm, exact),
+                "eps_arith": mrel(gpu, fmm)}
+
+    def crel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    return {
+        "reference": "oracle cross-covariance filter (FP64) with exact C_Q and with the oracle's "
+                     "FP64 bbFMM C_Q, on the ray cells plus report rows",
+        "rows": int(len(ref["rows"])), "steps": K,
+        "x_hat": split(x_rows, ref["x_exact"], ref["x_bbfmm"]),
+        "var": split(v_rows, ref["var_exact"], ref["var_bbfmm"]),
+        "C_Q": {"eps_total": crel(cq_rows, ref["cq_exact"]),
+                "eps_H2": crel(ref["cq_bbfmm"], ref["cq_exact"]),
+                "eps_arith": crel(cq_rows, ref["cq_bbfmm"])},
+        "negative_variances": int(stats.negative_variances),
+        "min_cholesky_pivot_last_step": float(stats.min_pivot),
     }
 
 
@@ -285,12 +348,35 @@ def main():
     pr, keep = F.problem_from_csr(dim, n, rowptr, col, val, np.full(p, w["r_var"]),
                                   theta=w["theta"], ell=w["ell"], gamma=w["gamma"],
                                   prior=w["prior"])
-    op = F.make_options(n_c, a.precision, False, timing=True, riccati=a.riccati,
-                        sparse=a.w == "sparse")
-    info = F.plan(pr, op)
+    # the timed jobs replay each step as the HIP graph captured at init (no
+    # per-phase events); a separate pass with eager launches and HIP events
+    # around every phase gives the kernel times and the roofline
+    graph = not a.eager
+    ydev = torch.as_tensor(ys, dtype=torch.float64, device="cuda").contiguous()
+    # autotuning: every launch form of the row pass is timed on this problem
+    # and the winner recorded in a tuning cache, which hikf_init then reads
+    tuned = None
+    cache = a.tune_cache or os.path.join(tempfile.gettempdir(), "hikf_tune_cache.json")
+    if not a.no_tune:
+        from paper_1404_3816_amd import tune as T
+        best, ms = T.tune_problem(pr, keep, dict(n_c=n_c, precision=a.precision,
+                                                 sparse=a.w == "sparse", riccati=a.riccati),
+                                  ydev, steps=6, repeats=2)
+        T.merge_entry(cache, {"p": p, "cq": "f64" if a.precision == "f64" else "f32", "m": m,
+                              "variant": int(best),
+                              "ms": [round(ms[v], 4) if v in ms else None for v in T.VARIANTS],
+                              "workload": a.workload})
+        tuned = {"rowpass_candidates_ms": {str(v): round(t, 4) for v, t in ms.items()},
+                 "cache": cache}
+        log(f"[bench] row-pass launch forms (ms): {tuned['rowpass_candidates_ms']}, best {best}")
+    tc = cache if os.path.exists(cache) else None
+    op_run = F.make_options(n_c, a.precision, False, timing=not graph, graph=graph,
+                            riccati=a.riccati, sparse=a.w == "sparse", tune_cache=tc)
+    op_phase = F.make_options(n_c, a.precision, False, timing=True, graph=False,
+                              riccati=a.riccati, sparse=a.w == "sparse", tune_cache=tc)
+    info = F.plan(pr, op_run)
     resident = torch.empty(int(info.resident_bytes), dtype=torch.uint8, device="cuda")
     scratch = torch.empty(int(info.scratch_bytes), dtype=torch.uint8, device="cuda")
-    ydev = torch.as_tensor(ys, dtype=torch.float64, device="cuda").contiguous()
     stream = torch.cuda.current_stream()
     sh = ctypes.c_void_p(stream.cuda_stream)
     if a.calibrate_copy_mib:
@@ -305,20 +391,31 @@ def main():
         f"{info.scratch_bytes / 2**30:.2f} GiB, depth {info.depth}, near pairs "
         f"{info.near_pairs}, far pairs {info.far_pairs}")
 
-    def job(latencies):
+    def job(op, latencies=None, probe=None):
         handle = ctypes.c_void_p()
         H.check(H.hikf_init(ctypes.byref(pr), ctypes.byref(op),
                             ctypes.c_void_p(resident.data_ptr()), info.resident_bytes,
                             ctypes.c_void_p(scratch.data_ptr()), info.scratch_bytes, sh,
                             ctypes.byref(handle)), "hikf_init")
+        if probe is not None:
+            H.check(H.hikf_export_cq(handle, ctypes.c_void_p(probe["cq"].data_ptr()), sh),
+                    "hikf_export_cq", handle)
+            probe["cq_rows"] = probe["cq"][probe["rows"]].clone()
         for k in range(K):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            H.check(H.hikf_step(handle, ctypes.c_void_p(ydev[k].data_ptr()), None, None, sh),
+            if latencies is not None:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            xo = ctypes.c_void_p(probe["x"].data_ptr()) if probe is not None else None
+            vo = ctypes.c_void_p(probe["v"].data_ptr()) if probe is not None else None
+            H.check(H.hikf_step(handle, ctypes.c_void_p(ydev[k].data_ptr()), xo, vo, sh),
                     "hikf_step", handle)
-            e1.record(stream)
-            latencies.append((e0, e1))
+            if latencies is not None:
+                e1.record(stream)
+                latencies.append((e0, e1))
+            if probe is not None:
+                probe["xs"][k] = probe["x"][probe["rows"]]
+                probe["vs"][k] = probe["v"][probe["rows"]]
         return handle
 
     def finish(handle):
@@ -328,7 +425,7 @@ def main():
         return st
 
     for i in range(a.warmup):
-        st = finish(job([]))
+        st = finish(job(op_run))
         log(f"[bench] warmup job {i + 1}/{a.warmup} done (status {st.last_status}, "
             f"steps {st.steps_applied})")
     torch.cuda.synchronize()
@@ -336,7 +433,7 @@ def main():
     handles = []
     t0 = time.perf_counter()
     for i in range(a.steps):
-        handles.append(job(lat))
+        handles.append(job(op_run, lat))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stats = [finish(h) for h in handles]
@@ -344,24 +441,32 @@ def main():
     if last.last_status != 0 or last.steps_applied != K:
         raise SystemExit(f"bench: filter reported status {last.last_status} after "
                          f"{last.steps_applied} of {K} steps")
-    log(f"[bench] timed {a.steps} jobs in {t1 - t0:.3f} s")
+    log(f"[bench] timed {a.steps} jobs in {t1 - t0:.3f} s ({'graph' if graph else 'eager'} steps, "
+        f"row-pass variant {last.rowpass_variant})")
     lat_ms = np.array([e0.elapsed_time(e1) for e0, e1 in lat])
+
+    # phase pass: eager launches with HIP events on the launch stream
+    pstats = [finish(job(op_phase)) for _ in range(a.phase_jobs)]
+    torch.cuda.synchronize()
+    log(f"[bench] phase-timed pass: {a.phase_jobs} jobs")
     tot = np.zeros(H.HIKF_NUM_PHASES)
     cnt = np.zeros(H.HIKF_NUM_PHASES)
-    for s in stats:
-        tot += np.array(s.time_ms[:])
-        cnt += np.array(s.time_count[:])
+    for s_ in pstats:
+        tot += np.array(s_.time_ms[:])
+        cnt += np.array(s_.time_count[:])
     avg = {name: (tot[i] / cnt[i] if cnt[i] else None) for i, name in enumerate(H.PHASES)}
 
     # roofline of the dominant kernel: the fused row pass, 2 m p^2 FP64 flops
     row_s = avg["rowpass"] / 1e3
     row_tflops = 2.0 * m * p * p / row_s / 1e12
+    tqb = 8 if a.precision == "f64" else 4
     roof = {"bound": "mfma", "achieved": round(row_tflops, 3), "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s", "frac": round(row_tflops / PEAK_FP64_TFLOPS, 4),
             "traffic": measured_traffic(a.workload, "k_rowpass"), "traffic_unit": "bytes/launch",
-            "algorithmic_bytes": (8 + 4 + 8) * m * p, "kernel": "k_rowpass (FP64 MFMA)",
-            "avg_ms": round(avg["rowpass"], 4)}
-    tq = 8 if a.precision == "f64" else 4
+            "algorithmic_bytes": (8 + tqb + 8) * m * p, "kernel": "k_rowpass (FP64 MFMA)",
+            "avg_ms": round(avg["rowpass"], 4), "launches": int(cnt[H.PHASES.index("rowpass")]),
+            "timed_in": "phase pass (eager launches, HIP events on the launch stream)"}
+    tq = tqb
     # M2L and P2P run on FP64 / FP32 MFMA, or on BF16 MFMA (three products per
     # FP32 product with the refinement terms): frac is issued work over peak
     issue = {"f64": 1, "f32": 1, "bf16x3": 3, "bf16": 1}[a.precision]
@@ -393,6 +498,25 @@ def main():
                       "frac_hbm": round(by / avg["p2m"] / 1e6 / PEAK_HBM_GBS, 4)}
     init_ms = sum(avg[k] or 0.0 for k in ("operators", "p2m", "m2m", "m2l", "l2l", "p2p", "init"))
 
+    # accuracy: one more job in the timed configuration, x_hat / diag P on the
+    # report rows of the full-size oracle references after every step
+    acc = None
+    if not a.no_accuracy:
+        path = os.path.join(ROOT, "tests", "golden", f"fullsize_{a.workload}.npz")
+        if os.path.exists(path) and n_c == w["n_c"]:
+            rows = np.load(path, allow_pickle=False)["rows"]
+            rd = torch.as_tensor(rows, device="cuda")
+            probe = {"rows": rd, "cq": torch.empty(m, p, dtype=torch.float64, device="cuda"),
+                     "x": torch.empty(m, dtype=torch.float64, device="cuda"),
+                     "v": torch.empty(m, dtype=torch.float64, device="cuda"),
+                     "xs": torch.empty(K, len(rows), dtype=torch.float64, device="cuda"),
+                     "vs": torch.empty(K, len(rows), dtype=torch.float64, device="cuda")}
+            ast = finish(job(op_run, probe=probe))
+            acc = accuracy_report(a.workload, K, probe["xs"].cpu().numpy(),
+                                  probe["vs"].cpu().numpy(), probe["cq_rows"].cpu().numpy(), ast)
+            del probe
+            log(f"[bench] accuracy: {json.dumps(acc)}")
+
     wall = t1 - t0
     result = {
         "metric": "assim steps/s at m=1M,p=256; Q·H^T MFMA/HBM % of peak; p50/p99 step latency",
@@ -406,15 +530,25 @@ def main():
                    "kernel": f"theta*exp(-(r/{w['ell']})^{w['gamma']:g})",
                    "fmm_dtype": a.precision, "step_dtype": "f64",
                    "assim_steps_per_job": K, "gather_every": a.riccati or 1, "fmm_w": a.w,
+                   "step_launch": "hip graph per step" if graph else "eager, phase events",
+                   "rowpass_variant": int(last.rowpass_variant),
+                   "rowpass_form": ("persistent" if last.rowpass_variant & 1 else "one tile per "
+                                    "workgroup") + (", 32-row tiles x 4 column parts"
+                                                    if (last.rowpass_variant & 2 or p > 256)
+                                                    else ", 64-row tiles x 2 column halves"),
                    "parallelism": "none (1 GPU)"},
         "warm_steps_per_s": round(1e3 / float(np.mean(lat_ms)), 2),
         "step_latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
                             "p99": round(float(np.percentile(lat_ms, 99)), 4),
-                            "mean": round(float(np.mean(lat_ms)), 4)},
+                            "mean": round(float(np.mean(lat_ms)), 4),
+                            "timed_in": "timed jobs (host-stream events around each hikf_step)"},
         "init_ms_kernels": round(init_ms, 3),
         "phase_avg_ms": {k: (round(v, 4) if v is not None else None) for k, v in avg.items()},
+        "phase_timed_in": "phase pass (eager launches, HIP events on the launch stream)",
         "roofline": roof,
         "fmm_roofline": fmm,
+        "accuracy": acc,
+        "autotune": tuned,
     }
     if not a.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample ...")
