@@ -131,14 +131,31 @@ def interaction_counts(dim, n, leaf):
     return near, far
 
 
+def lowrank_basis(T_list, eps):
+    """Common basis of a level's M2L operators (the SVD compression of the
+    black-box FMM): the left singular vectors of [T_o1 T_o2 ...] whose
+    singular values are at least eps times the largest.  The kernel is
+    symmetric and the interaction list closed under o -> -o (T_-o = T_o^T),
+    so the same basis serves the sources.  Returns U (r x k)."""
+    fat = np.hstack(T_list)
+    U, sv, _ = np.linalg.svd(fat, full_matrices=False)
+    k = int((sv >= eps * sv[0]).sum()) if sv[0] > 0 else 1
+    return U[:, :max(k, 1)]
+
+
 def bbfmm_apply(dim, n, W, nc, leaf=None, family="powexp", theta=1.0,
-                ell=1.0, gamma=1.0):
+                ell=1.0, gamma=1.0, svd_eps=None):
     """Approximate Q @ W (W is (m, p) in grid order) by the black-box FMM.
 
     An N that is not leaf * 2^D is handled by the padded-tree reading: the
     tree covers Npad = padded_size(N, leaf) cells per axis of the same size
     h = 1/N (root box [0, Npad h]^dim), the cells beyond N carry zero weight,
-    and only the N^dim real rows are returned."""
+    and only the N^dim real rows are returned.
+
+    svd_eps: if given, every level's M2L runs in the compressed form
+    U (U^T T_o U) (U^T M) with the basis U of ``lowrank_basis`` at that
+    relative singular-value threshold (the low-rank M2L of the black-box
+    FMM; ranks follow the decay of the operators' singular values)."""
     if leaf is None:
         leaf = 8 if dim == 2 else 4
     W = np.asarray(W, np.float64)
@@ -150,12 +167,12 @@ def bbfmm_apply(dim, n, W, nc, leaf=None, family="powexp", theta=1.0,
         Wp = np.zeros((npad,) * dim + (p,))
         Wp[(slice(0, n),) * dim] = W.reshape((n,) * dim + (p,))
         out = _bbfmm_tree(dim, npad, 1.0 / n, Wp.reshape(npad ** dim, p), nc, leaf,
-                          family, theta, ell, gamma)
+                          family, theta, ell, gamma, svd_eps)
         return out.reshape((npad,) * dim + (p,))[(slice(0, n),) * dim].reshape(n ** dim, p)
-    return _bbfmm_tree(dim, n, 1.0 / n, W, nc, leaf, family, theta, ell, gamma)
+    return _bbfmm_tree(dim, n, 1.0 / n, W, nc, leaf, family, theta, ell, gamma, svd_eps)
 
 
-def _bbfmm_tree(dim, n, h, W, nc, leaf, family, theta, ell, gamma):
+def _bbfmm_tree(dim, n, h, W, nc, leaf, family, theta, ell, gamma, svd_eps=None):
     """The FMM passes on a tree of n = leaf * 2^D cells per axis of side h
     (grid-order layout of ``W`` and of the result, the first axis fastest)."""
     K = kernel(family, theta, ell, gamma)
@@ -201,18 +218,25 @@ def _bbfmm_tree(dim, n, h, W, nc, leaf, family, theta, ell, gamma):
         for lev in range(2, D + 1):
             nb = 2 ** lev
             s = n * h / nb                                # box side
-            acc = np.zeros_like(M[lev])
+            Ts = {}
             for o in il_offsets(dim):
                 diff = s * (np.asarray(o)[None, None, :]
                             + 0.5 * (xi_vec[None, :, :] - xi_vec[:, None, :]))
-                T = K(np.sqrt((diff * diff).sum(-1)))    # (k tgt, k' src)
+                Ts[o] = K(np.sqrt((diff * diff).sum(-1)))    # (k tgt, k' src)
+            Mlev = M[lev]
+            if svd_eps is not None:
+                U = lowrank_basis(list(Ts.values()), svd_eps)
+                Ts = {o: U.T @ T @ U for o, T in Ts.items()}
+                Mlev = np.matmul(U.T, Mlev)               # compressed multipoles
+            acc = np.zeros(Mlev.shape)
+            for o, T in Ts.items():
                 tb = [_il_axis_targets(nb, v) for v in o]
                 if any(len(t) == 0 for t in tb):
                     continue
                 sb = [t + v for t, v in zip(tb, o)]
-                src = M[lev][np.ix_(*sb)]
+                src = Mlev[np.ix_(*sb)]
                 acc[np.ix_(*tb)] += np.matmul(T, src)
-            L[lev] = acc
+            L[lev] = np.matmul(U, acc) if svd_eps is not None else acc
         # 5. L2L, levels 2 .. D-1 -> children
         for lev in range(2, D):
             for c in itertools.product((0, 1), repeat=dim):

@@ -78,3 +78,55 @@ def crosscov_gain_identity(C_prior, G, R):
     cf = sla.cho_factor(S, lower=True)
     K = sla.cho_solve(cf, C_prior.T).T
     return C_prior - K @ G, K @ R
+
+
+def psd_part(A):
+    """The nearest symmetric positive semidefinite matrix to sym(A) in the
+    Frobenius norm: its eigendecomposition with the negative eigenvalues set
+    to zero (LAPACK symmetric eigensolver via NumPy)."""
+    A = 0.5 * (np.asarray(A, np.float64) + np.asarray(A, np.float64).T)
+    w, V = np.linalg.eigh(A)
+    return (V * np.clip(w, 0.0, None)) @ V.T
+
+
+def crosscov_kf_guarded(CQ, H, R, x0, C0, var0, qdiag, ys, G0=None):
+    """Tier B with the measurement-space prior kept positive semidefinite.
+
+    The H^2 approximation of a smooth kernel makes H Q H^T (which enters
+    every step's G = H C_prior) indefinite; the random walk adds it every
+    step, so S = (G + G^T)/2 + R eventually fails its Cholesky.  This variant
+    carries G and h = H x_hat by the exact recursions of the cross-covariance
+    update (C_post = K R gives H C_post = G S^{-1} R, and H x_hat_post =
+    h + G S^{-1} nu), with H Q H^T replaced by its PSD part GQp:
+        G_{t+1|t} = G_{t|t-1} S^{-1} R + GQp,   h <- h + G S^{-1} nu,
+    starting from G_{1|0} = H C_0 + GQp (G0, when given, overrides it; for
+    the kernel prior P_0 = Q the start is 2 GQp) and h = H x_0.  Both p-space
+    quantities then describe one PSD measurement-space model, so S stays SPD
+    and the innovation loop is stable; the rows of C, x_hat and the variances
+    are updated as in ``crosscov_kf`` (with C_post = K R).
+    Returns (xs, variances).
+    """
+    H = _as_operator(H)
+    R = np.asarray(R, np.float64)
+    C = np.array(C0, np.float64, copy=True)
+    x = np.array(x0, np.float64, copy=True)
+    var = np.array(var0, np.float64, copy=True)
+    GQp = psd_part(H @ CQ)
+    G = np.array(G0, np.float64, copy=True) if G0 is not None else H @ C + GQp
+    h = H @ x
+    xs, vs = [], []
+    for y in np.atleast_2d(ys):
+        C = C + CQ
+        var = var + qdiag
+        S = 0.5 * (G + G.T) + R
+        cf = sla.cho_factor(S, lower=True)
+        K = sla.cho_solve(cf, C.T).T
+        nu = y - h
+        x = x + K @ nu
+        var = var - np.einsum("ij,ij->i", K, C)
+        C = K @ R
+        h = h + G @ sla.cho_solve(cf, nu)
+        G = G @ sla.cho_solve(cf, R) + GQp
+        xs.append(x.copy())
+        vs.append(var.copy())
+    return np.array(xs), np.array(vs)

@@ -154,3 +154,47 @@ def test_convergence_trend_of_paper_table():
     # like the table's 1e4 / 1e5 rows at 7 nodes: the accuracy does not
     # depend on the number of unknowns at a fixed kernel and node count
     assert abs(np.log10(errs[256][2] / errs[128][2])) < 0.5
+
+
+def test_lowrank_m2l_full_rank_is_the_plain_fmm():
+    # a threshold of 0 keeps every singular vector: U is orthogonal and
+    # U (U^T T U)(U^T M) = T M
+    rng = np.random.default_rng(9)
+    W = rng.standard_normal((64 * 64, 2))
+    plain = bbfmm.bbfmm_apply(2, 64, W, 4, 8, "powexp", 1.0, 0.1, 1.0)
+    full = bbfmm.bbfmm_apply(2, 64, W, 4, 8, "powexp", 1.0, 0.1, 1.0, svd_eps=0.0)
+    assert _rel(full, plain) < 1e-13
+
+
+@pytest.mark.parametrize("dim,n,nc,ell,gamma", [(2, 128, 5, 0.05, 2.0), (3, 32, 4, 0.2, 1.0)])
+def test_lowrank_m2l_error_follows_the_threshold(dim, n, nc, ell, gamma):
+    # the compressed M2L adds an error of about the threshold (relative to the
+    # far field) on top of the Chebyshev error, and keeps fewer than r ranks
+    rng = np.random.default_rng(10)
+    W = rng.standard_normal((n ** dim, 2))
+    plain = bbfmm.bbfmm_apply(dim, n, W, nc, None, "powexp", 1.0, ell, gamma)
+    errs = []
+    for eps in (1e-3, 1e-5, 1e-7):
+        lr = bbfmm.bbfmm_apply(dim, n, W, nc, None, "powexp", 1.0, ell, gamma, svd_eps=eps)
+        errs.append(_rel(lr, plain))
+        assert errs[-1] < 20 * eps
+    # a smaller threshold never keeps fewer ranks
+    assert errs[0] >= errs[1] >= errs[2] and errs[0] > errs[2]
+
+
+def test_lowrank_basis_rank_and_orthonormality():
+    from oracle.kernels import kernel
+    K = kernel("powexp", 1.0, 0.05, 2.0)
+    xi = bbfmm.cheb_nodes(5)
+    xv = xi[bbfmm._multi(5, 2)]
+    s = 1.0 / 128                                        # level 7 of a unit square
+    Ts = []
+    for o in bbfmm.il_offsets(2):
+        diff = s * (np.asarray(o)[None, None, :] + 0.5 * (xv[None, :, :] - xv[:, None, :]))
+        Ts.append(K(np.sqrt((diff * diff).sum(-1))))
+    U = bbfmm.lowrank_basis(Ts, 1e-5)
+    assert U.shape[0] == 25 and 1 <= U.shape[1] < 25
+    np.testing.assert_allclose(U.T @ U, np.eye(U.shape[1]), atol=1e-13)
+    # each operator is reproduced to the threshold by its projection
+    for T in Ts:
+        assert np.linalg.norm(U @ (U.T @ T @ U) @ U.T - T) <= 1e-4 * np.linalg.norm(np.hstack(Ts))
