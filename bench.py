@@ -59,6 +59,8 @@ def parse():
                     help="skip the accuracy job against the full-size oracle references")
     ap.add_argument("--eager", action="store_true",
                     help="time eager launches with phase events instead of the step graph")
+    ap.add_argument("--m2l-eps", type=float, default=0.0,
+                    help="low-rank M2L: relative singular-value threshold of the bases (0: dense)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the row-pass autotuning (use --tune-cache as it is, or the default)")
     ap.add_argument("--tune-cache", default=None,
@@ -70,8 +72,11 @@ def parse():
     ap.add_argument("--serving", action="store_true",
                     help="instead of the job benchmark: a serving mix of filters stepped "
                          "by hikf_step_batch under Poisson request arrivals")
-    ap.add_argument("--streams", type=int, default=16, help="serving: filters")
-    ap.add_argument("--requests", type=int, default=2000, help="serving: requests per run")
+    ap.add_argument("--streams", type=int, default=64, help="serving: filters")
+    ap.add_argument("--requests", type=int, default=10000, help="serving: requests per run")
+    ap.add_argument("--slots", type=int, default=8, help="serving: device streams")
+    ap.add_argument("--serving-budget-gb", type=float, default=0.0,
+                    help="serving: HBM budget of the filters (default 70%% of free memory)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the jobs, run one plain device copy of this many MiB "
                          "(reference kernel for hardware byte counters)")
@@ -227,96 +232,124 @@ def accuracy_report(workload, K, x_rows, v_rows, cq_rows, stats):
 
 
 def serving(a):
-    """Serving mix: `streams` filters of different sizes, requests arriving as a
-    Poisson process with uniform stream ids.  The dispatcher takes, per round,
-    the oldest pending request of every stream that has one (per-stream order
-    is kept), steps them with one hikf_step_batch call on one stream, and
-    waits for it; a request's latency runs from its arrival to the end of its
-    round.  First a closed loop (all requests at time zero) gives the
-    saturation rate, then Poisson runs at 0.5x, 0.9x and 1.2x of it (the last
-    one overloaded: its queue, and so its latency, grows over the run)."""
-    import collections
-
+    """Serving mix (paper_1404_3816_amd/serve.py): `streams` filters of
+    different sizes, kernels and ray counts; requests (one assimilation step
+    each) arrive as a Poisson process with uniform stream ids.  The server
+    dispatches continuously on `slots` device streams and admits filters by
+    an HBM budget; the plain path steps one filter at a time on the same
+    request sequence.  First closed loops (every request at time zero) give
+    each path's saturation rate, then Poisson runs at 0.5x and 0.9x of the
+    server's saturation measure the latency of both; a last server run with
+    half the memory the filters need exercises eviction and re-admission."""
     import torch
 
     import synth
-    from paper_1404_3816_amd import filter as F
+    from paper_1404_3816_amd import serve as SV
 
     torch.cuda.set_device(0)
     cfgs = synth.serving_streams(a.streams, seed=1)
-    filters, ys, xo, vo = [], [], [], []
-    t0 = time.perf_counter()
-    for c in cfgs:
+    specs = []
+    for i, c in enumerate(cfgs):
         rowptr, col, val = synth.crosswell_h(2, c["n"], c["p"])
-        pr, keep = F.problem_from_csr(2, c["n"], rowptr, col, val, np.full(c["p"], c["r_var"]),
-                                      theta=c["theta"], ell=c["ell"], gamma=c["gamma"],
-                                      prior=c["prior"])
-        filters.append(F.HikfFilter(pr, F.make_options(c["n_c"], "f32", False, graph=True), keep))
-        # measurement values do not change the work of a step
-        ys.append(torch.as_tensor(synth.normal_draws(c["seed"], a.requests, c["p"]) * 1e-2,
-                                  device="cuda"))
-        xo.append(torch.empty(c["m"], dtype=torch.float64, device="cuda"))
-        vo.append(torch.empty(c["m"], dtype=torch.float64, device="cuda"))
+        specs.append(SV.StreamSpec(2, c["n"], rowptr, col, val, np.full(c["p"], c["r_var"]),
+                                   theta=c["theta"], ell=c["ell"], gamma=c["gamma"],
+                                   n_c=c["n_c"], precision=c["precision"], prior=c["prior"],
+                                   psd_guard=c["psd_guard"], name=f"s{i}"))
+    # measurement streams: seeded draws (the work of a step does not depend
+    # on them); every run takes the next requests of each stream's sequence
+    per_stream = a.requests * 6 // len(cfgs) + 64
+    ys = [torch.as_tensor(synth.normal_draws(c["seed"], per_stream, c["p"]) * 1e-2,
+                          device="cuda") for c in cfgs]
+    cursor = [0] * len(cfgs)
+    sizes = [SV._Stream(sp, sp.plan().resident_bytes, 0).resident_bytes for sp in specs]
+    resident = sum(sizes)
+    free, total = torch.cuda.mem_get_info()
+    budget = int(a.serving_budget_gb * 2**30) if a.serving_budget_gb else int(0.7 * free)
+    log(f"[serving] {len(specs)} streams ({sum(c['gamma'] == 2.0 for c in cfgs)} Gaussian), "
+        f"resident regions {resident / 2**30:.1f} GiB, budget {budget / 2**30:.1f} GiB")
+
+    def requests(rate, seed, cursor):
+        arr, sid = synth.poisson_requests(a.requests, len(cfgs), rate, seed)
+        out = []
+        for i in range(a.requests):
+            s = int(sid[i])
+            out.append(SV.Request(i, s, float(arr[i]), ys[s][cursor[s] % per_stream]))
+            cursor[s] += 1
+        return out
+
+    def served(server, rate, seed):
+        rq = requests(rate, seed, cursor)
+        t0 = time.perf_counter()
+        server.run(rq)
+        return SV.latency_summary(rq, time.perf_counter() - t0)
+
+    server = SV.Server(specs, budget, slots=a.slots)
+    t0 = time.perf_counter()
+    server.run(requests(None, 98, cursor))                       # admission + warm-up
+    log(f"[serving] warm-up (admits every stream) {time.perf_counter() - t0:.1f} s")
+    runs = {"server": {}, "sequential": {}}
+    runs["server"]["saturation"] = served(server, None, 2)
+    sat = runs["server"]["saturation"]["achieved_per_s"]
+    log(f"[serving] server closed loop: {runs['server']['saturation']}")
+    for frac, sd in ((0.5, 3), (0.9, 4)):
+        runs["server"][f"poisson_{frac}x"] = served(server, frac * sat, sd)
+        log(f"[serving] server at {frac} x saturation: {runs['server'][f'poisson_{frac}x']}")
+    stats = server.query()
+    failed = [i for i, st in enumerate(stats) if st is not None and st.last_status != 0]
+    server_states = server.final_states()
+    server_counts = [st.steps_done for st in server.streams]
+    server.close()
+    del server
     torch.cuda.synchronize()
-    log(f"[serving] {len(filters)} filters built in {time.perf_counter() - t0:.1f} s")
-    step_of = [0] * len(filters)
 
-    def run(rate, seed):
-        arr, sid = synth.poisson_requests(a.requests, len(filters), rate, seed)
-        queues = [collections.deque() for _ in filters]
-        lat, done, i = [], 0, 0
-        t_start = time.perf_counter()
-        while done < a.requests:
-            now = time.perf_counter() - t_start
-            while i < a.requests and arr[i] <= now:
-                queues[sid[i]].append(arr[i])
-                i += 1
-            batch = [s for s in range(len(filters)) if queues[s]]
-            if not batch:
-                time.sleep(max(0.0, min(1e-3, arr[i] - now)))
-                continue
-            yb = []
-            for s in batch:
-                yb.append(ys[s][step_of[s] % a.requests])
-                step_of[s] += 1
-            F.step_batch([filters[s] for s in batch], yb, [xo[s] for s in batch],
-                         [vo[s] for s in batch])
-            torch.cuda.synchronize()
-            t_done = time.perf_counter() - t_start
-            for s in batch:
-                lat.append(t_done - queues[s].popleft())
-            done += len(batch)
-        wall = time.perf_counter() - t_start
-        lat = np.array(lat) * 1e3
-        return {"offered_per_s": rate, "achieved_per_s": round(a.requests / wall, 1),
-                "p50_ms": round(float(np.percentile(lat, 50)), 3),
-                "p99_ms": round(float(np.percentile(lat, 99)), 3)}
-
-    run(None, 99)                                       # warm-up
-    sat = run(None, 2)
-    log(f"[serving] closed loop: {sat}")
-    runs = [sat]
-    for frac, sd in ((0.5, 3), (0.9, 4), (1.2, 5)):
-        r = run(frac * sat["achieved_per_s"], sd)
-        log(f"[serving] {frac} x saturation: {r}")
-        runs.append(r)
-    stats = [f.query() for f in filters]
-    failed = [{"stream": i, "status": st.last_status, "steps": st.steps_applied,
-               "min_pivot": st.min_pivot, "n": cfgs[i]["n"], "p": cfgs[i]["p"]}
-              for i, st in enumerate(stats) if st.last_status != 0]
-    if failed:
-        log(f"[serving] filters whose last step failed: {failed}")
+    # the plain path: one filter at a time, the same request sequences
+    cursor2 = [0] * len(cfgs)
+    filters = SV.run_sequential(specs, requests(None, 98, cursor2))
+    for name, rate, sd in (("saturation", None, 2), ("poisson_0.5x", 0.5 * sat, 3),
+                           ("poisson_0.9x", 0.9 * sat, 4)):
+        rq = requests(rate, sd, cursor2)
+        t0 = time.perf_counter()
+        filters = SV.run_sequential(specs, rq, filters=filters)
+        runs["sequential"][name] = SV.latency_summary(rq, time.perf_counter() - t0)
+        log(f"[serving] sequential {name}: {runs['sequential'][name]}")
+    # each stream's state after the same requests, in the mix and alone
+    same = 0
+    for k, f in enumerate(filters):
+        if f is None or server_states[k] is None:
+            continue
+        x, v, _ = f.export_state()
+        same += int(torch.equal(x.cpu(), server_states[k][0]) and
+                    torch.equal(v.cpu(), server_states[k][1]))
+    active = sum(1 for k, f in enumerate(filters) if f is not None and server_states[k] is not None)
     for f in filters:
-        f.close()
+        if f is not None:
+            f.close()
+    torch.cuda.synchronize()
+
+    # a budget of half the resident regions: streams are evicted and re-admitted
+    small = SV.Server(specs, max(resident // 2, max(sizes)), slots=a.slots)
+    cursor3 = [0] * len(cfgs)
+    t0 = time.perf_counter()
+    rq = requests(None, 2, cursor3)[:max(1, a.requests // 5)]
+    small.run(rq)
+    evict_run = SV.latency_summary(rq, time.perf_counter() - t0)
+    evict_run.update({k: int(v) for k, v in small.stats.items()})
+    small.close()
+    log(f"[serving] half-memory closed loop: {evict_run}")
     mean_flops = float(np.mean([2.0 * c["m"] * c["p"] ** 2 for c in cfgs]))
     print(json.dumps({
         "metric": "serving requests/s (assimilation steps over a mixed set of filters)",
-        "value": sat["achieved_per_s"], "unit": "requests/s", "n_gpus": 1,
-        "higher_is_better": True, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"serving-{len(filters)}-streams", "requests": a.requests,
-                   "streams": [{k: c[k] for k in ("n", "p", "gamma", "ell", "n_c")} for c in cfgs],
+        "value": runs["server"]["saturation"]["achieved_per_s"], "unit": "requests/s",
+        "n_gpus": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"serving-{len(cfgs)}-streams", "requests_per_run": a.requests,
+                   "slots": a.slots, "budget_gib": round(budget / 2**30, 1),
+                   "resident_gib": round(resident / 2**30, 2),
+                   "streams": [{k: c[k] for k in ("n", "p", "gamma", "ell", "n_c", "precision",
+                                                  "psd_guard")} for c in cfgs],
                    "mean_row_pass_flops": mean_flops},
-        "runs": runs, "failed_filters": failed,
+        "runs": runs, "half_memory_run": evict_run,
+        "mix_equals_solo": {"streams_compared": active, "bitwise_equal": same},
+        "failed_streams": failed, "steps_per_stream": server_counts,
     }), flush=True)
 
 
@@ -360,7 +393,8 @@ def main():
     if not a.no_tune:
         from paper_1404_3816_amd import tune as T
         best, ms = T.tune_problem(pr, keep, dict(n_c=n_c, precision=a.precision,
-                                                 sparse=a.w == "sparse", riccati=a.riccati),
+                                                 sparse=a.w == "sparse", riccati=a.riccati,
+                                                 m2l_eps=a.m2l_eps),
                                   ydev, steps=6, repeats=2)
         T.merge_entry(cache, {"p": p, "cq": "f64" if a.precision == "f64" else "f32", "m": m,
                               "variant": int(best),
@@ -371,9 +405,11 @@ def main():
         log(f"[bench] row-pass launch forms (ms): {tuned['rowpass_candidates_ms']}, best {best}")
     tc = cache if os.path.exists(cache) else None
     op_run = F.make_options(n_c, a.precision, False, timing=not graph, graph=graph,
-                            riccati=a.riccati, sparse=a.w == "sparse", tune_cache=tc)
+                            riccati=a.riccati, sparse=a.w == "sparse", tune_cache=tc,
+                            m2l_eps=a.m2l_eps)
     op_phase = F.make_options(n_c, a.precision, False, timing=True, graph=False,
-                              riccati=a.riccati, sparse=a.w == "sparse", tune_cache=tc)
+                              riccati=a.riccati, sparse=a.w == "sparse", tune_cache=tc,
+                              m2l_eps=a.m2l_eps)
     info = F.plan(pr, op_run)
     resident = torch.empty(int(info.resident_bytes), dtype=torch.uint8, device="cuda")
     scratch = torch.empty(int(info.scratch_bytes), dtype=torch.uint8, device="cuda")
@@ -530,6 +566,8 @@ def main():
                    "kernel": f"theta*exp(-(r/{w['ell']})^{w['gamma']:g})",
                    "fmm_dtype": a.precision, "step_dtype": "f64",
                    "assim_steps_per_job": K, "gather_every": a.riccati or 1, "fmm_w": a.w,
+                   "m2l": (f"low-rank, threshold {a.m2l_eps:g}, ranks per level "
+                           f"{[k for k in last.m2l_ranks if k]}" if a.m2l_eps > 0 else "dense"),
                    "step_launch": "hip graph per step" if graph else "eager, phase events",
                    "rowpass_variant": int(last.rowpass_variant),
                    "rowpass_form": ("persistent" if last.rowpass_variant & 1 else "one tile per "

@@ -148,18 +148,54 @@ typedef struct hikf_options {
                                 entry of tune_cache for this p and C_Q type
                                 (nearest m) when tune_cache names a readable
                                 cache, else the built-in default.  1 + v
-                                forces variant v = 0..3: v & 1 persistent
+                                forces variant v = 0..7: v & 1 persistent
                                 workgroups (one per compute unit, looping over
-                                row tiles; needs p / 16 even, else ignored),
-                                v & 2 32-row tiles with the columns in four
-                                parts instead of 64-row tiles in two halves
-                                (always the case for p > 256).  Results do not
-                                depend on the variant.                        */
+                                row tiles; in the 8-wave forms p / 16 must be
+                                even, else ignored), v & 2 32-row tiles with
+                                the columns in four parts instead of 64-row
+                                tiles in two halves (always the case for
+                                p > 256), v & 4 the dual form: 4-wave
+                                workgroups, one wave per SIMD holding two row
+                                groups (built for p = 64, 128, 256; ignored
+                                otherwise).  Results do not depend on the
+                                variant beyond the order in which x_hat and
+                                the variance add their column parts.          */
     int32_t reserved1;
     const char *tune_cache;  /* path of a JSON tuning cache written by the
                                 package's tuner (python -m
                                 paper_1404_3816_amd.tune), or NULL; read by
                                 hikf_init only                                */
+    int32_t psd_guard;       /* 1: keep the measurement-space prior positive
+                                semidefinite.  The H^2 approximation of a
+                                smooth kernel makes H Q H^T indefinite by
+                                about its error; every step adds it, and
+                                S = H P H^T + R then fails its Cholesky after
+                                a number of steps set by the most negative
+                                eigenvalue (for Gaussian kernels within tens
+                                of steps even at n_c = 8).  With the guard,
+                                hikf_init replaces H C_Q by its PSD part (the
+                                nearest PSD matrix; never farther from the
+                                exact H Q H^T) and G = H C_prior, h = H x_hat
+                                are carried by the exact p-space recursion
+                                (see riccati) from H C_0 + that part (2 x it
+                                for P_0 = Q) and H x_0.  riccati = N >= 1
+                                then only checks the carried values against a
+                                gather every N-th step (riccati_drift_*).
+                                0: off (the literal algorithm).               */
+    int32_t reserved4;
+    double m2l_eps;          /* > 0: low-rank M2L (the SVD compression of the
+                                black-box FMM).  Per level the translations
+                                share a basis U of rank k: the left singular
+                                vectors of all of the level's M2L operators
+                                with singular values at least m2l_eps times
+                                the largest (Sec. 3.2 cites theorems that fix
+                                the rank for an accuracy).  Multipoles are
+                                compressed by U^T, translated by U^T T U
+                                (k x k) and expanded by U, so a list entry
+                                costs 2 k^2 p instead of 2 r^2 p.  The ranks
+                                are in hikf_stats.m2l_ranks.  hikf_init then
+                                synchronises its stream once (the bases are
+                                computed on the host).  0: dense r x r M2L.   */
 } hikf_options;
 
 /* Phases timed when hikf_options.timing = 1 (indices of hikf_stats.time_ms). */
@@ -188,7 +224,7 @@ typedef struct hikf_plan_info {
     int64_t near_pairs;      /* (target leaf, source leaf) pairs in P2P       */
     int64_t far_pairs;       /* interaction-list pairs over all M2L levels    */
     size_t query_bytes;      /* scratch needed by hikf_cov_apply              */
-    int32_t rowpass_variant; /* the row-pass variant hikf_init will use (0..3):
+    int32_t rowpass_variant; /* the row-pass variant hikf_init will use (0..7):
                                 forced by the options, else from tune_cache,
                                 else the built-in default                     */
     int32_t reserved3;
@@ -203,7 +239,7 @@ typedef struct hikf_stats {
                                 over all steps since init (no clamping)       */
     double time_ms[HIKF_NUM_PHASES];     /* summed event time per phase       */
     int64_t time_count[HIKF_NUM_PHASES]; /* timed executions per phase        */
-    int32_t rowpass_variant; /* row-pass variant in use (0..3, see options)    */
+    int32_t rowpass_variant; /* row-pass variant in use (0..7, see options)    */
     int32_t reserved2;
     /* Drift of the p-space recursion (options.riccati >= 1): at every
      * periodic gather the carried G = H C_prior and h = H x_hat are compared
@@ -213,6 +249,8 @@ typedef struct hikf_stats {
     double riccati_drift_g;
     double riccati_drift_h;
     int64_t riccati_checks;
+    int32_t m2l_ranks[20];   /* rank of the low-rank M2L at each tree level
+                                (0 where unused: levels 0-1, dense M2L)       */
 } hikf_stats;
 
 typedef struct hikf_filter hikf_filter;
@@ -222,7 +260,7 @@ typedef struct hikf_filter hikf_filter;
  * no device memory and allocates nothing.
  * Errors: HIKF_E_INVALID (dim not 2/3, N < 1, p < 1, nnz < 0, theta/ell not
  * positive, gamma outside (0, 2], n_c outside 1..8, rowpass_variant outside
- * 0..4, NULL arrays),
+ * 0..8, psd_guard not 0 or 1, m2l_eps outside [0, 1), NULL arrays),
  * HIKF_E_UNSUPPORTED (p not a multiple of 16 or above 512, n_c^dim above
  * 64, a tree of 2^31 cells or more).  Any N >= 1 is accepted: the tree
  * covers Npad = leaf * 2^D >= N cells per axis (leaf 8 in 2-D, 4 in 3-D) of
@@ -333,10 +371,48 @@ hikf_status hikf_export_state(hikf_filter *f, double *x_dev, double *var_dev,
                               double *c_dev, void *stream);
 
 /* Overwrite the state from caller device buffers (same layouts; NULL keeps
- * that part).  Used for checkpoint / resume. */
+ * that part).  The next step gathers G and h from the imported rows (with
+ * the PSD guard, which has no gather, use hikf_import_checkpoint).  For a
+ * checkpoint that carries its step count and problem identity, use
+ * hikf_export_checkpoint / hikf_import_checkpoint. */
 hikf_status hikf_import_state(hikf_filter *f, const double *x_dev,
                               const double *var_dev, const double *c_dev,
                               void *stream);
+
+/* Identity and position of a checkpoint (filled by hikf_export_checkpoint). */
+typedef struct hikf_checkpoint_info {
+    uint64_t problem_hash;   /* digest of H, R, x_0, grid, kernel, prior and
+                                the options that shape the state (n_c, FMM
+                                arithmetic, direct, sparse, psd_guard)        */
+    int64_t steps_applied;   /* steps applied when the checkpoint was taken   */
+    int64_t steps_issued;    /* steps issued (the recursion's gather period)  */
+    int32_t p;               /* measurements; pspace_dev holds p*p + p values */
+    int32_t carried;         /* 1: G and h were carried (recursion or guard) */
+} hikf_checkpoint_info;
+
+/*
+ * Checkpoint: x_hat (m), diag P (m), C (m*p), and the p-space state
+ * pspace_dev = [G (p*p, row-major) | h (p)] that the recursion or the PSD
+ * guard carries (any pointer may be NULL to skip that part), plus *info.
+ * Synchronises the stream (the step count is read from the device).
+ * Errors: HIKF_E_INVALID (NULL filter or info), HIKF_E_DEVICE.
+ */
+hikf_status hikf_export_checkpoint(hikf_filter *f, double *x_dev, double *var_dev,
+                                   double *c_dev, double *pspace_dev,
+                                   hikf_checkpoint_info *info, void *stream);
+
+/*
+ * Resume from a checkpoint of a filter built from the same problem and
+ * options: the parts given are copied in, the step count is restored, and
+ * with pspace_dev (and info->carried) the carried G, h are restored so the
+ * next step continues exactly as the exported filter's would have.
+ * Errors (nothing is copied): HIKF_E_INVALID (NULL filter or info, a
+ * problem hash or p that differs from this filter's, or the PSD guard
+ * without pspace_dev), HIKF_E_DEVICE.
+ */
+hikf_status hikf_import_checkpoint(hikf_filter *f, const double *x_dev, const double *var_dev,
+                                   const double *c_dev, const double *pspace_dev,
+                                   const hikf_checkpoint_info *info, void *stream);
 
 /*
  * Copy C_Q = Q H^T (m x p, grid order, p contiguous) widened to FP64 into

@@ -50,6 +50,7 @@ Layout make_layout(const Geometry &g) {
     L.Gg = take(p * p * 8);
     L.hg = take(p * 8);
     L.drift = take(3 * 8);
+    L.hash = take(8);
     L.resident_bytes = off;
 
     off = 0;
@@ -66,6 +67,7 @@ Layout make_layout(const Geometry &g) {
         L.W = take(size_t(g.mpad) * p * tq);
     }
     L.knear = take(size_t(g.dim == 2 ? 9 : 27) * kLeafPts * kLeafPts * tq);
+    if (g.psd_guard) L.psw = take(3 * p * p * 8);
     if (g.far) {
         const size_t r = size_t(g.r);
         L.sleaf = take(r * kLeafPts * tq);
@@ -77,6 +79,20 @@ Layout make_layout(const Geometry &g) {
         }
         ml_bytes = off - L.ML_level[2];
         L.L_base = take(ml_bytes);
+    }
+    if (g.far && g.m2l_eps > 0.0) {
+        // low-rank M2L: Gram matrices and bases per level (FP64), the
+        // per-slot products W, the compressed operators and the compress /
+        // expand operators (pass precision), compressed M and L of a level
+        const size_t r = size_t(g.r), rr = r * r, nlev = size_t(g.depth - 1);
+        L.lrA = take(nlev * rr * 8);
+        L.lrU = take(nlev * rr * 8);
+        L.lrW = take(size_t(g.noff()) * rr * 8);
+        L.lrC = take(nlev * g.noff() * rr * tq);
+        L.lrUt = take(nlev * rr * tq);
+        L.lrUe = take(nlev * rr * tq);
+        L.lrM = take(size_t(g.boxes(g.depth)) * r * p * tq);
+        L.lrL = take(size_t(g.boxes(g.depth)) * r * p * tq);
     }
     if (g.fmm_prec == HIKF_FMM_BF16X3 || g.fmm_prec == HIKF_FMM_BF16) {
         // BF16 hi / lo operands: W per leaf as [column][point], multipoles per
@@ -258,7 +274,7 @@ int cached_rowpass_variant(const char *path, int p, bool cq64, int64_t m) {
         const long ep_p = strtol(vp.c_str(), &ep, 10);
         const double em = strtod(vm.c_str(), nullptr);
         const long ev = strtol(vv.c_str(), nullptr, 10);
-        if (ep_p != p || vcq != (cq64 ? "f64" : "f32") || ev < 0 || ev > 3 || !(em > 0)) continue;
+        if (ep_p != p || vcq != (cq64 ? "f64" : "f32") || ev < 0 || ev > 7 || !(em > 0)) continue;
         const double d = fabs(log(em / double(m)));
         if (d < best_d) {
             best_d = d;
@@ -323,7 +339,11 @@ hikf_status build_geometry(const hikf_problem *pr, const hikf_options *op, Geome
     g->fmm_prec = op->fmm_precision;
     g->prior = pr->prior_kind;
     if (op->history < 0 || op->history > 1000000) return HIKF_E_INVALID;
-    if (op->rowpass_variant < 0 || op->rowpass_variant > 4) return HIKF_E_INVALID;
+    if (op->rowpass_variant < 0 || op->rowpass_variant > 8) return HIKF_E_INVALID;
+    if (op->psd_guard != 0 && op->psd_guard != 1) return HIKF_E_INVALID;
+    g->psd_guard = op->psd_guard == 1;
+    if (!(op->m2l_eps >= 0.0 && op->m2l_eps < 1.0)) return HIKF_E_INVALID;
+    g->m2l_eps = op->m2l_eps;
     g->rp_variant = op->rowpass_variant > 0 ? op->rowpass_variant - 1 : kDefaultRowpassVariant;
     g->history = op->history;
     g->alpha = pr->alpha;
@@ -355,6 +375,8 @@ QueryPlan query_plan(const Geometry &g0) {
     q.g.nnz = 0;
     q.g.history = 0;
     q.g.sparse = false;           // Q v runs on a dense first column
+    q.g.psd_guard = false;
+    q.g.m2l_eps = 0.0;
     if (q.g.fmm_prec == HIKF_FMM_BF16X3 || q.g.fmm_prec == HIKF_FMM_BF16) q.g.fmm_prec = HIKF_FMM_F32;
     q.lay = hikf::make_layout(q.g);
     const size_t tq = q.g.fmm_prec == HIKF_FMM_F64 ? 8 : 4;
@@ -446,6 +468,26 @@ hipError_t noalloc_scratch(int dev, char **out) {
     return hipSuccess;
 }
 
+// FNV-1a over the sizes, kernel and options that shape a filter's state
+// (the device part covers H, R and x_0).
+uint64_t host_hash(const hikf_problem *pr, const hikf_options *op) {
+    uint64_t h = 1469598103934665603ull;
+    auto eat = [&](const void *d, size_t n) {
+        const unsigned char *b = static_cast<const unsigned char *>(d);
+        for (size_t i = 0; i < n; ++i) {
+            h ^= b[i];
+            h *= 1099511628211ull;
+        }
+    };
+    const int32_t ints[] = {pr->dim, pr->n, pr->kernel_family, pr->prior_kind, pr->p, op->n_c,
+                            op->fmm_precision, op->direct, op->sparse, op->psd_guard};
+    const double dbl[] = {pr->theta, pr->ell, pr->gamma, pr->alpha, op->m2l_eps};
+    eat(ints, sizeof(ints));
+    eat(dbl, sizeof(dbl));
+    eat(&pr->nnz, sizeof(pr->nnz));
+    return h;
+}
+
 hikf_status set_err(hikf_filter *f, hikf_status st, const char *what, hipError_t e) {
     if (f) snprintf(f->err, sizeof(f->err), "%s: %s", what, hipGetErrorString(e));
     return st;
@@ -535,27 +577,48 @@ hikf_status hikf_init(const hikf_problem *prob, const hikf_options *opt, void *r
     HIKF_TRY(hipMemcpyAsync(res + lay.rdiag, prob->r_diag_dev, size_t(g.p) * 8,
                             hipMemcpyDeviceToDevice, s), "copy R");
     HIKF_TRY(hikf::launch_validate(g, lay, res, prob->x0_dev, s), "validate");
-    HIKF_TRY(hikf::launch_fmm(g, lay, res, scr, s, &f->timing), "fmm");
+    HIKF_TRY(hikf::launch_hash(g, lay, res, prob->x0_dev, s), "hash");
+    f->host_hash = host_hash(prob, opt);
+    HIKF_TRY(hikf::launch_fmm(g, lay, res, scr, s, &f->timing, f->lr_ranks), "fmm");
     HIKF_TRY(hikf::launch_init_state(g, lay, res, prob->x0_dev, s), "init state");
     f->riccati = opt->riccati > 0 ? opt->riccati : 0;
     f->g.rp_variant = resolve_rowpass_variant(g, opt);
     // H C_Q: the fixed part of every step's G (and of the p-space recursion)
     HIKF_TRY(hikf::launch_gq(f->g, lay, res, s), "H C_Q");
+    if (g.psd_guard) {
+        // G_Q <- its PSD part; the first prior G = H C_0 + G_Q (2 G_Q for
+        // P_0 = Q, whose H C_0 is G_Q itself) and h = H x_0, then carried
+        double *GQ = reinterpret_cast<double *>(res + lay.GQ);
+        HIKF_TRY(hikf::launch_psd_project(f->g, GQ, reinterpret_cast<double *>(scr + lay.psw), s),
+                 "PSD guard");
+        HIKF_TRY(hikf::launch_gather_g(f->g, lay, res, s), "guard start");
+        if (g.prior == HIKF_PRIOR_KERNEL)
+            HIKF_TRY(hikf::launch_pp_scal(f->g, 2.0, GQ, reinterpret_cast<double *>(res + lay.G), s),
+                     "guard start");
+        HIKF_TRY(hikf::launch_set_status(lay, res, hikf::kStCarried, 1, s), "guard start");
+    }
     if (opt->graph && !opt->timing) {
         // capture on a private stream (the caller's may be the null stream,
         // which cannot be captured); the graph reads y from the resident copy
         hipStream_t cs = nullptr;
         HIKF_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
-        hipError_t ce = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-        if (ce == hipSuccess) {
-            hipError_t le = hikf::launch_step(f->g, lay, res,
-                                              reinterpret_cast<const double *>(res + lay.ybuf), cs,
-                                              nullptr, true, f->riccati > 0);
-            ce = hipStreamEndCapture(cs, &f->graph);
-            if (ce == hipSuccess) ce = le;
+        // the gathering step (the only one without the recursion; with it,
+        // the periodic check) and the carrying step (recursion or guard)
+        const bool want_gather = !g.psd_guard || f->riccati > 0;
+        const bool want_carry = f->riccati > 0 || g.psd_guard;
+        hipError_t ce = hipSuccess;
+        if (want_gather) {
+            ce = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (ce == hipSuccess) {
+                hipError_t le = hikf::launch_step(f->g, lay, res,
+                                                  reinterpret_cast<const double *>(res + lay.ybuf),
+                                                  cs, nullptr, true, f->riccati > 0);
+                ce = hipStreamEndCapture(cs, &f->graph);
+                if (ce == hipSuccess) ce = le;
+            }
+            if (ce == hipSuccess) ce = hipGraphInstantiate(&f->gexec, f->graph, nullptr, nullptr, 0);
         }
-        if (ce == hipSuccess) ce = hipGraphInstantiate(&f->gexec, f->graph, nullptr, nullptr, 0);
-        if (ce == hipSuccess && f->riccati) {
+        if (ce == hipSuccess && want_carry) {
             ce = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
             if (ce == hipSuccess) {
                 hipError_t le = hikf::launch_step(f->g, lay, res,
@@ -570,11 +633,13 @@ hikf_status hikf_init(const hikf_problem *prob, const hikf_options *opt, void *r
         (void)hipStreamDestroy(cs);
         if (ce != hipSuccess) {
             if (f->gexec) (void)hipGraphExecDestroy(f->gexec);
+            if (f->gexec_ng) (void)hipGraphExecDestroy(f->gexec_ng);
             if (f->graph) (void)hipGraphDestroy(f->graph);
             if (f->graph_ng) (void)hipGraphDestroy(f->graph_ng);
-            f->gexec = nullptr;
+            f->gexec = f->gexec_ng = nullptr;
             f->graph = f->graph_ng = nullptr;
         }
+        f->graphed = true;
         HIKF_TRY(ce, "step graph");
     }
 #undef HIKF_TRY
@@ -588,15 +653,23 @@ hikf_status hikf_step(hikf_filter *f, const double *y_dev, double *x_out_dev, do
     hipStream_t s = static_cast<hipStream_t>(stream);
     f->last_stream = s;
     hipError_t e;
-    const bool gather = !f->riccati || f->force_gather || f->issued % f->riccati == 0;
+    // gather: without the guard, every step (no recursion), every riccati-th
+    // step and the first after init or an import (recursion); with the
+    // guard only every riccati-th step, as a check of the carried values
+    bool gather;
+    if (f->g.psd_guard)
+        gather = f->riccati > 0 && f->issued > 0 && f->issued % f->riccati == 0;
+    else
+        gather = !f->riccati || f->force_gather || f->issued % f->riccati == 0;
     f->force_gather = false;
     ++f->issued;
-    if (f->gexec) {
+    if (f->graphed) {
         e = hipMemcpyAsync(f->res + f->lay.ybuf, y_dev, size_t(f->g.p) * 8,
                            hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess) e = hipGraphLaunch(gather ? f->gexec : f->gexec_ng, s);
     } else {
-        e = hikf::launch_step(f->g, f->lay, f->res, y_dev, s, &f->timing, gather, f->riccati > 0);
+        e = hikf::launch_step(f->g, f->lay, f->res, y_dev, s, &f->timing, gather,
+                              f->riccati > 0 || f->g.psd_guard);
     }
     if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "step", e);
     const size_t mb = size_t(f->g.m) * 8;
@@ -707,6 +780,7 @@ hikf_status hikf_query(hikf_filter *f, hikf_stats *out) {
     out->riccati_drift_g = drift[0];
     out->riccati_drift_h = drift[1];
     out->riccati_checks = int64_t(drift[2]);
+    for (int lev = 0; lev < 20; ++lev) out->m2l_ranks[lev] = f->lr_ranks[lev];
     if (f->timing.on) {
         e = f->timing.collect();
         if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "timing", e);
@@ -752,6 +826,83 @@ hikf_status hikf_import_state(hikf_filter *f, const double *x_dev, const double 
         e = hipMemsetAsync(f->res + f->lay.status + 4 * hikf::kStCarried, 0, 4, s);
     if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "import", e);
     f->force_gather = true;
+    return HIKF_OK;
+}
+
+namespace {
+// the filter's full problem hash (host part + the device digest of H, R, x_0)
+hikf_status problem_hash(hikf_filter *f, uint64_t *out) {
+    unsigned long long dev = 0;
+    hipError_t e = hipStreamSynchronize(f->last_stream);
+    if (e == hipSuccess) e = hipMemcpy(&dev, f->res + f->lay.hash, 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "read hash", e);
+    *out = f->host_hash ^ (uint64_t(dev) * 0x9E3779B97F4A7C15ull);
+    return HIKF_OK;
+}
+}  // namespace
+
+hikf_status hikf_export_checkpoint(hikf_filter *f, double *x_dev, double *var_dev, double *c_dev,
+                                   double *pspace_dev, hikf_checkpoint_info *info, void *stream) {
+    if (!f || !info) return HIKF_E_INVALID;
+    hikf_status st = hikf_export_state(f, x_dev, var_dev, c_dev, stream);
+    if (st != HIKF_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t pp2 = size_t(f->g.p) * f->g.p;
+    hipError_t e = hipSuccess;
+    if (pspace_dev) {
+        e = hipMemcpyAsync(pspace_dev, f->res + f->lay.G, pp2 * 8, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(pspace_dev + pp2, f->res + f->lay.hvec, size_t(f->g.p) * 8,
+                               hipMemcpyDeviceToDevice, s);
+    }
+    if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "export checkpoint", e);
+    uint64_t h = 0;
+    st = problem_hash(f, &h);             // synchronises the stream
+    if (st != HIKF_OK) return st;
+    long long steps = 0;
+    int status[hikf::kNumStatus];
+    e = hipMemcpy(&steps, f->res + f->lay.steps, 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(status, f->res + f->lay.status, sizeof(status), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "export checkpoint", e);
+    info->problem_hash = h;
+    info->steps_applied = steps;
+    info->steps_issued = f->issued;
+    info->p = f->g.p;
+    info->carried = status[hikf::kStCarried] == 1 ? 1 : 0;
+    return HIKF_OK;
+}
+
+hikf_status hikf_import_checkpoint(hikf_filter *f, const double *x_dev, const double *var_dev,
+                                   const double *c_dev, const double *pspace_dev,
+                                   const hikf_checkpoint_info *info, void *stream) {
+    if (!f || !info) return HIKF_E_INVALID;
+    if (info->p != f->g.p || (f->g.psd_guard && !(pspace_dev && info->carried)))
+        return HIKF_E_INVALID;
+    uint64_t h = 0;
+    hikf_status st = problem_hash(f, &h);
+    if (st != HIKF_OK) return st;
+    if (h != info->problem_hash) {
+        snprintf(f->err, sizeof(f->err), "checkpoint of another problem (hash %016llx, this "
+                 "filter %016llx)", (unsigned long long)info->problem_hash, (unsigned long long)h);
+        return HIKF_E_INVALID;
+    }
+    st = hikf_import_state(f, x_dev, var_dev, c_dev, stream);   // clears the carried flag
+    if (st != HIKF_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t pp2 = size_t(f->g.p) * f->g.p;
+    long long steps = info->steps_applied;
+    hipError_t e = hipMemcpyAsync(f->res + f->lay.steps, &steps, 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);      // `steps` is a host local
+    if (e == hipSuccess && pspace_dev && info->carried) {
+        e = hipMemcpyAsync(f->res + f->lay.G, pspace_dev, pp2 * 8, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(f->res + f->lay.hvec, pspace_dev + pp2, size_t(f->g.p) * 8,
+                               hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hikf::launch_set_status(f->lay, f->res, hikf::kStCarried, 1, s);
+        if (e == hipSuccess) f->force_gather = false;
+    }
+    if (e != hipSuccess) return set_err(f, HIKF_E_DEVICE, "import checkpoint", e);
+    f->issued = info->steps_issued;
     return HIKF_OK;
 }
 

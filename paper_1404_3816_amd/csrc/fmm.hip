@@ -17,6 +17,8 @@
 // on the fly).  Operators are built on the device in FP64 and stored in the
 // pass precision T (float or double).
 #include <algorithm>
+#include <cmath>
+#include <vector>
 
 #include "hikf_internal.h"
 
@@ -852,6 +854,132 @@ k_trans_mma(int dim, int r, int p, int lev, const T *M, const T *Tlev, T *L) {
     }
 }
 
+// ---------------------------------------------------------------- low-rank M2L
+// The compressed M2L of the black-box FMM: a level's translations T_o share
+// one basis U (r x k), the left singular vectors of [T_o1 T_o2 ...] (all
+// offsets with max|o| >= 2) whose singular values are at least eps times the
+// largest, and T_o ~ U (U^T T_o U) U^T.  The multipoles are compressed once
+// (U^T M, k x p per box), translated by the k x k operators C_o = U^T T_o U
+// and expanded once (U L~), so a list entry costs 2 k^2 p instead of 2 r^2 p.
+// U comes from the eigenvectors of the r x r Gram matrix sum_o T_o T_o^T
+// (FP64, evaluated from the kernel), found on the host by the cyclic Jacobi
+// method.
+
+// A[i][j] = sum_o sum_q T_o[i][q] T_o[j][q] for the level's box side s:
+// one workgroup per (i, j >= i), its threads over the (slot, q) pairs, a
+// fixed-order tree sum at the end
+__global__ void __launch_bounds__(kBlock)
+k_lr_gram(int dim, int nc, int r, double s, KernelParams kp, double *A) {
+    __shared__ double red[kBlock];
+    const int i = blockIdx.x / r, j = blockIdx.x % r;
+    if (j < i) return;
+    const int noff = dim == 2 ? 49 : 343;
+    int ki[3], kj[3], kq[3];
+    node_idx(i, nc, ki);
+    node_idx(j, nc, kj);
+    double acc = 0.0;
+    for (int t = threadIdx.x; t < noff * r; t += kBlock) {
+        const int oi = t / r, q = t % r;
+        const int o[3] = {oi % 7 - 3, (oi / 7) % 7 - 3, oi / 49 - 3};
+        int omax = 0;
+        for (int ax = 0; ax < dim; ++ax) omax = max(omax, abs(o[ax]));
+        if (omax < 2) continue;
+        node_idx(q, nc, kq);
+        double r2i = 0.0, r2j = 0.0;
+        for (int ax = 0; ax < dim; ++ax) {
+            const double xq = cheb_node(nc, kq[ax]);
+            const double di = s * (o[ax] + 0.5 * (xq - cheb_node(nc, ki[ax])));
+            const double dj = s * (o[ax] + 0.5 * (xq - cheb_node(nc, kj[ax])));
+            r2i += di * di;
+            r2j += dj * dj;
+        }
+        acc += kernel_from_r2<double>(r2i, kp) * kernel_from_r2<double>(r2j, kp);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = kBlock / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        A[i * r + j] = red[0];
+        A[j * r + i] = red[0];
+    }
+}
+
+// W[slot][i][b] = sum_q T_slot[i][q] U[q][b] (U: r x k, row stride k)
+__global__ void k_lr_w(int dim, int nc, int r, int k, double s, KernelParams kp, const double *U,
+                       double *W) {
+    const int noff = dim == 2 ? 49 : 343;
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= int64_t(noff) * r * k) return;
+    const int oi = int(idx / (int64_t(r) * k)), i = int((idx / k) % r), b = int(idx % k);
+    const int o[3] = {oi % 7 - 3, (oi / 7) % 7 - 3, oi / 49 - 3};
+    int omax = 0;
+    for (int ax = 0; ax < dim; ++ax) omax = max(omax, abs(o[ax]));
+    if (omax < 2) { W[idx] = 0.0; return; }
+    int ki[3], kq[3];
+    node_idx(i, nc, ki);
+    double acc = 0.0;
+    for (int q = 0; q < r; ++q) {
+        node_idx(q, nc, kq);
+        double r2 = 0.0;
+        for (int ax = 0; ax < dim; ++ax) {
+            const double d = s * (o[ax] + 0.5 * (cheb_node(nc, kq[ax]) - cheb_node(nc, ki[ax])));
+            r2 += d * d;
+        }
+        acc += kernel_from_r2<double>(r2, kp) * U[q * k + b];
+    }
+    W[idx] = acc;
+}
+
+// C[slot][a][b] = sum_i U[i][a] W[slot][i][b] in the pass precision, and
+// the compress / expand operators Ut = U^T (k x r), Ue = U (r x k)
+template <typename T>
+__global__ void k_lr_c(int noff, int r, int k, const double *U, const double *W, T *C, T *Ut,
+                       T *Ue) {
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t nc_ = int64_t(noff) * k * k;
+    if (idx < nc_) {
+        const int sl = int(idx / (int64_t(k) * k)), a = int((idx / k) % k), b = int(idx % k);
+        const double *Ws = W + int64_t(sl) * r * k;
+        double acc = 0.0;
+        for (int i = 0; i < r; ++i) acc += U[i * k + a] * Ws[i * k + b];
+        C[idx] = (T)acc;
+    }
+    if (idx < int64_t(r) * k) {
+        const int i = int(idx / k), a = int(idx % k);
+        Ut[a * r + i] = (T)U[i * k + a];
+        Ue[i * k + a] = (T)U[i * k + a];
+    }
+}
+
+// out[box][a][c] = sum_b op[a][b] in[box][b][c] (op: na x nb <= 64 x 64),
+// one workgroup per (box, 64 columns); the operator and the input panel are
+// staged in LDS
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_box_op(int na, int nb, int p, const T *op, const T *in, T *out) {
+    __shared__ T sop[64 * 64];
+    __shared__ T sin_[64 * 64];
+    const int64_t B = blockIdx.x;
+    const int c0 = blockIdx.y * 64;
+    const int ncol = min(64, p - c0);
+    for (int idx = threadIdx.x; idx < na * nb; idx += kBlock)
+        sop[(idx / nb) * 64 + idx % nb] = op[idx];
+    for (int idx = threadIdx.x; idx < nb * 64; idx += kBlock) {
+        const int b = idx / 64, c = idx % 64;
+        sin_[b * 64 + c] = c < ncol ? in[(B * nb + b) * p + c0 + c] : (T)0;
+    }
+    __syncthreads();
+    const int c = threadIdx.x & 63;
+    for (int a = threadIdx.x >> 6; a < na; a += kBlock / 64) {
+        T acc = 0;
+        for (int b = 0; b < nb; ++b) acc += sop[a * 64 + b] * sin_[b * 64 + c];
+        if (c < ncol) out[(B * na + a) * p + c0 + c] = acc;
+    }
+}
+
 // ---------------------------------------------------------------- BF16 split (MFMA)
 // v_mfma_f32_16x16x32_bf16: D += A B with lane l supplying the 8 values
 // A[l%16][8 (l/16) + i] and B[8 (l/16) + i][l%16], i = 0..7, and holding
@@ -1286,11 +1414,183 @@ __global__ void k_dense_w(int64_t m, int dim, int n, int npad, int p, const doub
     }
 }
 
+// Eigenvectors of the symmetric r x r matrix A (row-major) by the cyclic
+// Jacobi method (rotations zeroing a[p][q] with tan 2t = 2 a_pq / (a_qq -
+// a_pp)) until the off-diagonal mass is negligible; then the basis of the
+// low-rank M2L: the eigenvectors whose sqrt(eigenvalue) is at least eps
+// times the largest, sorted by decreasing eigenvalue, as U (r x k, row
+// stride k).  Returns k (at least 1).
+int lowrank_basis_host(int r, const double *A_in, double eps, double *U) {
+    std::vector<double> av(A_in, A_in + size_t(r) * r), vv(size_t(r) * r, 0.0);
+    double *a = av.data(), *v = vv.data();
+    for (int i = 0; i < r; ++i) v[i * r + i] = 1.0;
+    double scale = 0.0;
+    for (int i = 0; i < r * r; ++i) scale += a[i] * a[i];
+    // sweeps until the off-diagonal part is below 1e-13 of the whole (the
+    // kept eigenvalues are at least eps^2 of the largest, eps >= 1e-7 in use)
+    for (int sweep = 0; sweep < 50 && scale > 0.0; ++sweep) {
+        double off = 0.0;
+        for (int i = 0; i < r; ++i)
+            for (int j = i + 1; j < r; ++j) off += a[i * r + j] * a[i * r + j];
+        if (off <= 1e-26 * scale) break;
+        for (int pp = 0; pp < r; ++pp)
+            for (int qq = pp + 1; qq < r; ++qq) {
+                const double apq = a[pp * r + qq];
+                const double app = a[pp * r + pp], aqq = a[qq * r + qq];
+                if (std::fabs(apq) <= 1e-18 * std::sqrt(std::fabs(app * aqq)) || apq == 0.0) continue;
+                const double th = 0.5 * (aqq - app) / apq;
+                const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < r; ++k) {                    // columns pp, qq
+                    double *row = a + k * r;
+                    const double akp = row[pp], akq = row[qq];
+                    row[pp] = c * akp - sn * akq;
+                    row[qq] = sn * akp + c * akq;
+                }
+                double *rp = a + pp * r, *rq = a + qq * r;       // rows pp, qq
+                for (int k = 0; k < r; ++k) {
+                    const double apk = rp[k], aqk = rq[k];
+                    rp[k] = c * apk - sn * aqk;
+                    rq[k] = sn * apk + c * aqk;
+                }
+                for (int k = 0; k < r; ++k) {                    // eigenvector columns
+                    double *row = v + k * r;
+                    const double vkp = row[pp], vkq = row[qq];
+                    row[pp] = c * vkp - sn * vkq;
+                    row[qq] = sn * vkp + c * vkq;
+                }
+            }
+    }
+    std::vector<int> order(r);
+    for (int i = 0; i < r; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return a[x * r + x] > a[y * r + y]; });
+    const double top = std::max(a[order[0] * r + order[0]], 0.0);
+    int k = 0;
+    while (k < r && top > 0.0 &&
+           std::sqrt(std::max(a[order[k] * r + order[k]], 0.0)) >= eps * std::sqrt(top))
+        ++k;
+    if (k < 1) k = 1;
+    for (int i = 0; i < r; ++i)
+        for (int b = 0; b < k; ++b) U[size_t(i) * k + b] = v[i * r + order[b]];
+    return k;
+}
+
+// Low-rank M2L of every level (g.m2l_eps > 0): bases from the Gram matrices
+// (one host synchronisation), compressed operators, then per level
+// compress -> translate on MFMA (FP32 / FP64, or BF16 split) -> expand into L.
+// lr_ranks (optional, levels 0..D) receives the rank used at each level.
+template <typename T>
+hipError_t run_lowrank_m2l(const Geometry &g, const Layout &lay, char *scr, hipStream_t s,
+                           int *lr_ranks) {
+    const int p = g.p, r = g.r, dim = g.dim, D = g.depth, nlev = D - 1;
+    const int noff = g.noff();
+    const double root = double(g.npad) / g.n;
+    const bool bf16 = g.fmm_prec == HIKF_FMM_BF16X3 || g.fmm_prec == HIKF_FMM_BF16;
+    double *Ag = reinterpret_cast<double *>(scr + lay.lrA);
+    double *Ud = reinterpret_cast<double *>(scr + lay.lrU);
+    double *Wd = reinterpret_cast<double *>(scr + lay.lrW);
+    T *Ct = reinterpret_cast<T *>(scr + lay.lrC);
+    T *Ut = reinterpret_cast<T *>(scr + lay.lrUt);
+    T *Ue = reinterpret_cast<T *>(scr + lay.lrUe);
+    T *MT = reinterpret_cast<T *>(scr + lay.lrM);
+    T *LT = reinterpret_cast<T *>(scr + lay.lrL);
+    const size_t rr = size_t(r) * r;
+    for (int lev = 2; lev <= D; ++lev)
+        hipLaunchKernelGGL(k_lr_gram, dim3(unsigned(rr)), dim3(kBlock), 0, s, dim, g.nc, r,
+                           root / double(int64_t(1) << lev), g.kp, Ag + (lev - 2) * rr);
+    std::vector<double> Ah(size_t(nlev) * rr), Uh(size_t(nlev) * rr, 0.0);
+    hipError_t e = hipMemcpyAsync(Ah.data(), Ag, Ah.size() * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    std::vector<int> kl(nlev);
+    for (int l = 0; l < nlev; ++l)
+        kl[l] = lowrank_basis_host(r, Ah.data() + l * rr, g.m2l_eps, Uh.data() + l * rr);
+    e = hipMemcpyAsync(Ud, Uh.data(), Uh.size() * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);     // Uh is a host local
+    if (e != hipSuccess) return e;
+    if (lr_ranks)
+        for (int lev = 0; lev <= D; ++lev) lr_ranks[lev] = lev >= 2 ? kl[lev - 2] : 0;
+    for (int lev = 2; lev <= D; ++lev) {
+        const int k = kl[lev - 2];
+        const double sl = root / double(int64_t(1) << lev);
+        const int64_t nw = int64_t(noff) * r * k;
+        hipLaunchKernelGGL(k_lr_w, dim3(unsigned((nw + 255) / 256)), dim3(256), 0, s, dim, g.nc, r, k,
+                           sl, g.kp, Ud + (lev - 2) * rr, Wd);
+        const int64_t nc_ = std::max<int64_t>(int64_t(noff) * k * k, int64_t(r) * k);
+        hipLaunchKernelGGL(k_lr_c<T>, dim3(unsigned((nc_ + 255) / 256)), dim3(256), 0, s, noff, r, k,
+                           Ud + (lev - 2) * rr, Wd, Ct + size_t(lev - 2) * noff * rr,
+                           Ut + (lev - 2) * rr, Ue + (lev - 2) * rr);
+    }
+    auto Mlev = [&](int lev) { return reinterpret_cast<T *>(scr + lay.ML_level[lev]); };
+    auto Llev = [&](int lev) {
+        return reinterpret_cast<T *>(scr + lay.L_base + (lay.ML_level[lev] - lay.ML_level[2]));
+    };
+    for (int lev = 2; lev <= D; ++lev) {
+        const int k = kl[lev - 2];
+        const int64_t nbx = g.boxes(lev);
+        const dim3 gop(unsigned(nbx), (p + 63) / 64);
+        hipLaunchKernelGGL(k_box_op<T>, gop, dim3(kBlock), 0, s, k, r, p,
+                           static_cast<const T *>(Ut + (lev - 2) * rr),
+                           static_cast<const T *>(Mlev(lev)), MT);
+        const T *Cl = Ct + size_t(lev - 2) * noff * rr;
+        bool done = false;
+        if constexpr (sizeof(T) == 4) {
+            if (bf16) {
+                const int kr = (k + 31) / 32 * 32, rt16 = (k + 15) / 16 * 16;
+                __bf16 *Th = reinterpret_cast<__bf16 *>(scr + lay.Tsplit);
+                __bf16 *Tl = Th + int64_t(noff) * rt16 * kr;
+                hipLaunchKernelGGL(k_split_t, dim3(unsigned((int64_t(noff) * rt16 * kr + 255) / 256)),
+                                   dim3(256), 0, s, int64_t(noff), k, rt16, kr, Cl, Th, Tl);
+                __bf16 *Mh = reinterpret_cast<__bf16 *>(scr + lay.MS_level[lev]);
+                __bf16 *Ml = Mh + nbx * p * kr;
+                hipLaunchKernelGGL(k_split_m, dim3(unsigned(nbx), (p + 63) / 64), dim3(kBlock), 0, s, k,
+                                   kr, p, MT, Mh, Ml);
+                const size_t lds = size_t(rt16 + 128) * (kr + 8) * 2 * sizeof(__bf16);
+                const dim3 grid(unsigned(nbx), (p + 127) / 128);
+                const bool split = g.fmm_prec == HIKF_FMM_BF16X3;
+#define HIKF_LR_BF16(SPL, KRV)                                                                   \
+    do {                                                                                         \
+        e = allow_lds(k_m2l_bf16<SPL, 128, KRV>, lds);                                           \
+        if (e != hipSuccess) return e;                                                           \
+        hipLaunchKernelGGL((k_m2l_bf16<SPL, 128, KRV>), grid, dim3(kBlock), lds, s, dim, k, p, lev, \
+                           Mh, Ml, Th, Tl, LT);                                                  \
+    } while (0)
+                if (split) { if (kr == 32) HIKF_LR_BF16(true, 32); else HIKF_LR_BF16(true, 64); }
+                else       { if (kr == 32) HIKF_LR_BF16(false, 32); else HIKF_LR_BF16(false, 64); }
+#undef HIKF_LR_BF16
+                done = true;
+            }
+        }
+        if (!done) {
+            constexpr int MPT = sizeof(T) == 4 ? 128 : 64;
+            const int RT = (k + 15) / 16, KR = (k + 3) / 4 * 4;
+            const size_t lds = (size_t(KR) * (MPT + Mma<T>::pad) + size_t(16 * RT) * 68) * sizeof(T);
+            const dim3 grid(unsigned(nbx), (p + MPT - 1) / MPT);
+            if (k <= 32) {
+                e = allow_lds(k_trans_mma<T, MPT, 32, kM2L>, lds);
+                if (e != hipSuccess) return e;
+                hipLaunchKernelGGL((k_trans_mma<T, MPT, 32, kM2L>), grid, dim3(kBlock), lds, s, dim, k,
+                                   p, lev, static_cast<const T *>(MT), Cl, LT);
+            } else {
+                e = allow_lds(k_trans_mma<T, MPT, 64, kM2L>, lds);
+                if (e != hipSuccess) return e;
+                hipLaunchKernelGGL((k_trans_mma<T, MPT, 64, kM2L>), grid, dim3(kBlock), lds, s, dim, k,
+                                   p, lev, static_cast<const T *>(MT), Cl, LT);
+            }
+        }
+        hipLaunchKernelGGL(k_box_op<T>, gop, dim3(kBlock), 0, s, r, k, p,
+                           static_cast<const T *>(Ue + (lev - 2) * rr),
+                           static_cast<const T *>(LT), Llev(lev));
+    }
+    return hipGetLastError();
+}
+
 // vdense == nullptr: W = H^T from the CSR arrays in RES, result into C_Q.
 // Otherwise W's first column is vdense and the result goes to out (m x p).
 template <typename T>
 hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, hipStream_t s,
-                   Timing *tm, const double *vdense = nullptr, T *out = nullptr) {
+                   Timing *tm, const double *vdense = nullptr, T *out = nullptr,
+                   int *lr_ranks = nullptr) {
     const int p = g.p, r = g.r, dim = g.dim, D = g.depth;
     const int64_t m = g.m;
     const bool bf16 = g.fmm_prec == HIKF_FMM_BF16X3 || g.fmm_prec == HIKF_FMM_BF16;
@@ -1390,8 +1690,13 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
         tend(tm, HIKF_PHASE_M2M, s);
         // M2L
         tbegin(tm, HIKF_PHASE_M2L, s);
+        const bool lowrank = g.m2l_eps > 0.0 && !vdense;
+        if (lowrank) {
+            e = run_lowrank_m2l<T>(g, lay, scr, s, lr_ranks);
+            if (e != hipSuccess) return e;
+        }
         if constexpr (sizeof(T) == 4) {
-            if (bf16) {
+            if (bf16 && !lowrank) {
                 const int kr = g.kr32(), rt16 = (r + 15) / 16 * 16;
                 const int64_t nslots = int64_t(D - 1) * g.noff();
                 __bf16 *Th = reinterpret_cast<__bf16 *>(scr + lay.Tsplit);
@@ -1421,7 +1726,7 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
                 }
             }
         }
-        if (!bf16) {
+        if (!bf16 && !lowrank) {
             constexpr int MPT = sizeof(T) == 4 ? 128 : 64;
             const int RT = (r + 15) / 16, KR = (r + 3) / 4 * 4;
             const size_t lds = (size_t(KR) * (MPT + Mma<T>::pad) + size_t(16 * RT) * 68) * sizeof(T);
@@ -1536,9 +1841,10 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
 }  // namespace
 
 hipError_t launch_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, hipStream_t s,
-                      Timing *t) {
-    if (g.fmm_prec == HIKF_FMM_F64) return run_fmm<double>(g, lay, res, scr, s, t);
-    return run_fmm<float>(g, lay, res, scr, s, t);
+                      Timing *t, int *lr_ranks) {
+    if (g.fmm_prec == HIKF_FMM_F64)
+        return run_fmm<double>(g, lay, res, scr, s, t, nullptr, nullptr, lr_ranks);
+    return run_fmm<float>(g, lay, res, scr, s, t, nullptr, nullptr, lr_ranks);
 }
 
 hipError_t launch_fmm_apply(const Geometry &g, const Layout &lay, char *scr, const double *v,

@@ -14,6 +14,7 @@ constexpr int kLeafPts = 64;      // points per leaf: 8x8 (2-D) or 4x4x4 (3-D)
 constexpr int kMaxP = 512;        // measurements (rays) per step
 constexpr int kMaxR = 64;         // Chebyshev nodes per box
 constexpr int kNumStatus = 8;     // ints in the device status block
+constexpr int kPsdIterations = 64; // Newton-Schulz sign iterations of the PSD guard
 
 // device status block layout (int32 slots)
 enum : int {
@@ -65,6 +66,8 @@ struct Geometry {
     int cpr = 1;                  // gather chunks per ray
     int num_cu = 256;             // compute units of the device (persistent grids)
     int rp_variant = 0;           // row-pass variant (rowpass.h): bit 0 persistent, bit 1 narrow
+    bool psd_guard = false;       // carry G, h with the PSD part of H C_Q (hikf_options.psd_guard)
+    double m2l_eps = 0.0;         // low-rank M2L threshold (hikf_options.m2l_eps), 0 = dense
     int64_t m = 0;                // n^dim cells (state size)
     int64_t mpad = 0;             // npad^dim cells of the tree
     int64_t nnz = 0;
@@ -93,6 +96,7 @@ struct Layout {
     size_t histC, histS;                      // per-step C_prior and S^{-1} (history)
     size_t psA, pivs;                         // p-space ping-pong buffer (with xbuf), pivots
     size_t Gg, hg, drift;                     // gathered G, h (drift check), drift record
+    size_t hash;                              // device part of the problem hash (uint64)
     size_t resident_bytes;
     // scratch
     size_t W, knear, sleaf, schild, m2l, lev_off;   // lev_off: start of M/L storage
@@ -100,6 +104,8 @@ struct Layout {
     size_t L_base;
     size_t Wsplit, Tsplit, MS_level[24];      // BF16 hi/lo operands (BF16 modes only)
     size_t bcur, boff, btmp, bkey, bval;      // nonzeros of H by leaf (sparse mode only)
+    size_t psw;                               // PSD guard: three p x p work matrices
+    size_t lrA, lrU, lrW, lrC, lrUt, lrUe, lrM, lrL;   // low-rank M2L (m2l_eps > 0)
     size_t scratch_bytes;
 };
 
@@ -130,14 +136,17 @@ inline void tbegin(Timing *t, int ph, hipStream_t s) { if (t && t->on) t->begin(
 inline void tend(Timing *t, int ph, hipStream_t s) { if (t && t->on) t->end(ph, s); }
 
 // ---- launch wrappers (defined in fmm.hip / step.hip) ----
+// lr_ranks (levels 0..depth, optional): ranks of the low-rank M2L
 hipError_t launch_fmm(const Geometry &g, const Layout &lay, char *res, char *scr,
-                      hipStream_t s, Timing *t);
+                      hipStream_t s, Timing *t, int *lr_ranks = nullptr);
 hipError_t launch_validate(const Geometry &g, const Layout &lay, char *res,
                            const double *x0, hipStream_t s);
 hipError_t launch_init_state(const Geometry &g, const Layout &lay, char *res,
                              const double *x0, hipStream_t s);
 // gather: form G, h from the rows of C (else use the carried ones);
 // advance: afterwards carry G, h to the next step by the p-space recursion
+// (with the PSD guard, gather only checks the carried G, h against the
+// gathered ones and keeps the carried ones)
 hipError_t launch_step(const Geometry &g, const Layout &lay, char *res,
                        const double *y, hipStream_t s, Timing *t, bool gather = true,
                        bool advance = false);
@@ -147,7 +156,16 @@ hipError_t rowpass_launch(const Geometry &g, const Layout &lay, char *res, hipSt
 hipError_t launch_pspace(const Geometry &g, const Layout &lay, char *res,
                          const double *y, hipStream_t s);
 hipError_t launch_advance(const Geometry &g, const Layout &lay, char *res, hipStream_t s);
+// PSD guard (pspace.hip): GQ <- PSD part of sym(GQ) in place; y = a x (p x p)
+hipError_t launch_psd_project(const Geometry &g, double *GQ, double *work, hipStream_t s);
+hipError_t launch_pp_scal(const Geometry &g, double a, const double *x, double *y, hipStream_t s);
+// the device part of the problem hash: H, R and x_0 into res + lay.hash
+hipError_t launch_hash(const Geometry &g, const Layout &lay, char *res, const double *x0,
+                       hipStream_t s);
+// set the status slot `slot` to `value` (a kernel, so graphs and streams order it)
+hipError_t launch_set_status(const Layout &lay, char *res, int slot, int value, hipStream_t s);
 hipError_t launch_gq(const Geometry &g, const Layout &lay, char *res, hipStream_t s);
+hipError_t launch_gather_g(const Geometry &g, const Layout &lay, char *res, hipStream_t s);
 hipError_t launch_widen_cq(const Geometry &g, const Layout &lay, char *res,
                            double *out, hipStream_t s);
 // Q v into column 0 of out (m x g.p in the FMM precision) with the tree of g
@@ -171,9 +189,12 @@ struct hikf_filter {
     hikf::Timing timing;
     hipGraph_t graph = nullptr;      // step captured at init (hikf_options.graph)
     hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph_ng = nullptr;   // the same without the gather (riccati mode)
+    hipGraph_t graph_ng = nullptr;   // the same without the gather (recursion or guard)
     hipGraphExec_t gexec_ng = nullptr;
+    bool graphed = false;            // steps replay gexec / gexec_ng
     int riccati = 0;                 // gather period of the p-space recursion, 0 = off
+    uint64_t host_hash = 0;          // host part of the problem hash (sizes, kernel, options)
+    int lr_ranks[24] = {};           // ranks of the low-rank M2L per level (0: dense / none)
     int64_t issued = 0;              // steps issued since init or the last import
     bool force_gather = true;
     char err[256] = {0};

@@ -345,3 +345,123 @@ hipError_t launch_advance(const Geometry &g, const Layout &lay, char *res, hipSt
 }
 
 }  // namespace hikf
+
+namespace hikf {
+
+// ---------------------------------------------------------------- PSD guard
+// The H^2 approximation of a smooth kernel makes G_Q = H C_Q indefinite by
+// about its approximation error; the random walk adds G_Q every step, so
+// S = (G + G^T)/2 + R loses definiteness after a number of steps that the
+// most negative eigenvalue sets.  The guard replaces G_Q by its positive
+// semidefinite part (G_Q + |G_Q|) / 2, the projection onto the PSD cone,
+// which is never farther from the exact H Q H^T than G_Q is.  |G_Q| =
+// G_Q sign(G_Q) comes from the inverse-free Newton-Schulz iteration for the
+// matrix sign,  X <- X (3 I - X^2) / 2  from X = G_Q / ||G_Q||_F, on FP64
+// MFMA: an eigenvalue of relative size e grows by 1.5x per iteration, so a
+// fixed count of iterations settles every eigenvalue above 1.5^-count of
+// the largest; smaller ones (far below R) keep a partly converged sign and
+// change by less than themselves.
+namespace {
+
+// Cout = alpha A B + beta D for p x p row-major matrices (D may be null);
+// one 256-thread workgroup per 32 x 32 block, FP64 MFMA
+__global__ void __launch_bounds__(NT)
+k_pp_gemm(int p, int nbk, const double *A, const double *B, const double *D, double alpha,
+          double beta, double *Cout) {
+    __shared__ double sA[BS * BP];
+    __shared__ double sBb[BS * BP];
+    const int bi = blockIdx.x / nbk, bj = blockIdx.x % nbk, t = threadIdx.x;
+    d4 acc = d4{0, 0, 0, 0};
+    for (int kb = 0; kb < nbk; ++kb) {
+        __syncthreads();
+        blk_load_p(sA, A, p, bi, kb);
+        blk_load_p(sBb, B, p, kb, bj);
+        __syncthreads();
+        acc = tile_mma<false, false>(acc, sA, sBb, 1.0);
+    }
+    __syncthreads();
+    tile_write(sA, acc);
+    __syncthreads();
+    for (int idx = t; idx < BS * BS; idx += NT) {
+        const int r = idx / BS, c = idx % BS, i = bi * BS + r, j = bj * BS + c;
+        if (i < p && j < p) {
+            const int64_t o = int64_t(i) * p + j;
+            Cout[o] = alpha * sA[r * BP + c] + (D ? beta * D[o] : 0.0);
+        }
+    }
+}
+
+// X = sym(G) / ||sym(G)||_F (X = 0 for G = 0), one workgroup
+__global__ void __launch_bounds__(NT) k_pp_scale(int p, const double *G, double *X) {
+    __shared__ double red[NT];
+    const int t = threadIdx.x;
+    const int64_t n = int64_t(p) * p;
+    double s = 0.0;
+    for (int64_t i = t; i < n; i += NT) {
+        const int64_t r = i / p, c = i % p;
+        const double v = 0.5 * (G[i] + G[c * p + r]);
+        s += v * v;
+    }
+    red[t] = s;
+    __syncthreads();
+    for (int k = NT / 2; k > 0; k >>= 1) {
+        if (t < k) red[t] += red[t + k];
+        __syncthreads();
+    }
+    const double inv = red[0] > 0.0 ? 1.0 / sqrt(red[0]) : 0.0;
+    for (int64_t i = t; i < n; i += NT) {
+        const int64_t r = i / p, c = i % p;
+        X[i] = inv * 0.5 * (G[i] + G[c * p + r]);
+    }
+}
+
+// G = (P + P^T) / 2 (the product of the last iteration, symmetrised)
+__global__ void k_pp_sym(int p, const double *P, double *G) {
+    const int64_t n = int64_t(p) * p;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t r = i / p, c = i % p;
+        G[i] = 0.5 * (P[i] + P[c * p + r]);
+    }
+}
+
+// y = a x (p x p)
+__global__ void k_pp_scal(int p, double a, const double *x, double *y) {
+    const int64_t n = int64_t(p) * p;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        y[i] = a * x[i];
+}
+
+}  // namespace
+
+// In place: GQ <- the PSD part of sym(GQ).  work: three p x p buffers.
+hipError_t launch_psd_project(const Geometry &g, double *GQ, double *work, hipStream_t s) {
+    const int p = g.p, nbk = g.pp / BS;
+    const int64_t pp2 = int64_t(p) * p;
+    double *X = work, *Y = work + pp2, *Z = work + 2 * pp2;
+    const unsigned eb = unsigned((pp2 + 255) / 256);
+    hipLaunchKernelGGL(k_pp_scale, dim3(1), dim3(NT), 0, s, p, GQ, X);
+    for (int it = 0; it < kPsdIterations; ++it) {
+        // Y = X X;  Z = 1.5 X - 0.5 X Y;  X <- Z
+        hipLaunchKernelGGL(k_pp_gemm, dim3(nbk * nbk), dim3(NT), 0, s, p, nbk, X, X,
+                           static_cast<const double *>(nullptr), 1.0, 0.0, Y);
+        hipLaunchKernelGGL(k_pp_gemm, dim3(nbk * nbk), dim3(NT), 0, s, p, nbk, X, Y, X, -0.5, 1.5, Z);
+        double *tmp = X;
+        X = Z;
+        Z = tmp;
+    }
+    // GQ <- sym((GQ + GQ X) / 2)
+    hipLaunchKernelGGL(k_pp_gemm, dim3(nbk * nbk), dim3(NT), 0, s, p, nbk, GQ, X, GQ, 0.5, 0.5, Y);
+    hipLaunchKernelGGL(k_pp_sym, dim3(eb), dim3(256), 0, s, p, Y, GQ);
+    return hipGetLastError();
+}
+
+// y = a x for p x p matrices (the guard's start G = 2 G_Q+ for P_0 = Q)
+hipError_t launch_pp_scal(const Geometry &g, double a, const double *x, double *y, hipStream_t s) {
+    const int64_t pp2 = int64_t(g.p) * g.p;
+    hipLaunchKernelGGL(k_pp_scal, dim3(unsigned((pp2 + 255) / 256)), dim3(256), 0, s, g.p, a, x, y);
+    return hipGetLastError();
+}
+
+}  // namespace hikf

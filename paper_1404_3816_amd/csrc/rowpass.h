@@ -343,17 +343,267 @@ hipError_t rowpass_go(const Geometry &g, const Layout &lay, char *res, hipStream
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- dual form
+// One wave per SIMD: 256 threads = 4 waves per tile of 64 rows, P <= 256.
+// Wave w takes the row pair rp = w % 2 (row groups 2 rp and 2 rp + 1, 16
+// rows each) and the column half c = w / 2.  Every S^{-1} value read from LDS
+// feeds two MFMAs (one per row group), which halves the LDS traffic per
+// MFMA, and the register file a single wave per SIMD may use (accumulators
+// in AGPRs) leaves room to load C_prior two k blocks ahead, so the loads are
+// in flight for two blocks of MFMAs instead of one.  The column mapping, the
+// slab layout and the epilogue are those of the form above, per row group.
+template <typename TQ, int NT, bool PERSIST>
+__device__ __forceinline__ void rowpass_dual_part(double *sB, double *red, int64_t m,
+                                                  int64_t ntiles, double *C, const TQ *CQ,
+                                                  const double *Sinv, const double *nu,
+                                                  const double *rdiag, double *xhat,
+                                                  double *var, double kdiag,
+                                                  unsigned long long *negvar, const int part) {
+    typedef typename Pair<TQ>::v2 qv2;
+    constexpr int P = NT * 16, LDB = P + 8, SLAB = 16 * LDB, NTH = 256;
+    constexpr int PER2 = (8 * P + NTH - 1) / NTH;       // slab column pairs per thread
+    constexpr int NH = (NT + 1) / 2;                    // tiles of column half 0
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, q = lane >> 4, rp = wave & 1;
+    const int T0 = part ? NH : 0, NHp = part ? NT - NH : NH;
+    const int acol = rp_col(lr & 3, lr >> 2);
+    int64_t tile = blockIdx.x;
+
+    double keep[2][NH][4];                      // C_prior of the own columns, per row group
+    double cur[2][4];
+    dv2 pc[2][2][2];                            // C blocks in flight: [stage][group][half]
+    qv2 pq[2][2][2];
+    dv2 bpre[PER2];
+    d4 acc[2][NH];
+
+    auto rbase_of = [&](int64_t tl, int gg) -> int64_t {
+        const int64_t r = tl * 64 + (2 * rp + gg) * 16 + lr;
+        return (r < m ? r : 0) * P + 2 * q;
+    };
+    auto load_block = [&](int st, int64_t tl, int kb) {
+#pragma unroll
+        for (int gg = 0; gg < 2; ++gg) {
+            const int64_t b = rbase_of(tl, gg) + 16 * kb;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                pc[st][gg][h] = *reinterpret_cast<const dv2 *>(C + b + 8 * h);
+                pq[st][gg][h] = *reinterpret_cast<const qv2 *>(CQ + b + 8 * h);
+            }
+        }
+    };
+
+    // prologue: slab 0 into buffer 0, C_prior blocks 0 and 1 of the first tile
+#pragma unroll
+    for (int u = 0; u < PER2; ++u) {
+        const int idx = tid + NTH * u, rr = idx / (P / 2), c = 2 * (idx % (P / 2));
+        if (idx < 8 * P)
+            *reinterpret_cast<dv2 *>(sB + rr * LDB + c) =
+                *reinterpret_cast<const dv2 *>(Sinv + int64_t(rr) * P + c);
+    }
+    load_block(0, tile, 0);
+    if (NT > 1) load_block(1, tile, 1);
+    __syncthreads();
+
+    for (;;) {
+        const int64_t next = tile + gridDim.x;
+        const bool more = PERSIST && next < ntiles;
+        bool okg[2];
+#pragma unroll
+        for (int gg = 0; gg < 2; ++gg) okg[gg] = tile * 64 + (2 * rp + gg) * 16 + lr < m;
+#pragma unroll
+        for (int gg = 0; gg < 2; ++gg)
+#pragma unroll
+            for (int t = 0; t < NH; ++t) acc[gg][t] = d4{0.0, 0.0, 0.0, 0.0};
+        const double *Sv = Sinv;
+        if (PERSIST) asm volatile("" : "+s"(Sv));
+
+#pragma unroll
+        for (int kb = 0; kb < NT; ++kb) {
+            const int st = kb & 1;
+#pragma unroll
+            for (int gg = 0; gg < 2; ++gg)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    cur[gg][2 * h] = okg[gg] ? pc[st][gg][h][0] + (double)pq[st][gg][h][0] : 0.0;
+                    cur[gg][2 * h + 1] = okg[gg] ? pc[st][gg][h][1] + (double)pq[st][gg][h][1] : 0.0;
+                }
+            // the block two ahead goes into the stage just consumed: this
+            // tile's block kb + 2, or the next tile's block kb + 2 - NT
+            if (kb + 2 < NT) load_block(st, tile, kb + 2);
+            else if (more && kb + 2 - NT < NT) load_block(st, next, kb + 2 - NT);
+            const bool pfs = kb + 1 < NT || more;
+            const int nslab = kb + 1 < NT ? 16 * (kb + 1) : 0;
+            if (pfs) {
+#pragma unroll
+                for (int u = 0; u < PER2; ++u) {
+                    const int idx = tid + NTH * u, rr = idx / (P / 2), c = 2 * (idx % (P / 2));
+                    if (idx < 8 * P)
+                        bpre[u] = *reinterpret_cast<const dv2 *>(Sv + int64_t(nslab + rr) * P + c);
+                }
+            }
+            if (kb >= T0 && kb < T0 + NHp) {
+#pragma unroll
+                for (int gg = 0; gg < 2; ++gg)
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4) keep[gg][kb - T0][s4] = cur[gg][s4];
+            }
+            {
+                const double *B = sB + (kb & 1) * SLAB + 2 * q * LDB + acol + 16 * T0;
+                constexpr int NQ = 4 * NH;
+                auto aop = [&](int i) {
+                    const int si = i / NH, ti = i % NH;
+                    return B[(8 * (si >> 1) + (si & 1)) * LDB + 16 * ti];
+                };
+                double ring[4];
+                ring[0] = aop(0);
+                if (NQ > 1) ring[1] = aop(1);
+                if (NQ > 2) ring[2] = aop(2);
+#pragma unroll
+                for (int i = 0; i < NQ; ++i) {
+                    if (i + 3 < NQ) ring[(i + 3) % 4] = aop(i + 3);
+                    const int si = i / NH, ti = i % NH;
+                    if (ti < NHp) {
+                        acc[0][ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(ring[i % 4], cur[0][si], acc[0][ti], 0, 0, 0);
+                        acc[1][ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(ring[i % 4], cur[1][si], acc[1][ti], 0, 0, 0);
+                    }
+                }
+            }
+            if (pfs) {
+#pragma unroll
+                for (int u = 0; u < PER2; ++u) {
+                    const int idx = tid + NTH * u, rr = idx / (P / 2), c = 2 * (idx % (P / 2));
+                    if (idx < 8 * P)
+                        *reinterpret_cast<dv2 *>(sB + ((kb + 1) & 1) * SLAB + rr * LDB + c) = bpre[u];
+                }
+            }
+            __syncthreads();
+        }
+        // with NT = 1 only one block was prefetched per tile; load the next
+        // tile's now
+        if (NT == 1 && more) load_block(0, next, 0);
+
+        const double *nu_t = nu, *rdiag_t = rdiag;
+        if (PERSIST) asm volatile("" : "+s"(nu_t), "+s"(rdiag_t));
+        const bool odd = lr & 1;
+        auto swap_pair = [](double x) {
+            int2 v = __builtin_bit_cast(int2, x);
+            v.x = __builtin_amdgcn_mov_dpp(v.x, 0xB1, 0xF, 0xF, false);
+            v.y = __builtin_amdgcn_mov_dpp(v.y, 0xB1, 0xF, 0xF, false);
+            return __builtin_bit_cast(double, v);
+        };
+#pragma unroll
+        for (int gg = 0; gg < 2; ++gg) {
+            double dv = 0.0, dx = 0.0;
+#pragma unroll
+            for (int t = 0; t < NH; ++t) {
+                if (t >= NHp) continue;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int c = 16 * (T0 + t) + 8 * h + 2 * q;
+                    const dv2 nv = *reinterpret_cast<const dv2 *>(nu_t + c);
+                    const double k0 = acc[gg][t][2 * h], k1 = acc[gg][t][2 * h + 1];
+                    dv += k0 * keep[gg][t][2 * h] + k1 * keep[gg][t][2 * h + 1];
+                    dx += k0 * nv[0] + k1 * nv[1];
+                }
+            }
+            // C <- K R with whole-row stores (see the form above)
+            const int64_t row = tile * 64 + (2 * rp + gg) * 16 + lr;
+            const int64_t r0 = row - odd;
+#pragma unroll
+            for (int t = 0; t < NH; ++t) {
+                if (t >= NHp) continue;
+                const int c0 = 16 * (T0 + t) + 2 * q;
+                const dv2 ra = *reinterpret_cast<const dv2 *>(rdiag_t + c0);
+                const dv2 rb = *reinterpret_cast<const dv2 *>(rdiag_t + c0 + 8);
+                const dv2 a = dv2{acc[gg][t][0] * ra[0], acc[gg][t][1] * ra[1]};
+                const dv2 b = dv2{acc[gg][t][2] * rb[0], acc[gg][t][3] * rb[1]};
+                const dv2 g2 = dv2{swap_pair(odd ? a[0] : b[0]), swap_pair(odd ? a[1] : b[1])};
+                const int cc = c0 + (odd ? 8 : 0);
+                if (r0 < m) __builtin_nontemporal_store(odd ? g2 : a, reinterpret_cast<dv2 *>(C + r0 * P + cc));
+                if (r0 + 1 < m)
+                    __builtin_nontemporal_store(odd ? b : g2, reinterpret_cast<dv2 *>(C + (r0 + 1) * P + cc));
+            }
+            dv += __shfl_xor(dv, 16, 64);
+            dx += __shfl_xor(dx, 16, 64);
+            dv += __shfl_xor(dv, 32, 64);
+            dx += __shfl_xor(dx, 32, 64);
+            if (q == 0) {
+                red[((part * 4 + 2 * rp + gg) * 16 + lr) * 2 + 0] = dv;
+                red[((part * 4 + 2 * rp + gg) * 16 + lr) * 2 + 1] = dx;
+            }
+        }
+        __syncthreads();
+        if (tid < 64) {
+            const int64_t r = tile * 64 + tid;
+            if (r < m) {
+                const double sv = red[tid * 2] + red[(64 + tid) * 2];
+                const double sx = red[tid * 2 + 1] + red[(64 + tid) * 2 + 1];
+                const double v = var[r] + kdiag - sv;
+                var[r] = v;
+                xhat[r] += sx;
+                if (v < 0.0) atomicAdd(negvar, 1ull);
+            }
+        }
+        if (!more) break;
+        tile = next;
+    }
+}
+
+template <typename TQ, int NT, bool PERSIST>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_rowpass_dual(int64_t m, int64_t ntiles, double *C, const TQ *CQ, const double *Sinv,
+               const double *nu, const double *rdiag, double *xhat, double *var, double kdiag,
+               const int *status, unsigned long long *negvar) {
+    __shared__ __align__(16) double sB[2 * 16 * (NT * 16 + 8)];
+    __shared__ double red[2 * 64 * 2];
+    if (status[kStStep] != HIKF_OK) return;
+    if (int64_t(blockIdx.x) >= ntiles) return;
+    const int part = (threadIdx.x >> 6) >> 1;
+    rowpass_dual_part<TQ, NT, PERSIST>(sB, red, m, ntiles, C, CQ, Sinv, nu, rdiag, xhat, var,
+                                       kdiag, negvar, part);
+}
+
+template <typename TQ, int NT, bool PERSIST>
+hipError_t rowpass_go_dual(const Geometry &g, const Layout &lay, char *res, hipStream_t s) {
+    const int64_t ntiles = (g.m + 63) / 64;
+    int64_t blocks = ntiles;
+    if (PERSIST) {
+        blocks = g.num_cu > 0 ? g.num_cu : 256;
+        if (blocks > ntiles) blocks = ntiles;
+    }
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((k_rowpass_dual<TQ, NT, PERSIST>), dim3(unsigned(blocks)), dim3(256), 0, s,
+                       g.m, ntiles, reinterpret_cast<double *>(res + lay.C),
+                       reinterpret_cast<const TQ *>(res + lay.CQ),
+                       reinterpret_cast<const double *>(res + lay.sinv),
+                       reinterpret_cast<const double *>(res + lay.nu),
+                       reinterpret_cast<const double *>(res + lay.rdiag),
+                       reinterpret_cast<double *>(res + lay.xhat),
+                       reinterpret_cast<double *>(res + lay.var),
+                       g.kp.family == HIKF_KERNEL_TEST_R2 ? 0.0 : g.kp.theta,
+                       reinterpret_cast<const int *>(res + lay.status),
+                       reinterpret_cast<unsigned long long *>(res + lay.negvar));
+    return hipGetLastError();
+}
+
 }  // namespace
 
 // Row-pass variants (Geometry::rp_variant): bit 0 = persistent workgroups
-// (for an even number of 16-column blocks; otherwise ignored), bit 1 = the
-// narrow split (32-row tiles, columns in four parts) instead of 64-row tiles
-// in two column halves; p > 256 always uses the narrow split, which its
-// register budget needs.
+// (for an even number of 16-column blocks in the 8-wave forms; otherwise
+// ignored), bit 1 = the narrow split (32-row tiles, columns in four parts)
+// instead of 64-row tiles in two column halves; p > 256 always uses the
+// narrow split, which its register budget needs; bit 2 = the dual form
+// (4 waves, one per SIMD, two row groups per wave; built for p = 64, 128
+// and 256, ignored for other p).
 template <typename TQ, int NT>
 hipError_t rowpass_launch(const Geometry &g, const Layout &lay, char *res, hipStream_t s) {
     constexpr bool kCanPersist = NT % 2 == 0;
     const bool persist = kCanPersist && (g.rp_variant & 1);
+    if constexpr (NT == 4 || NT == 8 || NT == 16) {
+        if (g.rp_variant & 4)
+            return (g.rp_variant & 1) ? rowpass_go_dual<TQ, NT, true>(g, lay, res, s)
+                                      : rowpass_go_dual<TQ, NT, false>(g, lay, res, s);
+    }
     const bool narrow = NT > 16 || (g.rp_variant & 2);
     if (narrow)
         return persist ? rowpass_go<TQ, NT, 4, 2, kCanPersist>(g, lay, res, s)

@@ -202,7 +202,7 @@ k_reduce_g(int p, int cpr, const double *partial, const double *GQ, double *G, d
 // import, or if every step since the last gather failed).
 __global__ void __launch_bounds__(256)
 k_drift(int p, const double *Gg, const double *hg, double *G, double *h, double *drift,
-        int *status) {
+        int *status, int keep_carried) {
     __shared__ double red[4][256];
     if (status[kStInit] != 0) return;
     const int t = threadIdx.x;
@@ -236,11 +236,49 @@ k_drift(int p, const double *Gg, const double *hg, double *G, double *h, double 
         drift[1] = fmax(drift[1], rh);
         drift[2] += 1.0;
     }
+    if (keep_carried) return;                // the PSD guard keeps its own G, h
     __syncthreads();
     for (int64_t i = t; i < n; i += 256) G[i] = Gg[i];
     for (int i = t; i < p; i += 256) h[i] = hg[i];
     if (t == 0) status[kStCarried] = 0;
 }
+
+// ---------------------------------------------------------------- problem hash
+// An order-independent 64-bit digest of H (row pointers, columns, values), R
+// and x_0: every element's bits are mixed with its position and array
+// (SplitMix64 finaliser) and the results are summed modulo 2^64.
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_hash(int p, int64_t nnz, int64_t m, const int64_t *rowptr, const int32_t *col,
+                       const double *val, const double *rdiag, const double *x0,
+                       unsigned long long *out) {
+    unsigned long long acc = 0;
+    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = tid; i <= p; i += stride)
+        acc += mix64((1ull << 60) ^ (unsigned long long)(i * 0x100000001B3ull) ^
+                     mix64((unsigned long long)rowptr[i]));
+    for (int64_t i = tid; i < nnz; i += stride) {
+        acc += mix64((2ull << 60) ^ (unsigned long long)i ^ mix64((unsigned long long)(uint32_t)col[i]));
+        acc += mix64((3ull << 60) ^ (unsigned long long)i ^
+                     mix64(__builtin_bit_cast(unsigned long long, val[i])));
+    }
+    for (int64_t i = tid; i < p; i += stride)
+        acc += mix64((4ull << 60) ^ (unsigned long long)i ^
+                     mix64(__builtin_bit_cast(unsigned long long, rdiag[i])));
+    if (x0)
+        for (int64_t i = tid; i < m; i += stride)
+            acc += mix64((5ull << 60) ^ (unsigned long long)i ^
+                         mix64(__builtin_bit_cast(unsigned long long, x0[i])));
+    if (acc) atomicAdd(out, acc);
+}
+
+__global__ void k_set_int(int *dst, int value) { *dst = value; }
 
 // ---------------------------------------------------------------- history
 // Covariance queries need every applied step's prior cross-covariance C_s
@@ -365,12 +403,12 @@ void run_gather(const Geometry &g, const Layout &lay, char *res, bool with_c, do
 template <typename TQ>
 hipError_t run_step(const Geometry &g, const Layout &lay, char *res, const double *y,
                     hipStream_t s, Timing *tm, bool gather, bool advance) {
-    if (gather && !advance) {
+    if (gather && !advance && !g.psd_guard) {
         run_gather<TQ>(g, lay, res, true, reinterpret_cast<double *>(res + lay.G),
                        reinterpret_cast<double *>(res + lay.hvec), s, tm);
     } else if (gather) {
         // recursion mode: gather aside, compare with the carried G, h, keep
-        // the gathered ones
+        // the gathered ones (the PSD guard keeps the carried ones)
         run_gather<TQ>(g, lay, res, true, reinterpret_cast<double *>(res + lay.Gg),
                        reinterpret_cast<double *>(res + lay.hg), s, tm);
         hipLaunchKernelGGL(k_drift, dim3(1), dim3(256), 0, s, g.p,
@@ -379,8 +417,9 @@ hipError_t run_step(const Geometry &g, const Layout &lay, char *res, const doubl
                            reinterpret_cast<double *>(res + lay.G),
                            reinterpret_cast<double *>(res + lay.hvec),
                            reinterpret_cast<double *>(res + lay.drift),
-                           reinterpret_cast<int *>(res + lay.status));
+                           reinterpret_cast<int *>(res + lay.status), g.psd_guard ? 1 : 0);
     }
+    if (g.psd_guard) advance = true;
     const long long *steps = reinterpret_cast<const long long *>(res + lay.steps);
     if (g.history)
         hipLaunchKernelGGL(k_hist_c<TQ>, dim3(grid_for(g.m * g.p)), dim3(256), 0, s, g.m * g.p,
@@ -435,6 +474,27 @@ hipError_t launch_cov_tail(const Geometry &g, const Layout &lay, char *res, int 
     return hipGetLastError();
 }
 
+hipError_t launch_hash(const Geometry &g, const Layout &lay, char *res, const double *x0,
+                       hipStream_t s) {
+    unsigned long long *out = reinterpret_cast<unsigned long long *>(res + lay.hash);
+    hipError_t e = hipMemsetAsync(out, 0, 8, s);
+    if (e != hipSuccess) return e;
+    int64_t n = g.nnz > g.m ? g.nnz : g.m;
+    if (n < g.p + 1) n = g.p + 1;
+    hipLaunchKernelGGL(k_hash, dim3(grid_for(n)), dim3(256), 0, s, g.p, g.nnz, g.m,
+                       reinterpret_cast<const int64_t *>(res + lay.rowptr),
+                       reinterpret_cast<const int32_t *>(res + lay.col),
+                       reinterpret_cast<const double *>(res + lay.val),
+                       reinterpret_cast<const double *>(res + lay.rdiag), x0, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_status(const Layout &lay, char *res, int slot, int value, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s,
+                       reinterpret_cast<int *>(res + lay.status) + slot, value);
+    return hipGetLastError();
+}
+
 hipError_t launch_validate(const Geometry &g, const Layout &lay, char *res, const double *x0,
                            hipStream_t s) {
     int64_t n = g.nnz > g.m ? g.nnz : g.m;
@@ -478,6 +538,15 @@ hipError_t launch_step(const Geometry &g, const Layout &lay, char *res, const do
                        hipStream_t s, Timing *t, bool gather, bool advance) {
     if (g.fmm_prec == HIKF_FMM_F64) return run_step<double>(g, lay, res, y, s, t, gather, advance);
     return run_step<float>(g, lay, res, y, s, t, gather, advance);
+}
+
+// G = H C + G_Q and h = H x_hat from the current state (the PSD guard's start)
+hipError_t launch_gather_g(const Geometry &g, const Layout &lay, char *res, hipStream_t s) {
+    double *G = reinterpret_cast<double *>(res + lay.G);
+    double *h = reinterpret_cast<double *>(res + lay.hvec);
+    if (g.fmm_prec == HIKF_FMM_F64) run_gather<double>(g, lay, res, true, G, h, s, nullptr);
+    else run_gather<float>(g, lay, res, true, G, h, s, nullptr);
+    return hipGetLastError();
 }
 
 // G_Q = H C_Q (p x p) for the p-space recursion; nu serves as a throw-away h

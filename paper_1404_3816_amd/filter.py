@@ -52,7 +52,8 @@ def problem_from_csr(dim, n, rowptr, col, val, r_diag, family="powexp", theta=1.
 
 
 def make_options(n_c=4, precision="f32", direct=False, timing=False, graph=False, riccati=0,
-                 history=0, sparse=False, rowpass_variant=None, tune_cache=None):
+                 history=0, sparse=False, rowpass_variant=None, tune_cache=None,
+                 psd_guard=False, m2l_eps=0.0):
     """hikf_options; rowpass_variant None = automatic (tuning cache or the
     built-in default), else the variant 0..3 to force."""
     op = H.hikf_options()
@@ -66,6 +67,8 @@ def make_options(n_c=4, precision="f32", direct=False, timing=False, graph=False
     op.sparse = 1 if sparse else 0
     op.rowpass_variant = 0 if rowpass_variant is None else 1 + int(rowpass_variant)
     op.tune_cache = tune_cache.encode() if tune_cache else None
+    op.psd_guard = 1 if psd_guard else 0
+    op.m2l_eps = float(m2l_eps)
     return op
 
 
@@ -142,6 +145,32 @@ class HikfFilter:
                else ctypes.c_void_p(None))
         H.check(H.hikf_import_state(self.handle, ptr(ts[0]), ptr(ts[1]), ptr(ts[2]),
                                     _stream_handle(stream)), "hikf_import_state", self.handle)
+
+    def export_checkpoint(self, stream=None):
+        """(x, var, C, [G | h], info) device tensors and the checkpoint info."""
+        dev = self.resident.device
+        x = torch.empty(self.m, dtype=torch.float64, device=dev)
+        v = torch.empty(self.m, dtype=torch.float64, device=dev)
+        c = torch.empty(self.m, self.p, dtype=torch.float64, device=dev)
+        ps = torch.empty(self.p * self.p + self.p, dtype=torch.float64, device=dev)
+        info = H.hikf_checkpoint_info()
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+        H.check(H.hikf_export_checkpoint(self.handle, ptr(x), ptr(v), ptr(c), ptr(ps),
+                                         ctypes.byref(info), _stream_handle(stream)),
+                "hikf_export_checkpoint", self.handle)
+        return x, v, c, ps, info
+
+    def import_checkpoint(self, x, var, c, pspace, info, stream=None):
+        ts = [t.contiguous() if t is not None else None for t in (x, var, c, pspace)]
+        if stream is not None:
+            for t, orig in zip(ts, (x, var, c, pspace)):
+                if t is not None and t is not orig:
+                    t.record_stream(stream)
+        ptr = (lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None
+               else ctypes.c_void_p(None))
+        H.check(H.hikf_import_checkpoint(self.handle, ptr(ts[0]), ptr(ts[1]), ptr(ts[2]),
+                                         ptr(ts[3]), ctypes.byref(info), _stream_handle(stream)),
+                "hikf_import_checkpoint", self.handle)
 
     def cov_apply(self, v, stream=None):
         """P_{t|t} v for the current step t (needs options.history >= t)."""

@@ -59,7 +59,8 @@ class hikf_options(ctypes.Structure):
     _fields_ = [("n_c", c_i32), ("fmm_precision", c_i32), ("direct", c_i32),
                 ("timing", c_i32), ("riccati", c_i32), ("history", c_i32), ("graph", c_i32),
                 ("sparse", c_i32), ("rowpass_variant", c_i32), ("reserved1", c_i32),
-                ("tune_cache", ctypes.c_char_p)]
+                ("tune_cache", ctypes.c_char_p), ("psd_guard", c_i32), ("reserved4", c_i32),
+                ("m2l_eps", c_dbl)]
 
 
 class hikf_plan_info(ctypes.Structure):
@@ -80,7 +81,12 @@ class hikf_stats(ctypes.Structure):
                 ("time_count", c_i64 * HIKF_NUM_PHASES),
                 ("rowpass_variant", c_i32), ("reserved2", c_i32),
                 ("riccati_drift_g", c_dbl), ("riccati_drift_h", c_dbl),
-                ("riccati_checks", c_i64)]
+                ("riccati_checks", c_i64), ("m2l_ranks", c_i32 * 20)]
+
+
+class hikf_checkpoint_info(ctypes.Structure):
+    _fields_ = [("problem_hash", ctypes.c_uint64), ("steps_applied", c_i64),
+                ("steps_issued", c_i64), ("p", c_i32), ("carried", c_i32)]
 
 
 _P = ctypes.POINTER
@@ -96,6 +102,10 @@ _SIGS = {
     "hikf_query": (c_i32, [c_vp, _P(hikf_stats)]),
     "hikf_export_state": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     "hikf_import_state": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "hikf_export_checkpoint": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp,
+                                       _P(hikf_checkpoint_info), c_vp]),
+    "hikf_import_checkpoint": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp,
+                                       _P(hikf_checkpoint_info), c_vp]),
     "hikf_export_cq": (c_i32, [c_vp, c_vp, c_vp]),
     "hikf_destroy": (None, [c_vp]),
     "hikf_status_string": (ctypes.c_char_p, [c_i32]),
@@ -118,6 +128,8 @@ hikf_cov_apply_noalloc = _lib.hikf_cov_apply_noalloc
 hikf_query = _lib.hikf_query
 hikf_export_state = _lib.hikf_export_state
 hikf_import_state = _lib.hikf_import_state
+hikf_export_checkpoint = _lib.hikf_export_checkpoint
+hikf_import_checkpoint = _lib.hikf_import_checkpoint
 hikf_export_cq = _lib.hikf_export_cq
 hikf_destroy = _lib.hikf_destroy
 hikf_status_string = _lib.hikf_status_string

@@ -2,16 +2,18 @@
 
 The row pass (one per assimilation step; the gain, state, variance and
 cross-covariance rows of Algorithm Algorithm_HiKF) dominates the run time.
-It has four launch forms (hikf_options.rowpass_variant): 64- or 32-row tiles
-(columns in two halves or in four parts) and one workgroup per tile or
-persistent workgroups that loop over tiles.  Which is fastest depends on p,
+It has several launch forms (hikf_options.rowpass_variant): 8-wave
+workgroups on 64- or 32-row tiles (columns in two halves or in four parts),
+4-wave workgroups with one wave per SIMD and two row groups per wave (the
+dual form), each with one workgroup per tile or persistent workgroups that
+loop over tiles.  Which is fastest depends on p,
 m and the device, so this module measures them on the problem at hand and
 records the winner in a JSON cache that hikf_init reads (option tune_cache):
 
     {"device": "...", "rowpass": [{"p": 256, "cq": "f32", "m": 1048576,
-      "variant": 1, "ms": [2.67, 2.31, 2.71, 2.40]}, ...]}
+      "variant": 1, "ms": [2.67, 2.31, 2.71, 2.40, 3.40, 3.50]}, ...]}
 
-(ms: the row-pass time of each variant 0..3, null where a variant is the
+(ms: the row-pass time of each variant 0..5, null where a variant is the
 same launch as another for this p).
 
 Usage (on the GPU):
@@ -29,19 +31,25 @@ import torch
 
 from . import filter as F
 
-VARIANTS = (0, 1, 2, 3)
+VARIANTS = (0, 1, 2, 3, 4, 5)
 
 
 def distinct_variants(p):
-    """The variants that differ for p (persistence needs p / 16 even; p > 256
-    always uses the 32-row split)."""
+    """The variants that differ for p: persistence needs p / 16 even in the
+    8-wave forms, p > 256 always uses the 32-row split, and the dual form
+    (bit 2) is built for p = 64, 128 and 256 only."""
     out = []
     for v in VARIANTS:
         eff = v
-        if (p // 16) % 2:
-            eff &= ~1
-        if p > 256:
-            eff |= 2
+        if v & 4:
+            if p not in (64, 128, 256):
+                continue
+            eff = v & 5
+        else:
+            if (p // 16) % 2:
+                eff &= ~1
+            if p > 256:
+                eff |= 2
         if eff not in out:
             out.append(eff)
     return out

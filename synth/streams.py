@@ -90,17 +90,20 @@ def plume_observations(dim, n, rowptr, col, val, steps, r_var, seed: int):
     return observations(rowptr, inv, val, truth, r_var, seed)
 
 
-def serving_streams(count: int, seed: int = 1):
+def serving_streams(count: int = 64, seed: int = 1):
     """Filter configurations of a serving mix: per stream a 2-D grid with
     m log-uniform in [16384, 1048576] (N = round(sqrt(m))), p drawn from
-    {32, 64, 128, 256, 512}, an exponential kernel with ell ~ U[0.05, 0.3]
-    and n_c = 4; R = 1e-4 I and P_0 = Q as in the other workloads.
+    {32, 64, 128, 256, 512}, ell ~ U[0.05, 0.3] and the kernel exponential
+    or Gaussian with probability 1/2 each (drawn in that order per stream);
+    R = 1e-4 I and P_0 = Q as in the other workloads.
 
-    Gaussian-kernel streams are left out of the mix: for them H Q H^T has
-    eigenvalues far below R, and the indefinite part of the H^2 / FP32
-    approximation of Q (relative error ~1e-4 at n_c = 5), which the random
-    walk adds up step after step, overtakes R = 1e-4 within a few steps on
-    the larger grids, so S turns indefinite (seen up to n_c = 8)."""
+    The Chebyshev order and arithmetic follow the kernel: exponential
+    streams use n_c = 4 with the FP32 FMM; Gaussian streams use the largest
+    order, n_c = 8, the FP64 FMM and the PSD guard, because the H^2
+    approximation of a smooth kernel leaves H Q H^T indefinite at every
+    order up to 8 (the innovation covariance of the literal filter then
+    fails within 3 to 52 steps on these streams), and FP32 rounding of C_Q
+    alone moves its smallest eigenvalues by more than their size."""
     rng = np.random.default_rng(seed)
     out = []
     for s in range(count):
@@ -108,7 +111,10 @@ def serving_streams(count: int, seed: int = 1):
         n = int(round(np.sqrt(m)))
         p = int(rng.choice([32, 64, 128, 256, 512]))
         ell = float(rng.uniform(0.05, 0.3))
-        out.append(dict(dim=2, n=n, m=n * n, p=p, theta=1.0, ell=ell, gamma=1.0, n_c=4,
+        gauss = bool(rng.uniform() < 0.5)
+        out.append(dict(dim=2, n=n, m=n * n, p=p, theta=1.0, ell=ell,
+                        gamma=2.0 if gauss else 1.0, n_c=8 if gauss else 4,
+                        precision="f64" if gauss else "f32", psd_guard=gauss,
                         r_var=1e-4, prior="kernel", seed=seed + 1 + s))
     return out
 

@@ -190,10 +190,10 @@ def test_plan_rowpass_variant_range():
     op = H.hikf_options()
     op.n_c, op.fmm_precision = 4, H.HIKF_FMM_F32
     info = H.hikf_plan_info()
-    for v in range(5):
+    for v in range(9):
         op.rowpass_variant = v
         assert H.hikf_plan(ctypes.byref(pr), ctypes.byref(op), ctypes.byref(info)) == H.HIKF_OK
-    for v in (-1, 5):
+    for v in (-1, 9):
         op.rowpass_variant = v
         assert H.hikf_plan(ctypes.byref(pr), ctypes.byref(op),
                            ctypes.byref(info)) == H.HIKF_E_INVALID
@@ -228,3 +228,48 @@ def test_plan_reads_tuning_cache(tmp_path):
     assert variant(64, 32, H.HIKF_FMM_F32, forced=3) == 2  # forced variant 2
     assert variant(64, 32, H.HIKF_FMM_F32, path=None) == 0
     assert variant(64, 32, H.HIKF_FMM_F32, path=str(tmp_path / "missing.json")) == 0
+
+
+def test_checkpoint_calls_check_arguments_without_a_device():
+    from paper_1404_3816_amd import hikf as H
+    info = H.hikf_checkpoint_info()
+    assert H.hikf_export_checkpoint(None, None, None, None, None, ctypes.byref(info),
+                                    None) == H.HIKF_E_INVALID
+    assert H.hikf_import_checkpoint(None, None, None, None, None, ctypes.byref(info),
+                                    None) == H.HIKF_E_INVALID
+    assert H.hikf_export_checkpoint(4096, None, None, None, None, None, None) == H.HIKF_E_INVALID
+    assert H.hikf_import_checkpoint(4096, None, None, None, None, None, None) == H.HIKF_E_INVALID
+
+
+def test_plan_psd_guard_flag():
+    from paper_1404_3816_amd import hikf as H
+    pr = _problem(dim=2, n=64, p=32)
+    op = H.hikf_options()
+    op.n_c, op.fmm_precision = 4, H.HIKF_FMM_F64
+    info = H.hikf_plan_info()
+    op.psd_guard = 0
+    assert H.hikf_plan(ctypes.byref(pr), ctypes.byref(op), ctypes.byref(info)) == H.HIKF_OK
+    base = info.scratch_bytes
+    op.psd_guard = 1
+    assert H.hikf_plan(ctypes.byref(pr), ctypes.byref(op), ctypes.byref(info)) == H.HIKF_OK
+    assert info.scratch_bytes >= base + 3 * 32 * 32 * 8      # three p x p work matrices
+    op.psd_guard = 2
+    assert H.hikf_plan(ctypes.byref(pr), ctypes.byref(op), ctypes.byref(info)) == H.HIKF_E_INVALID
+
+
+def test_plan_lowrank_m2l_threshold():
+    from paper_1404_3816_amd import hikf as H
+    pr = _problem(dim=2, n=256, p=32)
+    op = H.hikf_options()
+    op.n_c, op.fmm_precision = 5, H.HIKF_FMM_F32
+    info = H.hikf_plan_info()
+    assert H.hikf_plan(ctypes.byref(pr), ctypes.byref(op), ctypes.byref(info)) == H.HIKF_OK
+    base = info.scratch_bytes
+    op.m2l_eps = 1e-5
+    assert H.hikf_plan(ctypes.byref(pr), ctypes.byref(op), ctypes.byref(info)) == H.HIKF_OK
+    # compressed M and L of the finest level: 2 x 1024 leaves x 25 nodes x 32 columns
+    assert info.scratch_bytes >= base + 2 * 1024 * 25 * 32 * 4
+    for bad in (-1e-3, 1.0, float("nan")):
+        op.m2l_eps = bad
+        assert H.hikf_plan(ctypes.byref(pr), ctypes.byref(op),
+                           ctypes.byref(info)) == H.HIKF_E_INVALID

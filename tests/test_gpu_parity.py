@@ -366,3 +366,35 @@ def test_largest_2d_order_matches_oracle_bbfmm():
         cq = f.export_cq().cpu().numpy()
         f.close()
         assert rel(cq, ref) < tol, prec
+
+
+# ------------------------------------------------------------------ low-rank M2L
+@pytest.mark.parametrize("dim,n,p,n_c,ell,gamma", [
+    (2, 128, 48, 5, 0.05, 2.0),
+    (2, 256, 32, 5, 0.05, 2.0),    # depth 5: ranks well below r at the fine levels
+    (3, 32, 32, 4, 0.2, 1.0),      # r = 64
+])
+@pytest.mark.parametrize("precision", ["f64", "f32", "bf16x3"])
+def test_cq_lowrank_m2l_matches_oracle(dim, n, p, n_c, ell, gamma, precision):
+    # the low-rank M2L against the oracle's bbFMM with the same singular-value
+    # threshold (same ranks; the bases may differ by rotations inside
+    # subspaces, which leave the projected operators unchanged), and against
+    # the plain bbFMM within the threshold's own error
+    case = Case(dim, n, p, ell=ell, gamma=gamma, steps=1)
+    eps = 1e-5
+    from oracle import bbfmm
+    ref_lr = bbfmm.bbfmm_apply(dim, n, case.h_dense().T, n_c, None, **case.kparams(), svd_eps=eps)
+    ref = case.cq_bbfmm(n_c)
+    f = case.gpu_filter(n_c=n_c, precision=precision, m2l_eps=eps)
+    cq = f.export_cq().cpu().numpy()
+    st = f.query()
+    f.close()
+    ranks = list(st.m2l_ranks)
+    r = n_c ** dim
+    assert all(0 < k <= r for k in ranks[2:len([x for x in ranks if x]) + 2])
+    e_lr, e_plain = rel(cq, ref_lr), rel(cq, ref)
+    print(f"low-rank M2L {precision} ranks {[k for k in ranks if k]} (r = {r}): vs oracle "
+          f"low-rank {e_lr:.3e}, vs oracle dense {e_plain:.3e}")
+    tol = {"f64": 1e-9, "f32": 2e-6, "bf16x3": 1e-4}[precision]
+    assert e_lr < tol
+    assert e_plain < 20 * eps + tol
