@@ -22,6 +22,10 @@ Contents, each a plain NumPy/SciPy restatement of what the paper defines:
 * ``bbfmm``       FP64 black-box FMM with Chebyshev interpolation, the
                   approximation Sec. 3.2 uses for Q H^T (Fong & Darve 2009,
                   cited there); reference for the GPU's H^2 error split.
+* ``enkf``        the perturbed-observation ensemble Kalman filter of
+                  Sec. 2.3 (eqs. ``equation_samplemean``,
+                  ``equation_samplecov1``, ``equation_samplegain_enkf``) on the
+                  random-walk model, with the draws passed in.
 * ``truth``       random-walk truths with covariance Q (Sec. 2.1 eq.
                   ``equation_random_walk``) for building test streams.
 
