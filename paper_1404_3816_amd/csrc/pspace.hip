@@ -21,6 +21,7 @@
 // A non-positive or non-finite pivot sets HIKF_E_NOT_SPD; every later
 // launch, and the row pass, then does nothing, so the state is untouched.
 #include "hikf_internal.h"
+#include "sweep.h"
 
 namespace hikf {
 namespace {
@@ -298,6 +299,28 @@ __global__ void k_ps_finish(int p, int nbk, const double *Gn, const double *hpar
 }
 
 }  // namespace
+
+hipError_t launch_sweep_inverse(const SweepArgs &w, hipStream_t s) {
+    PsArgs a;
+    a.p = w.p;
+    a.PP = w.pp;
+    a.nbk = w.pp / BS;
+    a.G = w.G;
+    a.rdiag = w.rdiag;
+    a.y = w.y;
+    a.hvec = w.hvec;
+    a.A = w.A;
+    a.X = w.X;
+    a.Sinv = w.Sinv;
+    a.nu = w.nu;
+    a.pivs = w.pivs;
+    a.minpiv = w.minpiv;
+    a.status = w.status;
+    a.steps = w.steps;
+    for (int k = 0; k < a.nbk; ++k)
+        hipLaunchKernelGGL(k_ps_sweep, dim3(a.nbk * a.nbk), dim3(NT), 0, s, a, k);
+    return hipGetLastError();
+}
 
 hipError_t launch_pspace(const Geometry &g, const Layout &lay, char *res, const double *y,
                          hipStream_t s) {

@@ -1,4 +1,5 @@
-"""ctypes binding of the C ABI in include/hikf.h (argument marshalling only).
+"""ctypes binding of the C ABI in include/hikf.h and include/hikf_enkf.h
+(argument marshalling only).
 
 Every function keeps its C name and signature; device pointers are passed
 as integers (``tensor.data_ptr()``) and streams as raw ``hipStream_t``
@@ -89,6 +90,28 @@ class hikf_checkpoint_info(ctypes.Structure):
                 ("steps_issued", c_i64), ("p", c_i32), ("carried", c_i32)]
 
 
+class hikf_enkf_problem(ctypes.Structure):
+    _fields_ = [("m", c_i64), ("p", c_i32), ("n_ens", c_i32), ("nnz", c_i64),
+                ("h_rowptr_dev", c_vp), ("h_col_dev", c_vp), ("h_val_dev", c_vp),
+                ("r_diag_dev", c_vp), ("timing", c_i32), ("reserved0", c_i32)]
+
+
+class hikf_enkf_plan_info(ctypes.Structure):
+    _fields_ = [("resident_bytes", c_sz), ("ld", c_i32), ("gather_chunks", c_i32)]
+
+
+HIKF_ENKF_PHASE_GATHER = 0
+HIKF_ENKF_PHASE_NSPACE = 1
+HIKF_ENKF_PHASE_TRANSFORM = 2
+HIKF_ENKF_NUM_PHASES = 4
+
+
+class hikf_enkf_stats(ctypes.Structure):
+    _fields_ = [("steps_applied", c_i64), ("last_status", c_i32), ("init_status", c_i32),
+                ("min_pivot", c_dbl), ("time_ms", c_dbl * HIKF_ENKF_NUM_PHASES),
+                ("time_count", c_i64 * HIKF_ENKF_NUM_PHASES)]
+
+
 _P = ctypes.POINTER
 
 _SIGS = {
@@ -110,6 +133,15 @@ _SIGS = {
     "hikf_destroy": (None, [c_vp]),
     "hikf_status_string": (ctypes.c_char_p, [c_i32]),
     "hikf_last_error": (ctypes.c_char_p, [c_vp]),
+    # include/hikf_enkf.h
+    "hikf_enkf_plan": (c_i32, [_P(hikf_enkf_problem), _P(hikf_enkf_plan_info)]),
+    "hikf_enkf_init": (c_i32, [_P(hikf_enkf_problem), c_vp, c_vp, c_sz, c_vp, _P(c_vp)]),
+    "hikf_enkf_step": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "hikf_enkf_query": (c_i32, [c_vp, _P(hikf_enkf_stats)]),
+    "hikf_enkf_export": (c_i32, [c_vp, c_vp, c_vp]),
+    "hikf_enkf_import": (c_i32, [c_vp, c_vp, c_vp]),
+    "hikf_enkf_destroy": (None, [c_vp]),
+    "hikf_enkf_last_error": (ctypes.c_char_p, [c_vp]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -134,6 +166,14 @@ hikf_export_cq = _lib.hikf_export_cq
 hikf_destroy = _lib.hikf_destroy
 hikf_status_string = _lib.hikf_status_string
 hikf_last_error = _lib.hikf_last_error
+hikf_enkf_plan = _lib.hikf_enkf_plan
+hikf_enkf_init = _lib.hikf_enkf_init
+hikf_enkf_step = _lib.hikf_enkf_step
+hikf_enkf_query = _lib.hikf_enkf_query
+hikf_enkf_export = _lib.hikf_enkf_export
+hikf_enkf_import = _lib.hikf_enkf_import
+hikf_enkf_destroy = _lib.hikf_enkf_destroy
+hikf_enkf_last_error = _lib.hikf_enkf_last_error
 
 
 class HikfError(RuntimeError):

@@ -1,7 +1,8 @@
 """Host-side checks of the C ABI (no GPU calls).
 
-The library must load, export every function include/hikf.h declares, and
-hikf_plan (host only) must validate shapes and report the tree it will build.
+The library must load, export every function include/hikf.h and
+include/hikf_enkf.h declare, and hikf_plan / hikf_enkf_plan (host only) must
+validate shapes and report the workspace they need.
 """
 
 import ctypes
@@ -17,9 +18,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared_functions():
-    src = open(os.path.join(ROOT, "include", "hikf.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(hikf_[a-z_]+)\s*\(", src)))
+    names = set()
+    for header in ("hikf.h", "hikf_enkf.h"):
+        src = open(os.path.join(ROOT, "include", header)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(hikf_[a-z_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
@@ -273,3 +277,43 @@ def test_plan_lowrank_m2l_threshold():
         op.m2l_eps = bad
         assert H.hikf_plan(ctypes.byref(pr), ctypes.byref(op),
                            ctypes.byref(info)) == H.HIKF_E_INVALID
+
+
+def _enkf_problem(m=1000, p=32, n_ens=40, nnz=500):
+    from paper_1404_3816_amd import hikf as H
+    pr = H.hikf_enkf_problem()
+    pr.m, pr.p, pr.n_ens, pr.nnz = m, p, n_ens, nnz
+    fake = 256  # never dereferenced by the plan
+    pr.h_rowptr_dev = pr.h_col_dev = pr.h_val_dev = pr.r_diag_dev = fake
+    return pr
+
+
+@pytest.mark.parametrize("n_ens,ld", [(2, 16), (16, 16), (17, 32), (40, 48), (81, 96), (100, 128),
+                                      (400, 400), (401, 448), (512, 512)])
+def test_enkf_plan_pads_the_ensemble_to_a_tile_width(n_ens, ld):
+    from paper_1404_3816_amd import hikf as H
+    info = H.hikf_enkf_plan_info()
+    pr = _enkf_problem(n_ens=n_ens)
+    assert H.hikf_enkf_plan(ctypes.byref(pr), ctypes.byref(info)) == H.HIKF_OK
+    assert info.ld == ld
+    # the ensemble alone: m rows of ld doubles
+    assert info.resident_bytes >= pr.m * ld * 8
+
+
+@pytest.mark.parametrize("field,value,code", [("n_ens", 1, 1), ("n_ens", 513, 2), ("p", 0, 1),
+                                              ("p", 513, 2), ("m", 0, 1), ("nnz", -1, 1)])
+def test_enkf_plan_rejects_bad_shapes(field, value, code):
+    from paper_1404_3816_amd import hikf as H
+    pr = _enkf_problem()
+    setattr(pr, field, value)
+    info = H.hikf_enkf_plan_info()
+    assert H.hikf_enkf_plan(ctypes.byref(pr), ctypes.byref(info)) == code
+
+
+def test_enkf_plan_rejects_null_arrays():
+    from paper_1404_3816_amd import hikf as H
+    pr = _enkf_problem()
+    pr.r_diag_dev = None
+    info = H.hikf_enkf_plan_info()
+    assert H.hikf_enkf_plan(ctypes.byref(pr), ctypes.byref(info)) == H.HIKF_E_INVALID
+    assert H.hikf_enkf_step(None, None, None, None, None, None, None) == H.HIKF_E_INVALID
