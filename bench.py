@@ -76,6 +76,8 @@ def parse():
                     help="instead of the HiKF job: the ensemble Kalman filter (Sec. 2.3) on "
                          "the workload's grid and rays")
     ap.add_argument("--members", type=int, default=400, help="EnKF: ensemble size N")
+    ap.add_argument("--enkf-tile-rows", type=int, default=0, choices=[0, 32, 64],
+                    help="EnKF: rows per workgroup of the transform (0 = automatic)")
     ap.add_argument("--streams", type=int, default=64, help="serving: filters")
     ap.add_argument("--requests", type=int, default=10000, help="serving: requests per run")
     ap.add_argument("--slots", type=int, default=8, help="serving: device streams")
@@ -87,15 +89,32 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_source_digest():
-    """SHA-256 over the source of the row-pass kernel (rowpass.h) and the
-    shared header."""
+# the sources whose SHA-256 a traffic record carries, per kernel
+KERNEL_SOURCES = {"k_rowpass": ("rowpass.h", "hikf_internal.h"),
+                  "k_en_transform": ("enkf_transform.h", "enkf_internal.h", "hikf_internal.h")}
+
+
+def kernel_source_digest(kernel="k_rowpass"):
+    """SHA-256 over the sources of a dominant kernel (the row pass: rowpass.h
+    and the shared header; the EnKF transform: its unit and headers)."""
     csrc = os.path.join(ROOT, "paper_1404_3816_amd", "csrc")
     h = hashlib.sha256()
-    for name in ("rowpass.h", "hikf_internal.h"):
+    for name in KERNEL_SOURCES[kernel]:
         with open(os.path.join(csrc, name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def calibration_copy(mib):
+    """One plain device-to-device copy of `mib` MiB: the reference kernel
+    whose FETCH_SIZE / WRITE_SIZE readings scale the counters of the others."""
+    import torch
+    nel = mib * 2**20 // 8
+    src = torch.ones(nel, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"[bench] calibration copy of {mib} MiB done")
 
 
 def measured_traffic(workload, kernel):
@@ -106,7 +125,7 @@ def measured_traffic(workload, kernel):
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.md")
     if not os.path.exists(path):
         return None
-    digest = kernel_source_digest()
+    digest = kernel_source_digest(kernel)
     for line in open(path):
         if line.startswith("traffic-record: "):
             rec = json.loads(line[len("traffic-record: "):])
@@ -280,7 +299,7 @@ def enkf_bench(a):
     Vs = [np.sqrt(w["r_var"]) * synth.normal_draws(w["seed"] + 200 + k, p, N) for k in range(K)]
     log(f"[enkf] {a.workload}: m={m} p={p} N={N}, {K} steps per job; inputs drawn in "
         f"{time.perf_counter() - t0:.1f} s")
-    pr, keep = EN.enkf_problem(rowptr, col, val, r, m, N)
+    pr, keep = EN.enkf_problem(rowptr, col, val, r, m, N, tile_rows=a.enkf_tile_rows)
     ld = int(EN.enkf_plan(pr).ld)
     X0d = torch.as_tensor(X0, device="cuda")
     Ed = []
@@ -292,9 +311,12 @@ def enkf_bench(a):
     yd = torch.as_tensor(ys, device="cuda").contiguous()
     mo = torch.empty(m, dtype=torch.float64, device="cuda")
     vo = torch.empty(m, dtype=torch.float64, device="cuda")
+    if a.calibrate_copy_mib:
+        calibration_copy(a.calibrate_copy_mib)
 
     def job(timing=False, steps=K):
-        prb, kp = EN.enkf_problem(rowptr, col, val, r, m, N, timing=timing)
+        prb, kp = EN.enkf_problem(rowptr, col, val, r, m, N, timing=timing,
+                                  tile_rows=a.enkf_tile_rows)
         f = EN.EnkfFilter(prb, X0d, kp)
         for k in range(steps):
             f.step(Ed[k % 2], yd[k], Vd[k], mo, vo)
@@ -345,13 +367,15 @@ def enkf_bench(a):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"enkf-{a.workload}-N{N}", "m": m, "p": p, "members": N,
-                   "ld": ld, "assim_steps_per_job": K,
+                   "ld": ld, "tile_rows": a.enkf_tile_rows or 64,
+                   "assim_steps_per_job": K,
                    "inputs": "white-noise X_0 and model-error draws (theta = 1)"},
         "phase_avg_ms": {k: (round(v, 4) if v is not None else None) for k, v in ph.items()},
         "roofline": {"bound": "mfma", "kernel": "k_en_transform (FP64 MFMA)",
                      "achieved": round(flops / (t_tf * 1e-3) / 1e12, 3), "peak": 78.6,
                      "unit": "TFLOP/s", "frac": round(flops / (t_tf * 1e-3) / 78.6e12, 4),
-                     "traffic": None, "algorithmic_bytes": int(24 * m * N),
+                     "traffic": measured_traffic(f"enkf-{a.workload}-N{N}", "k_en_transform"),
+                     "traffic_unit": "bytes/launch", "algorithmic_bytes": int(24 * m * N),
                      "avg_ms": round(t_tf, 4)},
         "accuracy": acc, "failed_jobs": failed,
         "cpu_baseline": {"value": round(1.0 / t_step_cpu, 5), "unit": "assim steps/s",
@@ -549,13 +573,7 @@ def main():
     stream = torch.cuda.current_stream()
     sh = ctypes.c_void_p(stream.cuda_stream)
     if a.calibrate_copy_mib:
-        nel = a.calibrate_copy_mib * 2**20 // 8
-        src = torch.ones(nel, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"[bench] calibration copy of {a.calibrate_copy_mib} MiB done")
-        del src, dst
+        calibration_copy(a.calibrate_copy_mib)
     log(f"[bench] resident {info.resident_bytes / 2**30:.2f} GiB, scratch "
         f"{info.scratch_bytes / 2**30:.2f} GiB, depth {info.depth}, near pairs "
         f"{info.near_pairs}, far pairs {info.far_pairs}")

@@ -11,7 +11,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhikf.so")
-SOURCES = ["api.hip", "fmm.hip", "step.hip", "pspace.hip", "enkf.hip", "enkf_transform.hip"] + [
+SOURCES = ["api.hip", "fmm.hip", "step.hip", "pspace.hip", "enkf.hip"] + [
+    f"enkf_transform_{k}.hip" for k in "abcde"] + [
     f"rowpass_{t}_{k}.hip" for t in ("f32", "f64") for k in (1, 2, 3, 4)]
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

@@ -17,6 +17,7 @@
 //   k_en_gemm (twice)          Z = S^{-1} D, T = (H A)^T Z   (N x N)
 //   k_en_wmat                  W = I + (I - 1 1^T / N) T / sqrt(N - 1)
 //   launch_enkf_transform      X <- (X + E) W, mean and variance rows
+//                              (enkf_transform.h)
 // so that every member gets x^j + K~ (d^j - H x^j) with K~ = A (H A)^T S^{-1}:
 // (X + E) W = X_f + A T.  A failed step (S not positive definite, a NaN or
 // Inf in y, V or the innovations) skips the transform: the ensemble is
@@ -242,43 +243,67 @@ k_en_gemm(int M, int N, int K, const double *A, int lda, const double *B, int ld
         }
 }
 
-// W = I + (T - 1 colmean(T)) / sqrt(N - 1) on the N x N block, 0 elsewhere
-// (one thread per column j); a non-finite T entry fails the step
-__global__ void k_en_wmat(int ld, int n_ens, const double *T, double *W, int *status) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= ld) return;
+// W = I + (T - 1 colmean(T)) / sqrt(N - 1) on the N x N block, 0 elsewhere:
+// one workgroup per column j (the column mean summed in a fixed order); a
+// non-finite T entry fails the step
+__global__ void __launch_bounds__(256) k_en_wmat(int ld, int n_ens, const double *T, double *W,
+                                                 int *status) {
+    __shared__ double red[256];
+    __shared__ int bad;
+    const int j = blockIdx.x, t = threadIdx.x;
     if (status[kStStep] != HIKF_OK) return;
+    if (t == 0) bad = 0;
     const bool in = j < n_ens;
-    double cm = 0.0;
-    int bad = 0;
-    if (in) {
-        for (int i = 0; i < n_ens; ++i) {
+    double s = 0.0;
+    int b = 0;
+    if (in)
+        for (int i = t; i < n_ens; i += 256) {
             const double v = T[int64_t(i) * ld + j];
-            if (!isfinite(v)) bad = 1;
-            cm += v;
+            if (!isfinite(v)) b = 1;
+            s += v;
         }
-        cm /= n_ens;
+    red[t] = s;
+    __syncthreads();
+    if (b) bad = 1;
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
     }
-    const double sc = 1.0 / sqrt(double(n_ens - 1));
-    for (int i = 0; i < ld; ++i) {
+    const double cm = red[0] / n_ens, sc = 1.0 / sqrt(double(n_ens - 1));
+    for (int i = t; i < ld; i += 256) {
         double w = 0.0;
         if (in && i < n_ens) w = (i == j ? 1.0 : 0.0) + (T[int64_t(i) * ld + j] - cm) * sc;
         W[int64_t(i) * ld + j] = w;
     }
-    if (bad) status[kStStep] = HIKF_E_INVALID;
+    if (t == 0 && bad) status[kStStep] = HIKF_E_INVALID;
 }
 
 template <typename T>
 T *at(char *base, size_t off) { return reinterpret_cast<T *>(base + off); }
 
 }  // namespace
+
+hipError_t launch_enkf_transform(int tile_rows, int64_t m, int n_ens, int ld, double *X,
+                                 const double *E, const double *W, double *xmean, double *xvar,
+                                 const int *status, long long *applied, hipStream_t s) {
+    switch (ld / 16) {
+#define HIKF_EN_CASE(N) \
+    case N: return enkf_transform_nt<N>(tile_rows, m, n_ens, X, E, W, xmean, xvar, status, applied, s);
+        HIKF_EN_CASE(1) HIKF_EN_CASE(2) HIKF_EN_CASE(3) HIKF_EN_CASE(4) HIKF_EN_CASE(5)
+        HIKF_EN_CASE(6) HIKF_EN_CASE(8) HIKF_EN_CASE(10) HIKF_EN_CASE(12) HIKF_EN_CASE(16)
+        HIKF_EN_CASE(20) HIKF_EN_CASE(24) HIKF_EN_CASE(25) HIKF_EN_CASE(28) HIKF_EN_CASE(32)
+#undef HIKF_EN_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace hikf
 
 using namespace hikf;
 
 struct hikf_enkf {
     int64_t m = 0, nnz = 0;
-    int p = 0, n = 0, ld = 0, pp = 0, nchunks = 0, device = 0;
+    int p = 0, n = 0, ld = 0, pp = 0, nchunks = 0, device = 0, tile_rows = 0;
     bool timing = false;
     char *res = nullptr;
     EnLayout L{};
@@ -302,6 +327,7 @@ hikf_status en_check(const hikf_enkf_problem *pr) {
     if (!pr || pr->m < 1 || pr->p < 1 || pr->n_ens < 2 || pr->nnz < 0) return HIKF_E_INVALID;
     if (!pr->h_rowptr_dev || !pr->r_diag_dev) return HIKF_E_INVALID;
     if (pr->nnz > 0 && (!pr->h_col_dev || !pr->h_val_dev)) return HIKF_E_INVALID;
+    if (pr->tile_rows != 0 && pr->tile_rows != 32 && pr->tile_rows != 64) return HIKF_E_INVALID;
     if (pr->p > kMaxP || pr->n_ens > kEnMaxMembers) return HIKF_E_UNSUPPORTED;
     return HIKF_OK;
 }
@@ -367,6 +393,7 @@ hikf_status hikf_enkf_init(const hikf_enkf_problem *pr, const double *x0_dev,
     f->ld = ld;
     f->pp = (pr->p + 31) / 32 * 32;
     f->timing = pr->timing != 0;
+    f->tile_rows = pr->tile_rows;
     f->res = static_cast<char *>(resident_dev);
     f->L = L;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -498,13 +525,14 @@ hikf_status hikf_enkf_step(hikf_enkf *f, const double *e_dev, const double *y_de
     hipLaunchKernelGGL((k_en_gemm<true, false>), dim3(tiles(ld, ld)), dim3(256), 0, st, ld, ld, p,
                        at<const double>(r, L.HA), ld, at<const double>(r, L.Z), ld,
                        at<double>(r, L.T), ld, status);
-    hipLaunchKernelGGL(k_en_wmat, dim3((ld + 255) / 256), dim3(256), 0, st, ld, n,
+    hipLaunchKernelGGL(k_en_wmat, dim3(ld), dim3(256), 0, st, ld, n,
                        at<const double>(r, L.T), at<double>(r, L.W), status);
     mark(HIKF_ENKF_PHASE_NSPACE, 1);
 
     mark(HIKF_ENKF_PHASE_TRANSFORM, 0);
     if (e == hipSuccess)
-        e = launch_enkf_transform(f->m, n, ld, at<double>(r, L.X), e_dev, at<const double>(r, L.W),
+        e = launch_enkf_transform(f->tile_rows, f->m, n, ld, at<double>(r, L.X), e_dev,
+                                  at<const double>(r, L.W),
                                   at<double>(r, L.xmean), at<double>(r, L.xvar), status,
                                   at<long long>(r, L.applied), st);
     mark(HIKF_ENKF_PHASE_TRANSFORM, 1);

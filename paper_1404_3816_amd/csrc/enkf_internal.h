@@ -1,5 +1,5 @@
-// Internal declarations of the ensemble Kalman filter sources (enkf.hip,
-// enkf_transform.hip); not part of the ABI.
+// Internal declarations of the ensemble Kalman filter sources (enkf.hip and
+// the enkf_transform_*.hip units); not part of the ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -21,10 +21,17 @@ inline int enkf_ld(int n_ens) {
 
 // X <- (X + E) W on the m rows of the ensemble (pitch ld), with the row
 // means and variances over the first n_ens columns in xmean / xvar; E may be
-// null.  Does nothing when status[kStStep] is not HIKF_OK; otherwise adds
-// one to applied[0].
-hipError_t launch_enkf_transform(int64_t m, int n_ens, int ld, double *X, const double *E,
-                                 const double *W, double *xmean, double *xvar,
+// null.  tile_rows: rows per workgroup, 32 or 64 (0 = by ld).  Does nothing
+// when status[kStStep] is not HIKF_OK; otherwise adds one to applied[0].
+hipError_t launch_enkf_transform(int tile_rows, int64_t m, int n_ens, int ld, double *X,
+                                 const double *E, const double *W, double *xmean, double *xvar,
                                  const int *status, long long *applied, hipStream_t s);
+
+// the transform for ld = 16 NT (defined in enkf_transform.h, instantiated
+// by one of the enkf_transform_*.hip units)
+template <int NT>
+hipError_t enkf_transform_nt(int tile_rows, int64_t m, int n_ens, double *X, const double *E,
+                             const double *W, double *xmean, double *xvar, const int *status,
+                             long long *applied, hipStream_t s);
 
 }  // namespace hikf

@@ -1,4 +1,6 @@
-// Ensemble transform of the EnKF analysis (Sec. 2.3): X <- (X + E) W for all
+// Ensemble transform of the EnKF analysis (Sec. 2.3), included by the
+// enkf_transform_*.hip units (each instantiates a few tile widths, so that
+// the kernels compile in parallel): X <- (X + E) W for all
 // m member rows, with the analysis sample mean (eq. equation_samplemean) and
 // the diagonal of the sample covariance (eq. equation_samplecov1) of every
 // row.  W = I + (I - 1 1^T / N) T / sqrt(N - 1) is the N x N matrix formed in
@@ -17,6 +19,8 @@
 // (pitch ld + 8 doubles), prefetched into registers one block ahead.  Every
 // row is read and written once; the row is written in place (a workgroup
 // has loaded all of its rows before its first store).
+#pragma once
+
 #include "enkf_internal.h"
 #include "hikf_internal.h"
 
@@ -230,12 +234,11 @@ k_en_transform(int64_t m, int n_ens, double *X, const double *E, const double *W
 #undef HIKF_EN_PART
 }
 
-template <int NT>
-hipError_t en_go(int64_t m, int n_ens, double *X, const double *E, const double *W,
-                 double *xmean, double *xvar, const int *status, long long *applied,
-                 hipStream_t s) {
-    // ld <= 256: 4 row groups x 2 column halves; ld <= 512: 2 x 4 quarters
-    constexpr int RG = NT * 16 <= 256 ? 4 : 2, CS = 8 / RG;
+template <int NT, int RG>
+hipError_t en_go_rg(int64_t m, int n_ens, double *X, const double *E, const double *W,
+                    double *xmean, double *xvar, const int *status, long long *applied,
+                    hipStream_t s) {
+    constexpr int CS = 8 / RG;
     const unsigned blocks = unsigned((m + 16 * RG - 1) / (16 * RG));
     if (E)
         hipLaunchKernelGGL((k_en_transform<NT, CS, RG, true>), dim3(blocks), dim3(64 * CS * RG), 0,
@@ -246,20 +249,27 @@ hipError_t en_go(int64_t m, int n_ens, double *X, const double *E, const double 
     return hipGetLastError();
 }
 
+// tile_rows 64 (and 0): 4 row groups x 2 column halves; 32: 2 row groups x
+// 4 column quarters (fewer accumulators per wave, twice the LDS reads of W
+// per row).  Measured on 1024^2 rows: 64-row tiles are faster at every ld
+// (N = 256: 2.67 vs 3.44 ms, N = 400: 6.27 vs 8.04, N = 512: 9.26 vs 11.73),
+// although at ld >= 448 a wave spills a few registers.
+template <int NT>
+hipError_t en_go(int tile_rows, int64_t m, int n_ens, double *X, const double *E, const double *W,
+                 double *xmean, double *xvar, const int *status, long long *applied,
+                 hipStream_t s) {
+    if (tile_rows != 32) return en_go_rg<NT, 4>(m, n_ens, X, E, W, xmean, xvar, status, applied, s);
+    return en_go_rg<NT, 2>(m, n_ens, X, E, W, xmean, xvar, status, applied, s);
+}
+
 }  // namespace
 
-hipError_t launch_enkf_transform(int64_t m, int n_ens, int ld, double *X, const double *E,
-                                 const double *W, double *xmean, double *xvar,
-                                 const int *status, long long *applied, hipStream_t s) {
-    switch (ld / 16) {
-#define HIKF_EN_CASE(N) \
-    case N: return en_go<N>(m, n_ens, X, E, W, xmean, xvar, status, applied, s);
-        HIKF_EN_CASE(1) HIKF_EN_CASE(2) HIKF_EN_CASE(3) HIKF_EN_CASE(4) HIKF_EN_CASE(5)
-        HIKF_EN_CASE(6) HIKF_EN_CASE(8) HIKF_EN_CASE(10) HIKF_EN_CASE(12) HIKF_EN_CASE(16)
-        HIKF_EN_CASE(20) HIKF_EN_CASE(24) HIKF_EN_CASE(25) HIKF_EN_CASE(28) HIKF_EN_CASE(32)
-#undef HIKF_EN_CASE
-    default: return hipErrorInvalidValue;
-    }
+// one tile width: the unit that instantiates it compiles its kernels
+template <int NT>
+hipError_t enkf_transform_nt(int tile_rows, int64_t m, int n_ens, double *X, const double *E,
+                             const double *W, double *xmean, double *xvar, const int *status,
+                             long long *applied, hipStream_t s) {
+    return en_go<NT>(tile_rows, m, n_ens, X, E, W, xmean, xvar, status, applied, s);
 }
 
 }  // namespace hikf

@@ -13,8 +13,9 @@ from . import hikf as H
 from .filter import _stream_handle
 
 
-def enkf_problem(rowptr, col, val, r_diag, m, n_ens, timing=False, device="cuda"):
-    """(hikf_enkf_problem, keepalive): device copies of H (CSR) and R."""
+def enkf_problem(rowptr, col, val, r_diag, m, n_ens, timing=False, tile_rows=0, device="cuda"):
+    """(hikf_enkf_problem, keepalive): device copies of H (CSR) and R;
+    tile_rows: rows per workgroup of the transform (0 = automatic)."""
     t_rowptr = torch.as_tensor(rowptr, dtype=torch.int64).to(device).contiguous()
     t_col = torch.as_tensor(col, dtype=torch.int32).to(device).contiguous()
     t_val = torch.as_tensor(val, dtype=torch.float64).to(device).contiguous()
@@ -27,6 +28,7 @@ def enkf_problem(rowptr, col, val, r_diag, m, n_ens, timing=False, device="cuda"
     pr.h_val_dev = t_val.data_ptr() if t_val.numel() else None
     pr.r_diag_dev = t_r.data_ptr()
     pr.timing = 1 if timing else 0
+    pr.tile_rows = int(tile_rows)
     return pr, (t_rowptr, t_col, t_val, t_r)
 
 

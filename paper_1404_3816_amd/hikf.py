@@ -93,7 +93,7 @@ class hikf_checkpoint_info(ctypes.Structure):
 class hikf_enkf_problem(ctypes.Structure):
     _fields_ = [("m", c_i64), ("p", c_i32), ("n_ens", c_i32), ("nnz", c_i64),
                 ("h_rowptr_dev", c_vp), ("h_col_dev", c_vp), ("h_val_dev", c_vp),
-                ("r_diag_dev", c_vp), ("timing", c_i32), ("reserved0", c_i32)]
+                ("r_diag_dev", c_vp), ("timing", c_i32), ("tile_rows", c_i32)]
 
 
 class hikf_enkf_plan_info(ctypes.Structure):

@@ -73,11 +73,11 @@ class EnCase:
     def oracle(self):
         return oracle_enkf.enkf_run(self.X0, self.H, self.r, self.ys, self.Es, self.Vs)
 
-    def gpu(self, timing=False):
+    def gpu(self, timing=False, tile_rows=0):
         import torch
         from paper_1404_3816_amd import enkf as EN
         pr, keep = EN.enkf_problem(self.rowptr, self.col, self.val, self.r, self.m, self.N,
-                                   timing=timing)
+                                   timing=timing, tile_rows=tile_rows)
         f = EN.EnkfFilter(pr, torch.as_tensor(self.X0, device="cuda"), keep)
         means, vars_ = [], []
         for k in range(self.steps):
@@ -114,6 +114,18 @@ def test_enkf_matches_oracle(n, p, N):
     assert em < TOL and ex < TOL and ev < vtol
     # elementwise on the ensemble, relative to its scale
     assert np.max(np.abs(Xg - Xo)) < TOL * np.max(np.abs(Xo))
+
+
+@pytest.mark.parametrize("N", [100, 400])
+def test_enkf_tile_forms_match_oracle(N):
+    # 32-row tiles (four column quarters per row group) against the oracle;
+    # the default 64-row form is covered above
+    case = EnCase(37, 32, N, steps=2)
+    Xo, mo, vo = case.oracle()
+    Xg, mg, vg, st = case.gpu(tile_rows=32)
+    assert st.steps_applied == case.steps
+    assert _rel(Xg, Xo) < TOL and _rel(mg[-1], mo[-1]) < TOL
+    assert _rel(vg[-1], vo[-1]) < _var_tol(Xo, vo[-1])
 
 
 def test_enkf_without_model_error():
@@ -180,3 +192,49 @@ def test_enkf_bad_h_poisons_the_filter():
     assert st.init_status == 1 and st.last_status == 1 and st.steps_applied == 0
     assert torch.equal(f.export(), before)
     f.close()
+
+
+def test_enkf_fullsize_matches_oracle_on_sampled_rows():
+    """1024 x 1024 grid, p = 256 crosswell rays, N = 400 members, two steps,
+    in the bench's launch configuration (64-row transform tiles).  The
+    analysis couples rows only through H X, i.e. through the ray cells, so
+    the oracle run on the ray cells plus 256 report rows is exact for those
+    rows.  Inputs: white-noise initial ensemble and model-error draws."""
+    import scipy.sparse as sp
+    import torch
+    from paper_1404_3816_amd import enkf as EN
+    w = synth.workload("crosswell-1024x1024-p256")
+    n, p, m, N, K = w["n"], w["p"], w["m"], 400, 2
+    rowptr, col, val = synth.crosswell_h(2, n, p, planes=8)
+    r = np.full(p, w["r_var"])
+    ys = synth.plume_observations(2, n, rowptr, col, val, K, w["r_var"], w["seed"] + 1)
+    X0 = synth.normal_draws(w["seed"] + 101, m, N)
+    Es = [synth.normal_draws(w["seed"] + 102 + k, m, N) for k in range(K)]
+    Vs = [np.sqrt(w["r_var"]) * synth.normal_draws(w["seed"] + 200 + k, p, N) for k in range(K)]
+    report = np.random.default_rng(7).choice(m, 256, replace=False)
+    rows = np.union1d(np.unique(col), report)
+    pos = np.searchsorted(rows, report)
+    Hs = sp.csr_matrix((val, col, rowptr), shape=(p, m))[:, rows].tocsr()
+    Xo, mo, vo = oracle_enkf.enkf_run(X0[rows], Hs, r, ys, [E[rows] for E in Es], Vs)
+
+    pr, keep = EN.enkf_problem(rowptr, col, val, r, m, N)
+    f = EN.EnkfFilter(pr, torch.as_tensor(X0, device="cuda"), keep)
+    assert f.ld == N
+    rd = torch.as_tensor(report, device="cuda")
+    mg, vg = [], []
+    mout = torch.empty(m, dtype=torch.float64, device="cuda")
+    vout = torch.empty(m, dtype=torch.float64, device="cuda")
+    for k in range(K):
+        f.step(torch.as_tensor(Es[k], device="cuda"), torch.as_tensor(ys[k], device="cuda"),
+               torch.as_tensor(Vs[k], device="cuda"), mout, vout)
+        mg.append(mout[rd].cpu().numpy())
+        vg.append(vout[rd].cpu().numpy())
+    Xg = f.export()[rd].cpu().numpy()
+    st = f.query()
+    f.close()
+    assert st.last_status == 0 and st.steps_applied == K
+    em = max(_rel(mg[k], mo[k][pos]) for k in range(K))
+    ev = max(_rel(vg[k], vo[k][pos]) for k in range(K))
+    ex = _rel(Xg, Xo[pos])
+    print(f"[enkf fullsize] mean {em:.2e} var {ev:.2e} ensemble rows {ex:.2e}")
+    assert em < TOL and ex < TOL and ev < _var_tol(Xo[pos], vo[-1][pos])
