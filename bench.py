@@ -76,7 +76,7 @@ def parse():
                     help="instead of the HiKF job: the ensemble Kalman filter (Sec. 2.3) on "
                          "the workload's grid and rays")
     ap.add_argument("--members", type=int, default=400, help="EnKF: ensemble size N")
-    ap.add_argument("--enkf-tile-rows", type=int, default=0, choices=[0, 32, 64],
+    ap.add_argument("--enkf-tile-rows", type=int, default=0, choices=[0, 32, 64, 128],
                     help="EnKF: rows per workgroup of the transform (0 = automatic)")
     ap.add_argument("--streams", type=int, default=64, help="serving: filters")
     ap.add_argument("--requests", type=int, default=10000, help="serving: requests per run")
@@ -367,7 +367,7 @@ def enkf_bench(a):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"enkf-{a.workload}-N{N}", "m": m, "p": p, "members": N,
-                   "ld": ld, "tile_rows": a.enkf_tile_rows or 64,
+                   "ld": ld, "tile_rows": a.enkf_tile_rows or (128 if ld <= 256 else 64),
                    "assim_steps_per_job": K,
                    "inputs": "white-noise X_0 and model-error draws (theta = 1)"},
         "phase_avg_ms": {k: (round(v, 4) if v is not None else None) for k, v in ph.items()},

@@ -49,7 +49,8 @@ typedef struct hikf_enkf_problem {
     const double  *r_diag_dev;   /* [p], finite and > 0                        */
     int32_t timing;              /* 1: HIP events around the step's phases     */
     int32_t tile_rows;           /* rows per workgroup of the ensemble
-                                    transform: 32, 64, or 0 = automatic (64)  */
+                                    transform: 32, 64, 128 (N <= 256 only), or
+                                    0 = automatic (128 for N <= 256, else 64) */
 } hikf_enkf_problem;
 
 typedef struct hikf_enkf_plan_info {
@@ -83,9 +84,9 @@ typedef struct hikf_enkf hikf_enkf;
 /*
  * Validate a problem and report the workspace (host only, reads no device
  * memory).  Errors: HIKF_E_INVALID (m < 1, p < 1, N < 2, nnz < 0, NULL
- * arrays, tile_rows not 0, 32 or 64), HIKF_E_UNSUPPORTED (p > 512 or
+ * arrays, tile_rows not 0, 32, 64 or 128), HIKF_E_UNSUPPORTED (p > 512 or
  * N > 512: the transform keeps a member row in the registers of a wave and
- * the sweep inverse handles p <= 512).
+ * the sweep inverse handles p <= 512; tile_rows 128 with N > 256).
  */
 hikf_status hikf_enkf_plan(const hikf_enkf_problem *prob, hikf_enkf_plan_info *out);
 

@@ -327,7 +327,9 @@ hikf_status en_check(const hikf_enkf_problem *pr) {
     if (!pr || pr->m < 1 || pr->p < 1 || pr->n_ens < 2 || pr->nnz < 0) return HIKF_E_INVALID;
     if (!pr->h_rowptr_dev || !pr->r_diag_dev) return HIKF_E_INVALID;
     if (pr->nnz > 0 && (!pr->h_col_dev || !pr->h_val_dev)) return HIKF_E_INVALID;
-    if (pr->tile_rows != 0 && pr->tile_rows != 32 && pr->tile_rows != 64) return HIKF_E_INVALID;
+    if (pr->tile_rows != 0 && pr->tile_rows != 32 && pr->tile_rows != 64 && pr->tile_rows != 128)
+        return HIKF_E_INVALID;
+    if (pr->tile_rows == 128 && pr->n_ens > 256) return HIKF_E_UNSUPPORTED;
     if (pr->p > kMaxP || pr->n_ens > kEnMaxMembers) return HIKF_E_UNSUPPORTED;
     return HIKF_OK;
 }

@@ -223,10 +223,11 @@ k_en_transform(int64_t m, int n_ens, double *X, const double *E, const double *W
     if (blockIdx.x == 0 && threadIdx.x == 0) applied[0] += 1;
     const int part = (threadIdx.x >> 6) / RG;
 #define HIKF_EN_PART(K) en_part<NT, CS, RG, (K), HAS_E>(sB, red, red2, m, n_ens, X, E, W, xmean, xvar)
-    if (part == 0)
+    // (with one column part only part 0 exists: no other part is compiled)
+    if (CS == 1 || part == 0)
         HIKF_EN_PART(0);
     else if (part == 1)
-        HIKF_EN_PART(1);
+        HIKF_EN_PART(CS > 1 ? 1 : 0);
     else if (CS > 2 && part == 2)
         HIKF_EN_PART(CS > 2 ? 2 : 0);
     else if (CS > 3)
@@ -249,15 +250,23 @@ hipError_t en_go_rg(int64_t m, int n_ens, double *X, const double *E, const doub
     return hipGetLastError();
 }
 
-// tile_rows 64 (and 0): 4 row groups x 2 column halves; 32: 2 row groups x
-// 4 column quarters (fewer accumulators per wave, twice the LDS reads of W
-// per row).  Measured on 1024^2 rows: 64-row tiles are faster at every ld
-// (N = 256: 2.67 vs 3.44 ms, N = 400: 6.27 vs 8.04, N = 512: 9.26 vs 11.73),
-// although at ld >= 448 a wave spills a few registers.
+// tile_rows 64: 4 row groups x 2 column halves; 32: 2 row groups x 4
+// column quarters (fewer accumulators per wave, twice the LDS reads of W
+// per row); 128 (ld <= 256): 8 row groups, every wave on all columns (twice
+// the MFMAs per k block and per slab of W); 0: 128 up to ld = 256, else 64.
+// Measured on 1024^2 rows (ms, fraction of the FP64 peak):
+//   N = 128: 128 rows 0.69 (0.64), 64 rows 0.82 (0.53)
+//   N = 256: 128 rows 2.41 (0.73), 64 rows 2.67 (0.66), 32 rows 3.44
+//   N = 400: 64 rows 6.27 (0.68), 32 rows 8.04;  N = 512: 64 rows 9.26
+//   (0.76), 32 rows 11.73 (at ld >= 448 a wave spills a few registers).
 template <int NT>
 hipError_t en_go(int tile_rows, int64_t m, int n_ens, double *X, const double *E, const double *W,
                  double *xmean, double *xvar, const int *status, long long *applied,
                  hipStream_t s) {
+    if constexpr (NT <= 16) {
+        if (tile_rows == 128 || tile_rows == 0)
+            return en_go_rg<NT, 8>(m, n_ens, X, E, W, xmean, xvar, status, applied, s);
+    }
     if (tile_rows != 32) return en_go_rg<NT, 4>(m, n_ens, X, E, W, xmean, xvar, status, applied, s);
     return en_go_rg<NT, 2>(m, n_ens, X, E, W, xmean, xvar, status, applied, s);
 }

@@ -55,7 +55,7 @@ def make_options(n_c=4, precision="f32", direct=False, timing=False, graph=False
                  history=0, sparse=False, rowpass_variant=None, tune_cache=None,
                  psd_guard=False, m2l_eps=0.0):
     """hikf_options; rowpass_variant None = automatic (tuning cache or the
-    built-in default), else the variant 0..3 to force."""
+    built-in default), else the variant 0..7 to force."""
     op = H.hikf_options()
     op.n_c = int(n_c)
     op.fmm_precision = PRECISIONS[precision]

@@ -116,13 +116,16 @@ def test_enkf_matches_oracle(n, p, N):
     assert np.max(np.abs(Xg - Xo)) < TOL * np.max(np.abs(Xo))
 
 
-@pytest.mark.parametrize("N", [100, 400])
-def test_enkf_tile_forms_match_oracle(N):
-    # 32-row tiles (four column quarters per row group) against the oracle;
-    # the default 64-row form is covered above
+@pytest.mark.parametrize("N,tile_rows", [(100, 32), (400, 32), (100, 64), (256, 64),
+                                        (100, 128), (256, 128)])
+def test_enkf_tile_forms_match_oracle(N, tile_rows):
+    # every transform tile form against the oracle: 32-row tiles (four
+    # column quarters per row group), 64-row tiles (two halves; the default
+    # above N = 256) and 128-row tiles (every wave on all columns; the
+    # default up to N = 256)
     case = EnCase(37, 32, N, steps=2)
     Xo, mo, vo = case.oracle()
-    Xg, mg, vg, st = case.gpu(tile_rows=32)
+    Xg, mg, vg, st = case.gpu(tile_rows=tile_rows)
     assert st.steps_applied == case.steps
     assert _rel(Xg, Xo) < TOL and _rel(mg[-1], mo[-1]) < TOL
     assert _rel(vg[-1], vo[-1]) < _var_tol(Xo, vo[-1])
