@@ -1080,6 +1080,8 @@ k_m2l_bf16(int dim, int r, int p, int lev, const __bf16 *Mh, const __bf16 *Ml,
            const __bf16 *Th, const __bf16 *Tl, float *L) {
     constexpr int NCT = PT / 16;
     constexpr int MAXT = 8;                            // tiles per wave
+    constexpr int CW = NCT / 4;                        // column tiles per wave
+    static_assert(NCT % 4 == 0 && CW <= MAXT, "column tiles must split over the 4 waves");
     constexpr int KP = KR + 8;
     constexpr int KCH = KR / 8;                        // 16-byte chunks per row
     constexpr int TPT = (KR * KCH + kBlock - 1) / kBlock;   // T chunks per thread (rt16 <= KR)
@@ -1160,21 +1162,32 @@ k_m2l_bf16(int dim, int r, int p, int lev, const __bf16 *Mh, const __bf16 *Ml,
         __syncthreads();
         const int on = next_il(oi);
         if (on < noff) HIKF_M2L_FETCH(on);             // in flight during the MFMAs
+        // the wave's tiles are every row tile rt < RT times the column tiles
+        // wave + 4 c (c < CW), u = rt CW + c: per k step the hi / lo A values
+        // of a row tile and B values of a column tile feed independent MFMAs
+        // (128^3, r = 64: 146 -> 129 ms over the levels; in the FP32 / FP64
+        // kernel above the same order measured slower, 3.52 -> 3.78 ms at
+        // 1024^2, r = 25, so that one keeps a tile's k loop innermost)
 #pragma unroll
-        for (int u = 0; u < MAXT; ++u) {
-            const int tile = wave + 4 * u;
-            if (tile >= ntiles) break;                 // uniform per wave
-            const int rt = tile / NCT, ct = tile % NCT;
-            const __bf16 *ah = sTh + (16 * rt + lr) * KP + 8 * q;
-            const __bf16 *al = sTl + (16 * rt + lr) * KP + 8 * q;
-            const __bf16 *bh = sMh + (16 * ct + lr) * KP + 8 * q;
-            const __bf16 *bl = sMl + (16 * ct + lr) * KP + 8 * q;
+        for (int k0 = 0; k0 < KR; k0 += 32) {
+            bf8 bh[CW], bl[CW];
 #pragma unroll
-            for (int k0 = 0; k0 < KR; k0 += 32)
-                acc[u] = mma_bf16<SPLIT>(*reinterpret_cast<const bf8 *>(ah + k0),
-                                         *reinterpret_cast<const bf8 *>(al + k0),
-                                         *reinterpret_cast<const bf8 *>(bh + k0),
-                                         *reinterpret_cast<const bf8 *>(bl + k0), acc[u]);
+            for (int c = 0; c < CW; ++c) {
+                const int off = (16 * (wave + 4 * c) + lr) * KP + 8 * q + k0;
+                bh[c] = *reinterpret_cast<const bf8 *>(sMh + off);
+                bl[c] = *reinterpret_cast<const bf8 *>(sMl + off);
+            }
+#pragma unroll
+            for (int rt = 0; rt < MAXT / CW; ++rt) {
+                if (rt < RT) {                          // uniform
+                    const int off = (16 * rt + lr) * KP + 8 * q + k0;
+                    const bf8 ah = *reinterpret_cast<const bf8 *>(sTh + off);
+                    const bf8 al = *reinterpret_cast<const bf8 *>(sTl + off);
+#pragma unroll
+                    for (int c = 0; c < CW; ++c)
+                        acc[rt * CW + c] = mma_bf16<SPLIT>(ah, al, bh[c], bl[c], acc[rt * CW + c]);
+                }
+            }
         }
         oi = on;
     }
@@ -1562,11 +1575,19 @@ hipError_t run_lowrank_m2l(const Geometry &g, const Layout &lay, char *scr, hipS
             }
         }
         if (!done) {
-            constexpr int MPT = sizeof(T) == 4 ? 128 : 64;
+            // the column tile of the dense M2L below (twice as wide at k <= 32)
+            constexpr int MPT = sizeof(T) == 4 ? 128 : 64, MPTW = 2 * MPT;
             const int RT = (k + 15) / 16, KR = (k + 3) / 4 * 4;
-            const size_t lds = (size_t(KR) * (MPT + Mma<T>::pad) + size_t(16 * RT) * 68) * sizeof(T);
-            const dim3 grid(unsigned(nbx), (p + MPT - 1) / MPT);
-            if (k <= 32) {
+            const bool wide = k <= 32 && p > MPT;
+            const int pt = wide ? MPTW : MPT;
+            const size_t lds = (size_t(KR) * (pt + Mma<T>::pad) + size_t(16 * RT) * 68) * sizeof(T);
+            const dim3 grid(unsigned(nbx), (p + pt - 1) / pt);
+            if (wide) {
+                e = allow_lds(k_trans_mma<T, MPTW, 32, kM2L>, lds);
+                if (e != hipSuccess) return e;
+                hipLaunchKernelGGL((k_trans_mma<T, MPTW, 32, kM2L>), grid, dim3(kBlock), lds, s, dim, k,
+                                   p, lev, static_cast<const T *>(MT), Cl, LT);
+            } else if (k <= 32) {
                 e = allow_lds(k_trans_mma<T, MPT, 32, kM2L>, lds);
                 if (e != hipSuccess) return e;
                 hipLaunchKernelGGL((k_trans_mma<T, MPT, 32, kM2L>), grid, dim3(kBlock), lds, s, dim, k,
@@ -1727,15 +1748,26 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
             }
         }
         if (!bf16 && !lowrank) {
-            constexpr int MPT = sizeof(T) == 4 ? 128 : 64;
+            // column tile: with r <= 32 the output is 2 node tiles high, so a
+            // tile twice as wide (256 FP32 / 128 FP64 columns) still fits 8
+            // MFMA tiles per wave and doubles the products per staged source
+            // (1024^2, p = 256, r = 25: 3.85 -> 3.52 ms); used when p fills it
+            constexpr int MPT = sizeof(T) == 4 ? 128 : 64, MPTW = 2 * MPT;
             const int RT = (r + 15) / 16, KR = (r + 3) / 4 * 4;
-            const size_t lds = (size_t(KR) * (MPT + Mma<T>::pad) + size_t(16 * RT) * 68) * sizeof(T);
-            e = r <= 32 ? allow_lds(k_trans_mma<T, MPT, 32, kM2L>, lds) : allow_lds(k_trans_mma<T, MPT, 64, kM2L>, lds);
+            const bool wide = r <= 32 && p > MPT;
+            const int pt = wide ? MPTW : MPT;
+            const size_t lds = (size_t(KR) * (pt + Mma<T>::pad) + size_t(16 * RT) * 68) * sizeof(T);
+            e = wide ? allow_lds(k_trans_mma<T, MPTW, 32, kM2L>, lds)
+                     : r <= 32 ? allow_lds(k_trans_mma<T, MPT, 32, kM2L>, lds)
+                               : allow_lds(k_trans_mma<T, MPT, 64, kM2L>, lds);
             if (e != hipSuccess) return e;
             for (int lev = 2; lev <= D; ++lev) {
-                const dim3 grid(unsigned(g.boxes(lev)), (p + MPT - 1) / MPT);
+                const dim3 grid(unsigned(g.boxes(lev)), (p + pt - 1) / pt);
                 const T *Tl = Tm2l + int64_t(lev - 2) * g.noff() * r * r;
-                if (r <= 32)
+                if (wide)
+                    hipLaunchKernelGGL((k_trans_mma<T, MPTW, 32, kM2L>), grid, dim3(kBlock), lds, s, dim, r, p,
+                                       lev, Mlev(lev), Tl, Llev(lev));
+                else if (r <= 32)
                     hipLaunchKernelGGL((k_trans_mma<T, MPT, 32, kM2L>), grid, dim3(kBlock), lds, s, dim, r, p,
                                        lev, Mlev(lev), Tl, Llev(lev));
                 else

@@ -47,6 +47,7 @@ def test_cq_direct_is_exact(precision, tol):
     (2, 32, 16, 4, 0.3, 1.0),      # depth 2: M2L only at the leaves
     (2, 64, 32, 4, 0.1, 1.0),      # depth 3
     (2, 128, 48, 5, 0.05, 2.0),    # depth 4, Gaussian, padded p-space (48 -> 64)
+    (2, 64, 208, 5, 0.1, 2.0),     # p > 128 with r <= 32: the wide M2L column tile, ragged
     (3, 16, 16, 3, 0.2, 1.0),      # octree depth 2
     (3, 32, 32, 4, 0.2, 1.0),      # octree depth 3
 ])
