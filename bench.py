@@ -480,16 +480,20 @@ def serving(a):
             f.close()
     torch.cuda.synchronize()
 
-    # a budget of half the resident regions: streams are evicted and re-admitted
+    # a budget of half the resident regions, Poisson arrivals at 0.5x the
+    # full-memory saturation: streams that go idle are evicted when others
+    # need the memory, and re-admitted (from their checkpoints) when their
+    # next request arrives
     small = SV.Server(specs, max(resident // 2, max(sizes)), slots=a.slots)
     cursor3 = [0] * len(cfgs)
     t0 = time.perf_counter()
-    rq = requests(None, 2, cursor3)[:max(1, a.requests // 5)]
+    rq = requests(0.5 * sat, 5, cursor3)[:max(1, a.requests // 5)]
     small.run(rq)
     evict_run = SV.latency_summary(rq, time.perf_counter() - t0)
     evict_run.update({k: int(v) for k, v in small.stats.items()})
+    evict_run["offered_per_s"] = round(0.5 * sat, 1)
     small.close()
-    log(f"[serving] half-memory closed loop: {evict_run}")
+    log(f"[serving] half-memory, Poisson at 0.5 x saturation: {evict_run}")
     mean_flops = float(np.mean([2.0 * c["m"] * c["p"] ** 2 for c in cfgs]))
     print(json.dumps({
         "metric": "serving requests/s (assimilation steps over a mixed set of filters)",
