@@ -175,6 +175,47 @@ def test_steps_direct_f32_match_dense_kf():
     assert ev < 1e-6
 
 
+def _config1_case():
+    # the small workload as specified: 32 x 32 grid, exponential ell = 0.3,
+    # p = 16 crosswell rays, R = 1e-4 I, x_0 = 0, P_0 = Q, 10 steps, truth a
+    # random walk with covariance Q (oracle.truth, seed 0) observed through H
+    import synth
+    from oracle import kernels, truth
+    case = Case(2, 32, 16, ell=0.3, gamma=1.0, steps=10, seed=0)
+    Q = kernels.dense_q(synth.cell_centres(2, 32), **case.kparams())
+    _, case.ys = truth.random_walk_stream(Q, case.h_dense(), case.r_var, 10, seed=0)
+    return case
+
+
+def test_config1_as_written_direct_f64_matches_dense_kf():
+    case = _config1_case()
+    _, xs, vs, stats = case.gpu_run(precision="f64", direct=True)
+    xa, va = case.tier_a()
+    assert stats.last_status == 0 and stats.steps_applied == 10
+    assert max_step_rel(xs, xa) < 1e-10 and max_step_rel(vs, va) < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_config1_as_written_fmm_matches_oracle(precision):
+    # the H^2 filter at n_c = 4 against the cross-covariance oracle on the
+    # oracle's own FP64 bbFMM C_Q; the FP32 bound is the C_Q bound times the
+    # output sensitivity the oracle measures on these data (1.5x margin)
+    from helpers import output_sensitivity
+    case = _config1_case()
+    cq, xs, vs, stats = case.gpu_run(n_c=4, precision=precision)
+    ref = case.cq_bbfmm(4)
+    xb, vb = case.tier_b(ref)
+    ex, ev = max_step_rel(xs, xb), max_step_rel(vs, vb)
+    print(f"config 1 ({precision}): C_Q {rel(cq, ref):.3e}, x {ex:.3e}, var {ev:.3e}")
+    assert stats.last_status == 0 and stats.steps_applied == 10
+    assert rel(cq, ref) < CQ_TOL[precision]
+    if precision == "f64":
+        assert ex < 1e-9 and ev < 1e-10
+    else:
+        kx, kv = output_sensitivity(case, ref)
+        assert ex < 1.5 * kx * CQ_TOL["f32"] and ev < 1.5 * kv * CQ_TOL["f32"]
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32", "bf16x3"])
 @pytest.mark.parametrize("n,p,n_c,ell,gamma", [(32, 16, 4, 0.3, 1.0), (64, 32, 5, 0.1, 2.0),
                                                (59, 32, 4, 0.2, 1.0)])
