@@ -1070,10 +1070,11 @@ __global__ void k_split_t(int64_t nslots, int r, int rt, int kr, const float *T,
 
 // M2L on BF16 MFMA: as k_trans_mma, with the translation tile (A, [target
 // node][source node]) and M_A (B, [column][source node]) staged as hi / lo.
-// Software-pipelined over the interaction list: the next source's tiles are
-// loaded into registers while the MFMAs of the current one run, then moved
-// to LDS between two barriers.  KR (nodes padded to 32) is a template
-// parameter so that the per-thread staging counts are compile-time.
+// Software-pipelined two sources deep over the interaction list: the tiles
+// of the next two sources sit in two register sets while the MFMAs of the
+// current one run, and each set is moved to LDS between two barriers when
+// its turn comes.  KR (nodes padded to 32) is a template parameter so that
+// the per-thread staging counts are compile-time.
 template <bool SPLIT, int PT, int KR>
 __global__ void __launch_bounds__(kBlock)
 k_m2l_bf16(int dim, int r, int p, int lev, const __bf16 *Mh, const __bf16 *Ml,
@@ -1110,64 +1111,61 @@ k_m2l_bf16(int dim, int r, int p, int lev, const __bf16 *Mh, const __bf16 *Ml,
         }
         return oi;
     };
-    bf8 th[TPT], tl[TPT], mh[MPT], ml[MPT];
     const bf8 zero8 = {};
-    // load the tiles of interaction-list offset OI into registers
-#define HIKF_M2L_FETCH(OI)                                                                    \
-    do {                                                                                      \
-        const int fo = (OI);                                                                  \
-        const int fa[3] = {b[0] + fo % 7 - 3, b[1] + (fo / 7) % 7 - 3,                        \
-                           dim == 3 ? b[2] + fo / 49 - 3 : 0};                                \
-        const int64_t A = box_index(fa, nb, dim);                                             \
-        const int64_t tbase = int64_t(fo) * rt16 * KR;                                        \
-        _Pragma("unroll") for (int u = 0; u < TPT; ++u) {                                     \
-            const int idx = tid + kBlock * u, i = idx / KCH, ch = idx % KCH;                  \
-            if (i < rt16) {                                                                   \
-                th[u] = *reinterpret_cast<const bf8 *>(Th + tbase + int64_t(i) * KR + 8 * ch); \
-                tl[u] = *reinterpret_cast<const bf8 *>(Tl + tbase + int64_t(i) * KR + 8 * ch); \
-            }                                                                                 \
-        }                                                                                     \
-        _Pragma("unroll") for (int u = 0; u < MPT; ++u) {                                     \
-            const int idx = tid + kBlock * u, c = idx / KCH, ch = idx % KCH;                  \
-            if (c < ncols) {                                                                  \
-                const int64_t g = (A * p + c0 + c) * KR + 8 * ch;                             \
-                mh[u] = *reinterpret_cast<const bf8 *>(Mh + g);                               \
-                ml[u] = *reinterpret_cast<const bf8 *>(Ml + g);                               \
-            } else {                                                                          \
-                mh[u] = ml[u] = zero8;                                                        \
-            }                                                                                 \
-        }                                                                                     \
+    // the tiles of interaction-list offset FO into register set S
+#define HIKF_M2L_FETCH(FO, S)                                                                     \
+    do {                                                                                          \
+        const int fo = (FO);                                                                      \
+        const int fa[3] = {b[0] + fo % 7 - 3, b[1] + (fo / 7) % 7 - 3,                            \
+                           dim == 3 ? b[2] + fo / 49 - 3 : 0};                                    \
+        const int64_t A = box_index(fa, nb, dim);                                                 \
+        const int64_t tbase = int64_t(fo) * rt16 * KR;                                            \
+        _Pragma("unroll") for (int u = 0; u < TPT; ++u) {                                         \
+            const int idx = tid + kBlock * u, i = idx / KCH, ch = idx % KCH;                      \
+            if (i < rt16) {                                                                       \
+                th##S[u] = *reinterpret_cast<const bf8 *>(Th + tbase + int64_t(i) * KR + 8 * ch); \
+                tl##S[u] = *reinterpret_cast<const bf8 *>(Tl + tbase + int64_t(i) * KR + 8 * ch); \
+            }                                                                                     \
+        }                                                                                         \
+        _Pragma("unroll") for (int u = 0; u < MPT; ++u) {                                         \
+            const int idx = tid + kBlock * u, c = idx / KCH, ch = idx % KCH;                      \
+            if (c < ncols) {                                                                      \
+                const int64_t g = (A * p + c0 + c) * KR + 8 * ch;                                 \
+                mh##S[u] = *reinterpret_cast<const bf8 *>(Mh + g);                                \
+                ml##S[u] = *reinterpret_cast<const bf8 *>(Ml + g);                                \
+            } else {                                                                              \
+                mh##S[u] = ml##S[u] = zero8;                                                      \
+            }                                                                                     \
+        }                                                                                         \
+    } while (0)
+    // register set S -> LDS, between two barriers
+#define HIKF_M2L_STAGE(S)                                                                         \
+    do {                                                                                          \
+        __syncthreads();                           /* LDS free (previous MFMAs done) */           \
+        _Pragma("unroll") for (int u = 0; u < TPT; ++u) {                                         \
+            const int idx = tid + kBlock * u, i = idx / KCH, ch = idx % KCH;                      \
+            if (i < rt16) {                                                                       \
+                *reinterpret_cast<bf8 *>(sTh + i * KP + 8 * ch) = th##S[u];                       \
+                *reinterpret_cast<bf8 *>(sTl + i * KP + 8 * ch) = tl##S[u];                       \
+            }                                                                                     \
+        }                                                                                         \
+        _Pragma("unroll") for (int u = 0; u < MPT; ++u) {                                         \
+            const int idx = tid + kBlock * u, c = idx / KCH, ch = idx % KCH;                      \
+            *reinterpret_cast<bf8 *>(sMh + c * KP + 8 * ch) = mh##S[u];                           \
+            *reinterpret_cast<bf8 *>(sMl + c * KP + 8 * ch) = ml##S[u];                           \
+        }                                                                                         \
+        __syncthreads();                                                                          \
     } while (0)
     f4v acc[MAXT];
 #pragma unroll
     for (int u = 0; u < MAXT; ++u) acc[u] = f4v{0, 0, 0, 0};
-    int oi = next_il(-1);
-    if (oi < noff) HIKF_M2L_FETCH(oi);
-    while (oi < noff) {
-        __syncthreads();                               // LDS free (previous MFMAs done)
-#pragma unroll
-        for (int u = 0; u < TPT; ++u) {
-            const int idx = tid + kBlock * u, i = idx / KCH, ch = idx % KCH;
-            if (i < rt16) {
-                *reinterpret_cast<bf8 *>(sTh + i * KP + 8 * ch) = th[u];
-                *reinterpret_cast<bf8 *>(sTl + i * KP + 8 * ch) = tl[u];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < MPT; ++u) {
-            const int idx = tid + kBlock * u, c = idx / KCH, ch = idx % KCH;
-            *reinterpret_cast<bf8 *>(sMh + c * KP + 8 * ch) = mh[u];
-            *reinterpret_cast<bf8 *>(sMl + c * KP + 8 * ch) = ml[u];
-        }
-        __syncthreads();
-        const int on = next_il(oi);
-        if (on < noff) HIKF_M2L_FETCH(on);             // in flight during the MFMAs
-        // the wave's tiles are every row tile rt < RT times the column tiles
-        // wave + 4 c (c < CW), u = rt CW + c: per k step the hi / lo A values
-        // of a row tile and B values of a column tile feed independent MFMAs
-        // (128^3, r = 64: 146 -> 129 ms over the levels; in the FP32 / FP64
-        // kernel above the same order measured slower, 3.52 -> 3.78 ms at
-        // 1024^2, r = 25, so that one keeps a tile's k loop innermost)
+    // the wave's tiles are every row tile rt < RT times the column tiles
+    // wave + 4 c (c < CW), u = rt CW + c: per k step the hi / lo A values
+    // of a row tile and B values of a column tile feed independent MFMAs
+    // (128^3, r = 64: 146 -> 129 ms over the levels; in the FP32 / FP64
+    // kernel above the same order measured slower, 3.52 -> 3.78 ms at
+    // 1024^2, r = 25, so that one keeps a tile's k loop innermost)
+    auto compute = [&]() __attribute__((always_inline)) {
 #pragma unroll
         for (int k0 = 0; k0 < KR; k0 += 32) {
             bf8 bh[CW], bl[CW];
@@ -1189,9 +1187,34 @@ k_m2l_bf16(int dim, int r, int p, int lev, const __bf16 *Mh, const __bf16 *Ml,
                 }
             }
         }
-        oi = on;
+    };
+    // Software pipeline two sources deep: while the MFMAs of list entry o0
+    // run, the tiles of o1 are already in registers (set 1 or 0) and those
+    // of o2 are being loaded into the set o0 came from.  The two register
+    // sets alternate (phase 0 / phase 1) so that each has a fixed name.
+    bf8 th0[TPT], tl0[TPT], mh0[MPT], ml0[MPT];
+    bf8 th1[TPT], tl1[TPT], mh1[MPT], ml1[MPT];
+    int o0 = next_il(-1);
+    int o1 = o0 < noff ? next_il(o0) : noff;
+    if (o0 < noff) HIKF_M2L_FETCH(o0, 0);
+    if (o1 < noff) HIKF_M2L_FETCH(o1, 1);
+    while (o0 < noff) {
+        HIKF_M2L_STAGE(0);
+        int o2 = o1 < noff ? next_il(o1) : noff;
+        if (o2 < noff) HIKF_M2L_FETCH(o2, 0);
+        compute();
+        o0 = o1;
+        o1 = o2;
+        if (o0 >= noff) break;
+        HIKF_M2L_STAGE(1);
+        o2 = o1 < noff ? next_il(o1) : noff;
+        if (o2 < noff) HIKF_M2L_FETCH(o2, 1);
+        compute();
+        o0 = o1;
+        o1 = o2;
     }
 #undef HIKF_M2L_FETCH
+#undef HIKF_M2L_STAGE
 #pragma unroll
     for (int u = 0; u < MAXT; ++u) {
         const int tile = wave + 4 * u;
