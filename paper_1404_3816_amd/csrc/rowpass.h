@@ -63,7 +63,8 @@ typedef double dv2 __attribute__((ext_vector_type(2)));
 // epilogue of the current one has issued its stores (the stores then drain
 // while the next tile computes).
 template <typename TQ, int NT, int CS, int RG_, int PART, bool PERSIST>
-__device__ __forceinline__ void rowpass_part(double *sB, double *red, int64_t m, int64_t ntiles,
+__device__ __forceinline__ void rowpass_part(double *sB, double *red, double *sNR, double *sVX,
+                                             int64_t m, int64_t ntiles,
                                              double *C, const TQ *CQ, const double *Sinv,
                                              const double *nu, const double *rdiag, double *xhat,
                                              double *var, double kdiag,
@@ -108,6 +109,12 @@ __device__ __forceinline__ void rowpass_part(double *sB, double *red, int64_t m,
             nq[h] = *reinterpret_cast<const qv2 *>(CQ + rb + 8 * h);
         }
     }
+    // nu and R for the epilogue, once per workgroup (the epilogue then
+    // reads LDS instead of waiting on L2 at the end of every tile)
+    for (int i = tid; i < P; i += NTH) {
+        sNR[i] = nu[i];
+        sNR[P + i] = rdiag[i];
+    }
     __syncthreads();
     // LDS buffer of k block kb: kb % 2 (a tile has an even number of k
     // blocks in the persistent form, so every tile starts in buffer 0)
@@ -126,6 +133,15 @@ __device__ __forceinline__ void rowpass_part(double *sB, double *red, int64_t m,
         }
 #pragma unroll
         for (int t = 0; t < NH; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+        // this tile's variance and state entries, read now and parked in LDS
+        // at the end of the first k block, so that the epilogue does not
+        // wait for them
+        double vpre = 0.0, xpre = 0.0;
+        const int64_t vrow = tile * (16 * RG) + tid;
+        if (tid < 16 * RG && vrow < m) {
+            vpre = var[vrow];
+            xpre = xhat[vrow];
+        }
         // the S^{-1} slabs are the same for every tile: the empty asm keeps
         // their loads inside this tile's k loop instead of hoisted out of
         // the tile loop
@@ -208,16 +224,21 @@ __device__ __forceinline__ void rowpass_part(double *sB, double *red, int64_t m,
                         *reinterpret_cast<dv2 *>(nbuf + rr * LDB + c) = bpre[u - U0];
                 }
             }
+            if (kb == 0 && tid < 16 * RG) {
+                sVX[2 * tid] = vpre;
+                sVX[2 * tid + 1] = xpre;
+            }
             __syncthreads();
         }
 
         // epilogue: lane holds K[row][16 t + col(q, r)] = acc[t - T0][r] and
-        // C_prior[row][16 t + col(q, r)] = keep[t - T0][r].  The nu and R
-        // pointers pass through an empty asm statement so that their loads
-        // stay here and are not hoisted out of the tile loop (which would
-        // hold them in registers for the whole kernel).
-        const double *nu_t = nu, *rdiag_t = rdiag;
-        if (PERSIST) asm volatile("" : "+s"(nu_t), "+s"(rdiag_t));
+        // C_prior[row][16 t + col(q, r)] = keep[t - T0][r].  nu and R come
+        // from LDS; their offset passes through an empty asm statement so
+        // that the reads stay here and are not hoisted out of the tile loop
+        // (which would hold them in registers for the whole kernel).
+        int zoff = 0;
+        if (PERSIST) asm volatile("" : "+s"(zoff));
+        const double *nu_t = sNR + zoff, *rdiag_t = sNR + P + zoff;
         double dv = 0.0, dx = 0.0;
 #pragma unroll
         for (int t = 0; t < NH; ++t)
@@ -278,14 +299,14 @@ __device__ __forceinline__ void rowpass_part(double *sB, double *red, int64_t m,
                     sv += red[(c * 16 * RG + tid) * 2];
                     sx += red[(c * 16 * RG + tid) * 2 + 1];
                 }
-                const double v = var[r] + kdiag - sv;
+                const double v = sVX[2 * tid] + kdiag - sv;
                 var[r] = v;
-                xhat[r] += sx;
+                xhat[r] = sVX[2 * tid + 1] + sx;
                 if (v < 0.0) atomicAdd(negvar, 1ull);
             }
         }
-        // `red` is written again only after the next tile's k loop, whose
-        // barriers order it after these reads
+        // `red` and `sVX` are written again only after the next tile's
+        // first k block, whose barrier orders it after these reads
         if (!more) break;
         tile = next;
     }
@@ -299,11 +320,13 @@ k_rowpass(int64_t m, int64_t ntiles, double *C, const TQ *CQ, const double *Sinv
     using RS = RowSplit<NT, CS, RG>;
     __shared__ __align__(16) double sB[2 * RS::SLAB];
     __shared__ double red[CS * RG * 16 * 2];
+    __shared__ __align__(16) double sNR[2 * RS::P];
+    __shared__ double sVX[2 * 16 * RG];
     if (status[kStStep] != HIKF_OK) return;
     if (int64_t(blockIdx.x) >= ntiles) return;
     const int part = (threadIdx.x >> 6) / RG;
 #define HIKF_RP_PART(K)                                                                        \
-    rowpass_part<TQ, NT, CS, RG, (K), PERSIST>(sB, red, m, ntiles, C, CQ, Sinv, nu, rdiag, xhat, \
+    rowpass_part<TQ, NT, CS, RG, (K), PERSIST>(sB, red, sNR, sVX, m, ntiles, C, CQ, Sinv, nu, rdiag, xhat, \
                                              var, kdiag, negvar)
     if (part == 0)
         HIKF_RP_PART(0);
