@@ -854,6 +854,117 @@ k_trans_mma(int dim, int r, int p, int lev, const T *M, const T *Tlev, T *L) {
     }
 }
 
+// M2L in FP32 on the 32 x 32 x 2 MFMA (16 < r <= 64; RMAX = 32 or 64 rows):
+// as k_trans_mma, with 32 x 32 output tiles.  Per 2-deep k step a lane
+// supplies one A value (translation row l % 32, k = l / 32) and one B value
+// (M row k, column l % 32) for 32 x 32 x 2 products, half the LDS operand
+// reads per flop of the 16 x 16 x 4 shape, and the k padding drops from a
+// multiple of 4 to a multiple of 2 (r = 25: 26 instead of 28).  A wave's
+// tiles share their row tile when RMAX = 32, so one A read feeds all of
+// them.  Lane l holds D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32] in v.
+template <int PT, int RMAX>
+__global__ void __launch_bounds__(kBlock)
+k_m2l_f32w(int dim, int r, int p, int lev, const float *M, const float *Tlev, float *L) {
+    typedef float v16 __attribute__((ext_vector_type(16)));
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    constexpr int NCT = PT / 32;                       // 32-column tiles
+    constexpr int RT = RMAX / 32;                      // 32-row tiles
+    constexpr int NTILE = RT * NCT;
+    constexpr int TW = NTILE / 4;                      // tiles per wave
+    static_assert(NTILE % 4 == 0 && TW >= 1, "tiles must split over the 4 waves");
+    constexpr int WP = PT + 4;                         // B row pitch (floats)
+    constexpr int TP = RMAX + 1;                       // A row pitch: odd, 32 rows on 32 banks
+    constexpr int MPT = (RMAX * PT / 4 + kBlock - 1) / kBlock;   // M float4 loads per thread
+    constexpr int TPT = (32 * RT * RMAX + kBlock - 1) / kBlock;  // T values per thread
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int KR2 = (r + 1) / 2 * 2;
+    float *sM = reinterpret_cast<float *>(smem_raw);   // [KR2][WP]
+    float *sT = sM + KR2 * WP;                         // [32 RT][TP]
+    const int64_t B = blockIdx.x;
+    const int c0 = blockIdx.y * PT;
+    const int ncols = min(PT, p - c0);
+    const int nb = 1 << lev;
+    const int noff = dim == 2 ? 49 : 343;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int l32 = lane & 31, h = lane >> 5;
+    const int nm = KR2 * (PT / 4), nt = 32 * RT * KR2;
+    int b[3];
+    box_coords(B, nb, dim, b);
+    auto next_il = [&](int oi) {
+        for (++oi; oi < noff; ++oi) {
+            int o[3] = {oi % 7 - 3, (oi / 7) % 7 - 3, oi / 49 - 3};
+            if (il_member(b, o, nb, dim)) break;
+        }
+        return oi;
+    };
+    f4 mreg[MPT];
+    float treg[TPT];
+    // the multipoles and translation tile of list entry fo into registers
+    auto fetch = [&](int fo) __attribute__((always_inline)) {
+        const int fa[3] = {b[0] + fo % 7 - 3, b[1] + (fo / 7) % 7 - 3, dim == 3 ? b[2] + fo / 49 - 3 : 0};
+        const int64_t A = box_index(fa, nb, dim);
+        const float *Toff = Tlev + int64_t(fo) * r * r;
+#pragma unroll
+        for (int u = 0; u < MPT; ++u) {
+            const int idx = tid + kBlock * u, k = idx / (PT / 4), ch = idx % (PT / 4);
+            f4 v = f4{0.f, 0.f, 0.f, 0.f};
+            if (idx < nm && k < r && 4 * ch < ncols)
+                v = *reinterpret_cast<const f4 *>(M + (A * r + k) * p + c0 + 4 * ch);
+            mreg[u] = v;
+        }
+#pragma unroll
+        for (int u = 0; u < TPT; ++u) {
+            const int idx = tid + kBlock * u, i = idx / KR2, k = idx % KR2;
+            treg[u] = (idx < nt && i < r && k < r) ? Toff[i * r + k] : 0.f;
+        }
+    };
+    v16 acc[TW];
+#pragma unroll
+    for (int u = 0; u < TW; ++u)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[u][v] = 0.f;
+    int oi = next_il(-1);
+    if (oi < noff) fetch(oi);
+    while (oi < noff) {
+        __syncthreads();                               // LDS free (previous MFMAs done)
+#pragma unroll
+        for (int u = 0; u < MPT; ++u) {
+            const int idx = tid + kBlock * u, k = idx / (PT / 4), ch = idx % (PT / 4);
+            if (idx < nm) *reinterpret_cast<f4 *>(sM + k * WP + 4 * ch) = mreg[u];
+        }
+#pragma unroll
+        for (int u = 0; u < TPT; ++u) {
+            const int idx = tid + kBlock * u, i = idx / KR2, k = idx % KR2;
+            if (idx < nt) sT[i * TP + k] = treg[u];
+        }
+        __syncthreads();
+        const int on = next_il(oi);
+        if (on < noff) fetch(on);                      // in flight during the MFMAs
+        for (int k0 = 0; k0 < KR2; k0 += 2) {
+            float a[RT];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) a[rt] = sT[(32 * rt + l32) * TP + k0 + h];
+#pragma unroll
+            for (int u = 0; u < TW; ++u) {
+                const int tile = wave + 4 * u, rt = tile / NCT, ct = tile % NCT;
+                const float bv = sM[(k0 + h) * WP + 32 * ct + l32];
+                acc[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rt], bv, acc[u], 0, 0, 0);
+            }
+        }
+        oi = on;
+    }
+#pragma unroll
+    for (int u = 0; u < TW; ++u) {
+        const int tile = wave + 4 * u, rt = tile / NCT, ct = tile % NCT;
+        const int c = 32 * ct + l32;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int k = 32 * rt + 8 * (v >> 2) + 4 * h + (v & 3);
+            if (k < r && c < ncols) L[(B * r + k) * p + c0 + c] = acc[u][v];
+        }
+    }
+}
+
 // ---------------------------------------------------------------- low-rank M2L
 // The compressed M2L of the black-box FMM: a level's translations T_o share
 // one basis U (r x k), the left singular vectors of [T_o1 T_o2 ...] (all
@@ -1770,7 +1881,33 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
                 }
             }
         }
-        if (!bf16 && !lowrank) {
+        bool wdone = false;
+        if constexpr (sizeof(T) == 4) {
+            if (!bf16 && !lowrank && r > 16) {
+                // FP32 with r > 16 on the 32 x 32 x 2 MFMA; 256-column tiles
+                // when p fills them and r <= 32 (at r > 32 they would hold
+                // the registers of a single wave per SIMD)
+                const int rmax = r <= 32 ? 32 : 64;
+                const int pt = p > 128 && rmax == 32 ? 256 : 128, KR2 = (r + 1) / 2 * 2;
+                const size_t lds = (size_t(KR2) * (pt + 4) + size_t(rmax) * (rmax + 1)) * sizeof(float);
+#define HIKF_M2L_F32W(PTV, RMV)                                                                   \
+    do {                                                                                          \
+        e = allow_lds(k_m2l_f32w<PTV, RMV>, lds);                                                 \
+        if (e != hipSuccess) return e;                                                            \
+        for (int lev = 2; lev <= D; ++lev) {                                                      \
+            const dim3 grid(unsigned(g.boxes(lev)), (p + PTV - 1) / PTV);                         \
+            hipLaunchKernelGGL((k_m2l_f32w<PTV, RMV>), grid, dim3(kBlock), lds, s, dim, r, p, lev, \
+                               Mlev(lev), Tm2l + int64_t(lev - 2) * g.noff() * r * r, Llev(lev)); \
+        }                                                                                         \
+    } while (0)
+                if (pt == 256) HIKF_M2L_F32W(256, 32);
+                else if (rmax == 32) HIKF_M2L_F32W(128, 32);
+                else HIKF_M2L_F32W(128, 64);
+#undef HIKF_M2L_F32W
+                wdone = true;
+            }
+        }
+        if (!bf16 && !lowrank && !wdone) {
             // column tile: with r <= 32 the output is 2 node tiles high, so a
             // tile twice as wide (256 FP32 / 128 FP64 columns) still fits 8
             // MFMA tiles per wave and doubles the products per staged source
