@@ -41,9 +41,10 @@ __device__ __forceinline__ double s_elem(const double *G, const double *rdiag, i
 
 // Load block (bi, bj) of the working matrix into LDS: from G (first use,
 // symmetrised, plus R) or from the PP x PP buffer A.
+// (threads t0, t0 + nthr, ... of the workgroup take part)
 __device__ void blk_load(double *s, const double *A, int PP, const double *G, const double *rdiag,
-                         int p, bool from_g, int bi, int bj) {
-    for (int idx = threadIdx.x; idx < BS * BS; idx += NT) {
+                         int p, bool from_g, int bi, int bj, int t0 = threadIdx.x, int nthr = NT) {
+    for (int idx = t0; idx < BS * BS; idx += nthr) {
         const int r = idx / BS, c = idx % BS, i = bi * BS + r, j = bj * BS + c;
         s[r * BP + c] = from_g ? s_elem(G, rdiag, p, i, j) : A[int64_t(i) * PP + j];
     }
@@ -177,10 +178,9 @@ __global__ void __launch_bounds__(NT) k_ps_sweep(PsArgs a, int k) {
     const double *src = (k & 1) ? a.X : a.A;
     double *dst = (k & 1) ? a.A : a.X;
     const bool first = k == 0;
+    // the pivot block first; wave 0 then sweeps it while waves 1-3 load the
+    // workgroup's other blocks
     blk_load(sP, src, a.PP, a.G, a.rdiag, a.p, first, k, k);
-    if (bi != k) blk_load(sI, src, a.PP, a.G, a.rdiag, a.p, first, bi, k);
-    if (bj != k) blk_load(sJ, src, a.PP, a.G, a.rdiag, a.p, first, k, bj);
-    if (bi != k && bj != k) blk_load(sT, src, a.PP, a.G, a.rdiag, a.p, first, bi, bj);
     __syncthreads();
     if (t < 64) {
         double pmin;
@@ -195,6 +195,11 @@ __global__ void __launch_bounds__(NT) k_ps_sweep(PsArgs a, int k) {
                 }
             }
         }
+    } else {
+        const int t0 = t - 64, nthr = NT - 64;
+        if (bi != k) blk_load(sI, src, a.PP, a.G, a.rdiag, a.p, first, bi, k, t0, nthr);
+        if (bj != k) blk_load(sJ, src, a.PP, a.G, a.rdiag, a.p, first, k, bj, t0, nthr);
+        if (bi != k && bj != k) blk_load(sT, src, a.PP, a.G, a.rdiag, a.p, first, bi, bj, t0, nthr);
     }
     __syncthreads();
     if (!okflag) return;
