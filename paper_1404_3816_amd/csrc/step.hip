@@ -98,14 +98,15 @@ __global__ void k_widen(int64_t n, const TQ *src, double *dst) {
 }
 
 // ---------------------------------------------------------------- 1. gather
-// One workgroup per (ray a, chunk ch of its nonzeros); thread t < p/2 sums
-// columns 2t and 2t + 1 of sum_e H_ae X[col_e][.] with 16-byte loads, where
-// X is C (WITH_C; the step adds the fixed H C_Q afterwards, since
-// H C_prior = H C + H C_Q) or C_Q (H C_Q, once at init),
+// One workgroup per (ray a, chunk ch of its nonzeros), taken 64 nonzeros at
+// a time: their column indices and values go to LDS first (one load per
+// thread, all in flight together), then thread t < p/2 sums columns 2t and
+// 2t + 1 of sum_e H_ae X[col_e][.] with 16-byte loads, sixteen rows in
+// flight per thread, where X is C (WITH_C; the step adds the fixed H C_Q
+// afterwards, since H C_prior = H C + H C_Q) or C_Q (H C_Q, once at init),
 // and the 64 threads after them split sum_e H_ae x_hat[col_e] (nonzero j
-// mod 64 each, then summed in a fixed order).  Eight nonzeros are loaded
-// before any is accumulated, so the row loads of a chunk are in flight
-// together.
+// mod 64 each, then summed in a fixed order).  A column index out of range
+// contributes nothing.
 template <typename TQ, bool WITH_C>
 __global__ void __launch_bounds__(512)
 k_gather(int p, int cpr, int64_t m, int64_t nnz, const int64_t *rowptr, const int32_t *col,
@@ -113,7 +114,11 @@ k_gather(int p, int cpr, int64_t m, int64_t nnz, const int64_t *rowptr, const in
          double *partial, const int *status) {
     typedef double dv2 __attribute__((ext_vector_type(2)));
     typedef TQ qv2 __attribute__((ext_vector_type(2)));
-    constexpr int U = 8;
+    constexpr int U = 16;
+    constexpr int kSub = 64;                           // nonzeros staged at a time
+    __shared__ int64_t sc[kSub];
+    __shared__ double sw[kSub];
+    __shared__ double hsum[64];
     if (status[kStInit] != 0) return;
     const int a = blockIdx.x, ch = blockIdx.y;
     int64_t r0 = rowptr[a], r1 = rowptr[a + 1];
@@ -124,56 +129,59 @@ k_gather(int p, int cpr, int64_t m, int64_t nnz, const int64_t *rowptr, const in
     double *out = partial + (int64_t(a) * cpr + ch) * (p + 1);
     const int half = p / 2;
     const int t = threadIdx.x;
-    __shared__ double hsum[64];
-    if (t >= half && t < half + 64) {
-        double acc = 0.0;
-        for (int64_t e = e0 + (t - half); e < e1; e += 64) {
-            const int64_t c = col[e];
-            if (c >= 0 && c < m) acc += val[e] * xhat[c];
+    dv2 acc = dv2{0.0, 0.0};
+    double hacc = 0.0;
+    for (int64_t b = e0; b < e1; b += kSub) {
+        const int n = int(e1 - b < kSub ? e1 - b : kSub);
+        if (b > e0) __syncthreads();                   // previous entries consumed
+        if (t < kSub) {
+            int64_t c = 0;
+            double w = 0.0;
+            if (t < n) {
+                c = col[b + t];
+                w = val[b + t];
+                if (c < 0 || c >= m) {
+                    c = 0;
+                    w = 0.0;
+                }
+            }
+            sc[t] = c;
+            sw[t] = w;
         }
-        hsum[t - half] = acc;
+        __syncthreads();
+        if (t >= half && t < half + 64) {
+            const int j = t - half;
+            if (j < n) hacc += sw[j] * xhat[sc[j]];
+        }
+        if (t < half) {
+            for (int e = 0; e < n; e += U) {
+                dv2 x[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t o = (e + u < n ? sc[e + u] : 0) * p + 2 * t;
+                    if constexpr (WITH_C) {
+                        x[u] = *reinterpret_cast<const dv2 *>(C + o);
+                    } else {
+                        const qv2 qv = *reinterpret_cast<const qv2 *>(CQ + o);
+                        x[u] = dv2{(double)qv[0], (double)qv[1]};
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (e + u < n) acc += sw[e + u] * x[u];
+            }
+        }
+    }
+    if (t >= half && t < half + 64) hsum[t - half] = hacc;
+    if (t < half) {
+        out[2 * t] = acc[0];
+        out[2 * t + 1] = acc[1];
     }
     __syncthreads();
     if (t == half) {
-        double acc = 0.0;
-        for (int j = 0; j < 64; ++j) acc += hsum[j];
-        out[p] = acc;
-    }
-    if (t < half) {
-        dv2 acc = dv2{0.0, 0.0};
-        int64_t e = e0;
-        for (; e + U <= e1; e += U) {
-            dv2 x[U];
-            double w[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int64_t c = col[e + u];
-                const bool ok = c >= 0 && c < m;
-                const int64_t o = (ok ? c : 0) * p + 2 * t;
-                if constexpr (WITH_C) {
-                    x[u] = *reinterpret_cast<const dv2 *>(C + o);
-                } else {
-                    const qv2 qv = *reinterpret_cast<const qv2 *>(CQ + o);
-                    x[u] = dv2{(double)qv[0], (double)qv[1]};
-                }
-                w[u] = ok ? val[e + u] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) acc += w[u] * x[u];
-        }
-        for (; e < e1; ++e) {
-            const int64_t c = col[e];
-            if (c < 0 || c >= m) continue;
-            const int64_t o = c * p + 2 * t;
-            if constexpr (WITH_C) {
-                acc += val[e] * *reinterpret_cast<const dv2 *>(C + o);
-            } else {
-                const qv2 qv = *reinterpret_cast<const qv2 *>(CQ + o);
-                acc += val[e] * dv2{(double)qv[0], (double)qv[1]};
-            }
-        }
-        out[2 * t] = acc[0];
-        out[2 * t + 1] = acc[1];
+        double s2 = 0.0;
+        for (int j = 0; j < 64; ++j) s2 += hsum[j];
+        out[p] = s2;
     }
 }
 

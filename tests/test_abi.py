@@ -98,7 +98,7 @@ def test_plan_reports_unsupported_shapes():
     assert _plan(_problem(dim=3, n=1300))[0] == H.HIKF_E_UNSUPPORTED   # 2048^3-cell tree
     assert _plan(_problem(p=20))[0] == H.HIKF_E_UNSUPPORTED      # not a multiple of 16
     assert _plan(_problem(p=528))[0] == H.HIKF_E_UNSUPPORTED     # above 512
-    assert _plan(_problem(dim=3, n=16), n_c=6)[0] == H.HIKF_E_UNSUPPORTED  # r > 128
+    assert _plan(_problem(dim=3, n=16), n_c=6)[0] == H.HIKF_E_UNSUPPORTED  # r = 216 > 64
 
 
 def test_plan_direct_mode_has_no_far_field():
