@@ -572,6 +572,17 @@ k_l2p_p2p_mma(int dim, int n, int npad, int ls, int depth, int r, int rpad, int 
     }
 }
 
+// value of lane src (uniform) of x, through the scalar unit
+__device__ __forceinline__ float lane_value(float x, int src) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), src));
+}
+__device__ __forceinline__ double lane_value(double x, int src) {
+    int2 v = __builtin_bit_cast(int2, x);
+    v.x = __builtin_amdgcn_readlane(v.x, src);
+    v.y = __builtin_amdgcn_readlane(v.y, src);
+    return __builtin_bit_cast(double, v);
+}
+
 // ---------------------------------------------------------------- L2P + P2P (sparse W)
 // One workgroup per (target leaf B, PT-column tile).  Near field: for every
 // bucket entry (ray a, point j, value v) of the NSL = 3^dim neighbour leaves
@@ -581,8 +592,11 @@ k_l2p_p2p_mma(int dim, int n, int npad, int ls, int depth, int r, int rpad, int 
 // first 64 entries of every neighbour bucket (one per lane) are all loaded up
 // front, so a workgroup waits for memory about twice; a wave then keeps its
 // own entries by a ballot and walks them with the kernel value generated from
-// the integer cell offset.  The far field adds S_leaf^T L_B on MFMA as in the
-// dense kernel, and the two meet in the epilogue.
+// the integer cell offset.  A bucket is ray-major, so a ray's entries (its
+// cells in the leaf) come in a run: the run is summed in a register and
+// added to the LDS tile once, when the column changes.  The far field adds
+// S_leaf^T L_B on MFMA as in the dense kernel, and the two meet in the
+// epilogue.
 template <typename T, int PT, int NSL>
 __global__ void __launch_bounds__(kBlock)
 k_l2p_p2p_sparse(int n, int ls, int depth, int r, int rpad, int p, int far, KernelParams kp,
@@ -591,14 +605,22 @@ k_l2p_p2p_sparse(int n, int ls, int depth, int r, int rpad, int p, int far, Kern
     typedef typename Mma<T>::v4 v4;
     constexpr int dim = NSL == 9 ? 2 : 3;
     constexpr int NTI = PT / 16;
-    constexpr int NFP = kLeafPts + 1;                  // pitch of the near-field tile
+    constexpr int NFP = kLeafPts;                      // pitch of the near-field tile
+    constexpr int KT = kLeafPts + 16;                  // pitch of S_leaf^T ([k][point])
     constexpr int WP = PT + Mma<T>::pad;
     constexpr int FU = (kLeafPts * kMaxR + kBlock - 1) / kBlock;   // far operand loads per thread
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int KP = rpad + 4;
-    T *nf = reinterpret_cast<T *>(smem_raw);           // [PT][NFP]
-    T *sK = nf + PT * NFP;                             // [64][KP]   S_leaf^T
-    T *sW = sK + kLeafPts * KP;                        // [rpad][WP] L_B tile
+    T *nf = reinterpret_cast<T *>(smem_raw);           // [PT][NFP], swizzled (nfi)
+    T *sK = nf + PT * NFP;                             // [rpad][KT] S_leaf^T
+    T *sW = sK + rpad * KT;                            // [rpad][WP] L_B tile
+    // element (column c, target i) of the near-field tile: i XOR a function
+    // of the low four bits of c, so that both the per-column writes (64
+    // targets) and the epilogue reads (16 columns x 4 target rows in the
+    // MFMA output layout) fall on distinct LDS banks
+    auto nfi = [](int c, int i) {
+        const int l = c & 15;
+        return c * NFP + (i ^ ((l & 3) | ((l & 4) << 2) | ((l & 8) ? 0x28 : 0)));
+    };
     const int64_t B = blockIdx.x;
     const int c0 = blockIdx.y * PT;
     const int ncols = min(PT, p - c0);
@@ -651,13 +673,20 @@ k_l2p_p2p_sparse(int n, int ls, int depth, int r, int rpad, int p, int far, Kern
 #pragma unroll
         for (int u = 0; u < FU; ++u) {
             const int idx = tid + kBlock * u;
-            if (idx < kLeafPts * rpad) sK[(idx / rpad) * KP + idx % rpad] = kreg[u];
+            if (idx < kLeafPts * rpad) sK[(idx % rpad) * KT + idx / rpad] = kreg[u];
             if (idx < rpad * PT) sW[(idx / PT) * WP + idx % PT] = lreg[u];
         }
     }
     int li[3];
     leaf_local(lane, dim, li);                         // this lane's target point
     __syncthreads();                                   // tile cleared, far operands staged
+    // the current run: its tile column (uniform; -1 before the first) and
+    // this lane's sum over it
+    int run_c = -1;
+    T run = (T)0;
+    auto flush = [&]() {
+        if (run_c >= 0) nf[nfi(run_c, lane)] += run;
+    };
     auto add_entries = [&](int kkl, T vl, int sl) {
         const int c = kkl / kLeafPts - c0;
         uint64_t mask = __ballot(kkl >= 0 && c >= 0 && c < ncols && (c & 3) == wave);
@@ -666,7 +695,7 @@ k_l2p_p2p_sparse(int n, int ls, int depth, int r, int rpad, int p, int far, Kern
             const int src = __builtin_ctzll(mask);
             mask &= mask - 1;
             const int ks = __builtin_amdgcn_readlane(kkl, src);
-            const T vs = __shfl(vl, src);
+            const T vs = lane_value(vl, src);
             int lj[3];
             leaf_local(ks % kLeafPts, dim, lj);
             int dsq = 0;
@@ -675,7 +704,13 @@ k_l2p_p2p_sparse(int n, int ls, int depth, int r, int rpad, int p, int far, Kern
                 const int d = o[ax] * ls + lj[ax] - li[ax];
                 dsq += d * d;
             }
-            nf[(ks / kLeafPts - c0) * NFP + lane] += kernel_from_r2<T>((T)dsq * h2, kp) * vs;
+            const int cs = ks / kLeafPts - c0;
+            if (cs != run_c) {                         // uniform
+                flush();
+                run_c = cs;
+                run = (T)0;
+            }
+            run += kernel_from_r2<T>((T)dsq * h2, kp) * vs;
         }
     };
 #pragma unroll
@@ -688,16 +723,17 @@ k_l2p_p2p_sparse(int n, int ls, int depth, int r, int rpad, int p, int far, Kern
             add_entries(e < hi ? key[e] : -1, e < hi ? bv[e] : (T)0, sl);
         }
     }
+    flush();
     v4 acc[NTI];
 #pragma unroll
     for (int t = 0; t < NTI; ++t) acc[t] = v4{0, 0, 0, 0};
     const int lr = lane & 15, q = lane >> 4;
     __syncthreads();                                   // near-field tile complete
     if (far) {
-        const T *arow = sK + (16 * wave + lr) * KP + q;
+        const T *arow = sK + q * KT + 16 * wave + lr;
         const T *bcol = sW + q * WP + lr;
         for (int k0 = 0; k0 < rpad; k0 += 4) {
-            const T av = arow[k0];
+            const T av = arow[k0 * KT];
 #pragma unroll
             for (int t = 0; t < NTI; ++t) acc[t] = Mma<T>::op(av, bcol[k0 * WP + 16 * t], acc[t]);
         }
@@ -710,7 +746,7 @@ k_l2p_p2p_sparse(int n, int ls, int depth, int r, int rpad, int p, int far, Kern
         for (int rr = 0; rr < 4; ++rr) {
             const int i = 16 * wave + Mma<T>::row(q, rr);
             const int64_t g = leaf_point_real(b, i, dim, n, ls);
-            if (g >= 0) CQ[g * p + c0 + c] = acc[t][rr] + nf[c * NFP + i];
+            if (g >= 0) CQ[g * p + c0 + c] = acc[t][rr] + nf[nfi(c, i)];
         }
     }
 }
@@ -1961,7 +1997,7 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
     if (sparse) {
         constexpr int PPT = sizeof(T) == 4 ? 64 : 32;
         const int rpad = (r + 3) / 4 * 4;
-        const size_t lds = (size_t(PPT) * (kLeafPts + 1) + size_t(kLeafPts) * (rpad + 4) +
+        const size_t lds = (size_t(PPT) * kLeafPts + size_t(rpad) * (kLeafPts + 16) +
                             size_t(rpad) * (PPT + Mma<T>::pad)) * sizeof(T);
         e = dim == 2 ? allow_lds(k_l2p_p2p_sparse<T, PPT, 9>, lds) : allow_lds(k_l2p_p2p_sparse<T, PPT, 27>, lds);
         if (e != hipSuccess) return e;
