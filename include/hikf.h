@@ -44,7 +44,7 @@ extern "C" {
 typedef enum hikf_status {
     HIKF_OK = 0,
     HIKF_E_INVALID = 1,     /* bad shape/parameter, NaN/Inf input, bad H  */
-    HIKF_E_UNSUPPORTED = 2, /* valid but outside what this build handles   */
+    HIKF_E_UNSUPPORTED = 2, /* valid but outside what the library supports */
     HIKF_E_NOMEM = 3,       /* workspace smaller than hikf_plan asked for   */
     HIKF_E_NOT_SPD = 4,     /* Cholesky of H C + R failed; step not applied */
     HIKF_E_DEVICE = 5       /* a HIP runtime call failed                    */
