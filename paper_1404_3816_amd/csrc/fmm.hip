@@ -1947,7 +1947,8 @@ hipError_t run_fmm(const Geometry &g, const Layout &lay, char *res, char *scr, h
             // column tile: with r <= 32 the output is 2 node tiles high, so a
             // tile twice as wide (256 FP32 / 128 FP64 columns) still fits 8
             // MFMA tiles per wave and doubles the products per staged source
-            // (1024^2, p = 256, r = 25: 3.85 -> 3.52 ms); used when p fills it
+            // (FP32 at 1024^2, p = 256, r = 25, before the 32 x 32 kernel above took
+            // that case: 3.85 -> 3.52 ms); used when p fills it
             constexpr int MPT = sizeof(T) == 4 ? 128 : 64, MPTW = 2 * MPT;
             const int RT = (r + 15) / 16, KR = (r + 3) / 4 * 4;
             const bool wide = r <= 32 && p > MPT;
