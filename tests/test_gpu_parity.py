@@ -48,6 +48,7 @@ def test_cq_direct_is_exact(precision, tol):
     (2, 64, 32, 4, 0.1, 1.0),      # depth 3
     (2, 128, 48, 5, 0.05, 2.0),    # depth 4, Gaussian, padded p-space (48 -> 64)
     (2, 64, 208, 5, 0.1, 2.0),     # p > 128 with r <= 32: the wide M2L column tile, ragged
+    (2, 64, 144, 7, 0.1, 1.0),     # r = 49 > 32: two 32-row M2L tiles, the second ragged; p tile ragged
     (3, 16, 16, 3, 0.2, 1.0),      # octree depth 2
     (3, 32, 32, 4, 0.2, 1.0),      # octree depth 3
 ])
