@@ -582,7 +582,7 @@ def main():
         f"{info.scratch_bytes / 2**30:.2f} GiB, depth {info.depth}, near pairs "
         f"{info.near_pairs}, far pairs {info.far_pairs}")
 
-    def job(op, latencies=None, probe=None):
+    def job(op, latencies=None, probe=None, steps=K):
         handle = ctypes.c_void_p()
         H.check(H.hikf_init(ctypes.byref(pr), ctypes.byref(op),
                             ctypes.c_void_p(resident.data_ptr()), info.resident_bytes,
@@ -592,7 +592,7 @@ def main():
             H.check(H.hikf_export_cq(handle, ctypes.c_void_p(probe["cq"].data_ptr()), sh),
                     "hikf_export_cq", handle)
             probe["cq_rows"] = probe["cq"][probe["rows"]].clone()
-        for k in range(K):
+        for k in range(steps):
             if latencies is not None:
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
@@ -635,6 +635,17 @@ def main():
     log(f"[bench] timed {a.steps} jobs in {t1 - t0:.3f} s ({'graph' if graph else 'eager'} steps, "
         f"row-pass variant {last.rowpass_variant})")
     lat_ms = np.array([e0.elapsed_time(e1) for e0, e1 in lat])
+
+    # cold start: init (FMM, operators, graph capture) plus the first step of
+    # a new filter, host clock, best of three jobs after the timed region
+    cold = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        tc0 = time.perf_counter()
+        hc = job(op_run, steps=1)
+        torch.cuda.synchronize()
+        cold.append((time.perf_counter() - tc0) * 1e3)
+        finish(hc)
 
     # phase pass: eager launches with HIP events on the launch stream
     pstats = [finish(job(op_phase)) for _ in range(a.phase_jobs)]
@@ -731,6 +742,8 @@ def main():
                                                     else ", 64-row tiles x 2 column halves"),
                    "parallelism": "none (1 GPU)"},
         "warm_steps_per_s": round(1e3 / float(np.mean(lat_ms)), 2),
+        "cold_ms": {"init_plus_first_step": round(min(cold), 3),
+                    "timed_in": "host clock around hikf_init and one hikf_step (best of 3 jobs)"},
         "step_latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
                             "p99": round(float(np.percentile(lat_ms, 99)), 4),
                             "mean": round(float(np.mean(lat_ms)), 4),
