@@ -145,8 +145,9 @@ __device__ __forceinline__ void rowpass_part(double *sB, double *red, double *sN
         // the S^{-1} slabs are the same for every tile: the empty asm keeps
         // their loads inside this tile's k loop instead of hoisted out of
         // the tile loop
-        const double *Sv = Sinv;
-        if (PERSIST) asm volatile("" : "+s"(Sv));
+        int soff = 0;
+        if (PERSIST) asm volatile("" : "+s"(soff));
+        const double *Sv = Sinv + soff;
 
 #pragma unroll
         for (int kb = 0; kb < NT; ++kb) {
@@ -437,8 +438,9 @@ __device__ __forceinline__ void rowpass_dual_part(double *sB, double *red, int64
         for (int gg = 0; gg < 2; ++gg)
 #pragma unroll
             for (int t = 0; t < NH; ++t) acc[gg][t] = d4{0.0, 0.0, 0.0, 0.0};
-        const double *Sv = Sinv;
-        if (PERSIST) asm volatile("" : "+s"(Sv));
+        int soff = 0;
+        if (PERSIST) asm volatile("" : "+s"(soff));
+        const double *Sv = Sinv + soff;
 
 #pragma unroll
         for (int kb = 0; kb < NT; ++kb) {
