@@ -144,7 +144,9 @@ __device__ __forceinline__ void rowpass_part(double *sB, double *red, double *sN
         }
         // the S^{-1} slabs are the same for every tile: the empty asm keeps
         // their loads inside this tile's k loop instead of hoisted out of
-        // the tile loop
+        // the tile loop.  It hides an offset, not the pointer: a pointer
+        // passed through asm loses its global address space, the loads
+        // become flat loads, and every wait for them becomes a full wait.
         int soff = 0;
         if (PERSIST) asm volatile("" : "+s"(soff));
         const double *Sv = Sinv + soff;
@@ -438,7 +440,7 @@ __device__ __forceinline__ void rowpass_dual_part(double *sB, double *red, int64
         for (int gg = 0; gg < 2; ++gg)
 #pragma unroll
             for (int t = 0; t < NH; ++t) acc[gg][t] = d4{0.0, 0.0, 0.0, 0.0};
-        int soff = 0;
+        int soff = 0;                                  // as in rowpass_part
         if (PERSIST) asm volatile("" : "+s"(soff));
         const double *Sv = Sinv + soff;
 
