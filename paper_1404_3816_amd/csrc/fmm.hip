@@ -303,20 +303,27 @@ k_p2m_sparse(int r, int p, const int *off, const int *key, const T *bv, const T 
     if (staged)
         for (int i = threadIdx.x; i < cnt; i += blockDim.x) { sk[i] = key[o0 + i]; sv[i] = bv[o0 + i]; }
     __syncthreads();
-    const int *ek = staged ? sk : key + o0;
-    const T *ev = staged ? sv : bv + o0;
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-        const int a = ek[i] / kLeafPts;
-        if (i == 0 || ek[i - 1] / kLeafPts != a) rs[a] = i;
-        if (i == cnt - 1 || ek[i + 1] / kLeafPts != a) re[a] = i + 1;
-    }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < r * p; idx += blockDim.x) {
-        const int k = idx / p, a = idx % p;
-        T acc = (T)0;
-        for (int i = rs[a]; i < re[a]; ++i) acc += sS[k * kLeafPts + ek[i] % kLeafPts] * ev[i];
-        Mleaf[(B * r + k) * p + a] = acc;
-    }
+    // the entries from LDS (staged) or from memory; two instances, so that
+    // each keeps its pointers' address space (a pointer chosen between LDS
+    // and global memory at run time would make every access a flat access)
+    auto sum_runs = [&](const int *ek, const T *ev) __attribute__((always_inline)) {
+        for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+            const int a = ek[i] / kLeafPts;
+            if (i == 0 || ek[i - 1] / kLeafPts != a) rs[a] = i;
+            if (i == cnt - 1 || ek[i + 1] / kLeafPts != a) re[a] = i + 1;
+        }
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < r * p; idx += blockDim.x) {
+            const int k = idx / p, a = idx % p;
+            T acc = (T)0;
+            for (int i = rs[a]; i < re[a]; ++i) acc += sS[k * kLeafPts + ek[i] % kLeafPts] * ev[i];
+            Mleaf[(B * r + k) * p + a] = acc;
+        }
+    };
+    if (staged)
+        sum_runs(sk, sv);
+    else
+        sum_runs(key + o0, bv + o0);
 }
 
 // ---------------------------------------------------------------- P2M

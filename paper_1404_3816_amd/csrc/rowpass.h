@@ -509,8 +509,9 @@ __device__ __forceinline__ void rowpass_dual_part(double *sB, double *red, int64
         // tile's now
         if (NT == 1 && more) load_block(0, next, 0);
 
-        const double *nu_t = nu, *rdiag_t = rdiag;
-        if (PERSIST) asm volatile("" : "+s"(nu_t), "+s"(rdiag_t));
+        int eoff = 0;                                  // an offset, as for the slabs
+        if (PERSIST) asm volatile("" : "+s"(eoff));
+        const double *nu_t = nu + eoff, *rdiag_t = rdiag + eoff;
         const bool odd = lr & 1;
         auto swap_pair = [](double x) {
             int2 v = __builtin_bit_cast(int2, x);
